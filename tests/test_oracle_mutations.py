@@ -1,0 +1,124 @@
+"""Plant plausible mistakes in copies of the oracle and check that the pins
+catch every one of them.
+
+Each mutation replaces one snippet of the oracle source (it must occur
+exactly once), the mutated source is executed as a fresh module, and the pins
+are run against it; at least one must fail.
+"""
+import os
+import sys
+import types
+
+import pytest
+
+import pins
+import test_oracle_pins as checks
+
+ORACLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                      "oracle", "worm_lbm.py")
+
+MUTATIONS = {
+    "dded_moves_on_pause": (
+        "                self._deposit(acc, dded, 0, 0)",
+        "                self._deposit(acc, dded, sx, sy)"),
+    "eed_stays_on_pause": (
+        "            self._deposit(acc, eed, sx, sy)",
+        "            self._deposit(acc, eed, *((sx, sy) if hp[i] else (0, 0)))"),
+    "tas_radius_without_extra_cell": (
+        "h = cx * cx + cy * cy <= (n + 1) * (n + 1)",
+        "h = cx * cx + cy * cy <= n * n"),
+    "tas_tests_position_before_move": (
+        "            cx = P[i][0] + D2Q8[m][0]\n            cy = P[i][1] + D2Q8[m][1]",
+        "            cx = P[i][0]\n            cy = P[i][1]"),
+    "worm_index_advances_on_pause": (
+        "                P[i] = [cx, cy]\n                k[i] += 1",
+        "                P[i] = [cx, cy]\n            k[i] += 1"),
+    "equilibrium_ignores_weights": (
+        "eed = Wc * self.w[i] * E",
+        "eed = Wc * E / c.q"),
+    "no_scattering_between_directions": (
+        "eed = Wc * self.w[i] * E",
+        "eed = Wc * self.e[i]"),
+    "dded_not_relaxed": (
+        "dded = (1.0 - Wc) * self.e[i]",
+        "dded = self.e[i]"),
+    "diffuse_wall_not_normalised": (
+        "Tg = r / C",
+        "Tg = r"),
+    "diffuse_emission_wrong_row": (
+        "e[i, yrow, :] += acc[1:nx + 1]",
+        "e[i, yrow + dy_in, :] += acc[1:nx + 1]"),
+    "periodic_x_wraps_to_wrong_side": (
+        "            a[:, nx] += a[:, 0]",
+        "            a[:, 1] += a[:, 0]"),
+    "one_sided_weight_gap": (
+        "w[j] = (up + dn) / (4.0 * math.pi)",
+        "w[j] = up / (2.0 * math.pi)"),
+    "ring_speed_not_per_hop": (
+        "return math.hypot(vx, vy) / self.ring_m",
+        "return math.hypot(vx, vy)"),
+    "w_corr_without_ballistic_part": (
+        "Wc = f * ((1.0 - W) * W + W * (W * self.lam))",
+        "Wc = f * (W * (W * self.lam))"),
+    "heat_flux_components_swapped": (
+        "qx = np.tensordot(self.s[:, 0], self.e, axes=(0, 0))",
+        "qx = np.tensordot(self.s[:, 1], self.e, axes=(0, 0))"),
+    "greedy_strict_less": (
+        "if dist <= delta:",
+        "if dist < delta:"),
+    "blackbody_corner_order": (
+        "        if c.y_edge == BLACKBODY:\n            e[:, 0, :] = w * c.t_y_lo\n"
+        "            e[:, c.ny - 1, :] = w * c.t_y_hi\n        if c.x_edge == BLACKBODY:\n"
+        "            e[:, :, 0] = w * c.t_x_lo\n            e[:, :, c.nx - 1] = w * c.t_x_hi",
+        "        if c.x_edge == BLACKBODY:\n            e[:, :, 0] = w * c.t_x_lo\n"
+        "            e[:, :, c.nx - 1] = w * c.t_x_hi\n        if c.y_edge == BLACKBODY:\n"
+        "            e[:, 0, :] = w * c.t_y_lo\n            e[:, c.ny - 1, :] = w * c.t_y_hi"),
+}
+
+
+def _load_mutant(name, old, new):
+    with open(ORACLE) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"snippet of {name} must occur exactly once"
+    src = src.replace(old, new)
+    modname = f"oracle_mutant_{name}"
+    mod = types.ModuleType(modname)
+    mod.__file__ = ORACLE
+    sys.modules[modname] = mod
+    try:
+        exec(compile(src, ORACLE, "exec"), mod.__dict__)
+    except Exception:
+        del sys.modules[modname]
+        raise
+    return mod
+
+
+def _consistency_checks(o):
+    """Checks beyond the pins: the nearest-lattice-point form of the greedy
+    (ties to the diagonal, from the '<=' of Eq. worm-paths) and the pull-form
+    step matrix of every boundary combination."""
+    saved = checks.o
+    checks.o = o
+    try:
+        checks.test_worm_greedy_is_nearest_lattice_point()
+        for xe, ye in [("blackbody", "blackbody"), ("periodic", "diffuse")]:
+            checks.test_push_step_equals_pull_matrix(xe, ye, 16, "uniform")
+    finally:
+        checks.o = saved
+
+
+@pytest.mark.parametrize("name", sorted(MUTATIONS))
+def test_mutation_is_caught(name):
+    old, new = MUTATIONS[name]
+    mod = _load_mutant(name, old, new)
+    try:
+        caught = []
+        for pin in pins.ALL_PINS + [_consistency_checks]:
+            try:
+                pin(mod)
+            except Exception as exc:   # AssertionError or a crash of the mutant
+                caught.append((pin.__name__, type(exc).__name__))
+                break
+        assert caught, f"mutation {name} passed every pin"
+    finally:
+        sys.modules.pop(f"oracle_mutant_{name}", None)
