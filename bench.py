@@ -1,0 +1,226 @@
+#!/usr/bin/env python3
+"""Throughput of the worm-LBM collide-and-stream on one MI355X.
+
+One bench step = one full time step of the method (every cell, every
+direction: relaxation, worm/TAS streaming, boundary treatment) on the
+workload below, run through the C-ABI library.  Prints one JSON line.
+
+Workload (default): 1024 x 1024 periodic lattice, Q = 64 directions evenly
+spaced in angle, TAS and grid-MFP correction, MFP 102.4 cells (Kn = 0.1 with
+L = 1024), Gaussian pulse sigma0 = 16 at a seeded position.  Inputs are
+synthetic (the paper's workloads are analytic initial conditions).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
+KERNEL_SRC = os.path.join(ROOT, "paper_1911_00180_amd", "csrc", "kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_1024x1024_q64_traffic.md")
+
+
+def bytes_per_update(q: int, per_cell_w: bool = False) -> float:
+    """Algorithmic HBM bytes per cell-direction update: the population is read
+    once and written once (8 B); per cell, E is read and written (8/Q B);
+    a per-cell weight field adds 4/Q B."""
+    return 8.0 + 8.0 / q + (4.0 / q if per_cell_w else 0.0)
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None if it is missing or was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if ":" in line and line.strip().startswith("- "):
+                k, v = line.strip()[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_sha256_16") != kernel_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def run_gpu(nx, ny, q, mfp, steps, warmup, edges, tile_x=0, rows=0, seed=1911):
+    import numpy as np
+    import torch
+
+    from paper_1911_00180_amd import inputs
+    from paper_1911_00180_amd.lattice import Lattice
+
+    x0, y0 = inputs.seeded_center(seed, nx, ny)
+    T0 = inputs.gaussian_pulse(nx, ny, 16.0, x0, y0).astype(np.float32)
+    lat = Lattice(nx, ny, q, mfp=mfp, device="cuda:0", tile_x=tile_x, rows_per_thread=rows,
+                  **edges)
+    lat.set_temperature(torch.from_numpy(T0))
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    lat.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    energy, _, _ = lat.totals()
+    lat.close()
+    del lat
+    torch.cuda.empty_cache()
+    return ms, wall, energy
+
+
+def cpu_baseline(budget_s: float = 15.0):
+    """The FP64 oracle on a bounded sample of the same workload: a 256 x 256
+    periodic crop with the same Q and MFP, timed on the host."""
+    import numpy as np
+
+    from oracle import worm_lbm as o
+    from paper_1911_00180_amd import inputs
+
+    nx = ny = 256
+    q = 64
+    x0, y0 = inputs.seeded_center(1911, 1024, 1024)
+    T0 = inputs.gaussian_pulse(nx, ny, 16.0, x0 % nx, y0 % ny)
+    lat = o.Lattice(o.Config(nx=nx, ny=ny, q=q, mfp=102.4))
+    lat.set_temperature(T0)
+    lat.schedule(4000)
+    n = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s:
+        lat.step()
+        n += 1
+    dt = time.perf_counter() - t0
+    return {
+        "value": nx * ny * q * n / dt / 1e9,
+        "unit": "Gupdates/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"256x256 periodic crop, Q=64, MFP 102.4, {n} steps of the FP64 numpy "
+                  f"oracle in {dt:.1f} s (numpy elementwise ops, one thread; host has "
+                  f"{os.cpu_count()} logical CPUs)",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--kn", type=float, default=0.1, help="Knudsen number vs L = 1024")
+    ap.add_argument("--tile-x", type=int, default=0)
+    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--large", action="store_true",
+                    help="also time the 4096 x 4096, Q = 256 wall-bounded lattice")
+    ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="only run a device copy of this size (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU slab decomposition is a design, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    if args.copy_probe_mib:
+        n = args.copy_probe_mib * (1 << 20) // 4
+        a = torch.ones(n, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
+                          "launches": 5}))
+        return
+
+    nx = ny = 1024
+    q = 64
+    mfp = args.kn * nx
+    ms, wall, energy = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.tile_x,
+                               args.rows)
+    updates = nx * ny * q * args.steps
+    gups = updates / (ms * 1e-3) / 1e9
+    ms_step = ms / args.steps
+    bpu = bytes_per_update(q)
+    alg_bytes_launch = bpu * nx * ny * q
+    achieved = alg_bytes_launch / (ms_step * 1e-3) / 1e9
+    traffic = recorded_traffic()
+    out = {
+        "metric": "G cell-direction updates/s",
+        "value": round(gups, 3),
+        "unit": "Gupdates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {
+            "workload": "worm-LBM collide-and-stream, 1024x1024 periodic, Q=64 evenly spaced "
+                        "directions, TAS + grid-MFP correction, gray model",
+            "nx": nx, "ny": ny, "q": q, "kn": args.kn, "mfp_cells": mfp,
+            "initial": "Gaussian pulse sigma0=16 at default_rng(1911) position",
+            "bytes_per_update": bpu,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+        },
+        "wall_s": round(wall, 4),
+        "energy_after": energy,
+    }
+    if args.large:
+        nl, ql = 4096, 256
+        edges = dict(x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0, t_x_hi=0.0)
+        msl, walll, _ = run_gpu(nl, nl, ql, 10.0 * nl, args.large_steps, 10, edges)
+        st = msl / args.large_steps
+        bl = bytes_per_update(ql) * nl * nl * ql
+        out["large"] = {
+            "workload": "4096x4096, Q=256, blackbody x walls (T=1/0), diffuse y walls, Kn=10",
+            "steps": args.large_steps,
+            "value": round(nl * nl * ql / (st * 1e-3) / 1e9, 3),
+            "unit": "Gupdates/s",
+            "ms_per_step": round(st, 4),
+            "roofline_frac": round(bl / (st * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

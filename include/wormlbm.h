@@ -1,0 +1,197 @@
+/*
+ * wormlbm.h -- C-ABI of the MI355X worm-LBM library (libwormlbm.so).
+ *
+ * The library advances the worm lattice Boltzmann method for the gray phonon
+ * Boltzmann transport equation on one AMD Instinct MI355X (gfx950):
+ * Hammer, Fritz, Bedoya-Martinez, "The worm-LBM, an algorithm for a high
+ * number of propagation directions on a lattice Boltzmann grid: the case of
+ * phonon transport", arXiv:1911.00180.  Section and equation names below are
+ * those of that paper.
+ *
+ * Units are lattice units: one cell per axial hop, one time step per hop,
+ * group velocity 1.  The mean free path (MFP) is given in cells, so the
+ * relaxation weight of Eq. W-Kn is W = 1 / MFP.  Temperatures are in the
+ * linearised gray model e_eq = T (unit heat capacity), so T = sum_i e_i.
+ *
+ * Memory.  The caller owns every device buffer: the workspace (size from
+ * wlbm_workspace_bytes) and all input/output arrays.  Pointers named d_* are
+ * device pointers, the others host pointers.  The library never allocates or
+ * frees device memory; it allocates a small amount of pinned host memory per
+ * lattice for schedule uploads, freed by wlbm_destroy.  The workspace must
+ * stay valid until wlbm_destroy.  Device arrays are row-major float32:
+ * fields are [ny][nx] (x fastest), populations are [q][ny][nx].
+ *
+ * Streams.  All device work of a lattice is enqueued on the HIP stream given
+ * at creation (or by wlbm_set_stream), as a hipStream_t passed as void*;
+ * NULL means the default stream.  Reads complete in stream order; only
+ * wlbm_read_totals, wlbm_set_mfp_field and wlbm_step (once per schedule chunk,
+ * to recycle its pinned staging buffer) wait on the host.
+ *
+ * Errors.  Every call returns a wlbm_status.  Invalid arguments are reported
+ * synchronously; a HIP runtime error is reported as WLBM_EHIP by the call that
+ * sees it.  wlbm_last_error() returns a thread-local message for the last
+ * failing call of the calling thread.  A lattice handle must not be used from
+ * two threads at once.
+ */
+#ifndef WORMLBM_H
+#define WORMLBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct wlbm_lattice wlbm_lattice;
+
+typedef enum wlbm_status {
+  WLBM_OK = 0,
+  WLBM_EINVAL = -1,      /* bad argument or parameter                           */
+  WLBM_EUNSTABLE = -2,   /* corrected relaxation weight above 1 (App. A)        */
+  WLBM_ENOMEM = -3,      /* workspace too small, or pinned host memory failed   */
+  WLBM_EHIP = -4,        /* HIP runtime error                                   */
+  WLBM_ENONFINITE = -5,  /* non-finite values found by a readout                */
+  WLBM_ESTATE = -6       /* call not valid in the current state                 */
+} wlbm_status;
+
+/* Edge types (Sec. 2.6).  x edges: periodic or blackbody.  y edges: periodic,
+ * blackbody or adiabatic diffuse.  Both edges of an axis have the same type. */
+enum {
+  WLBM_EDGE_PERIODIC = 0,
+  WLBM_EDGE_BLACKBODY = 1,
+  WLBM_EDGE_DIFFUSE = 2
+};
+
+/* Direction sets (Sec. 2.4).  UNIFORM: Q directions evenly spaced in angle,
+ * theta_i = 2 pi i / Q, weights 1/Q.  RING: the D2Q[M x 8] lattice vectors of
+ * the square ring max(|Vx|,|Vy|) = M, M = Q/8, counter-clockwise from (M, 0),
+ * weights from the angular gaps (Eq. weight).  Direction i of either set has
+ * the index i in every [q] array of this interface. */
+enum {
+  WLBM_DIRS_UNIFORM = 0,
+  WLBM_DIRS_RING = 1
+};
+
+typedef struct wlbm_params {
+  int32_t nx, ny;            /* lattice size, 1 .. 2^20 each, nx*ny*q < 2^40     */
+  int32_t q;                 /* number of directions, multiple of 8, 8 .. 1024   */
+  int32_t dirs;              /* WLBM_DIRS_*                                      */
+  double mfp_cells;          /* uniform MFP in cells (> 0; +inf gives W = 0)     */
+  int32_t emulate_3d;        /* 1: factor 3/2 of Eq. W-correction                */
+  int32_t mfp_correction;    /* 1: Eq. W-correction applied; 0: plain W          */
+  int32_t x_edge, y_edge;    /* WLBM_EDGE_*                                      */
+  double t_x_lo, t_x_hi;     /* blackbody temperatures at x = 0 and x = nx-1     */
+  double t_y_lo, t_y_hi;     /* blackbody temperatures at y = 0 and y = ny-1     */
+  int32_t tile_x;            /* kernel tile width: 0 (auto), 64, 128 or 256      */
+  int32_t rows_per_thread;   /* kernel rows per thread: 0 (auto), 1, 2, 4 or 8   */
+  int32_t sched_chunk;       /* steps per schedule upload: 0 (auto) or 16..65536 */
+  int32_t reserved[5];       /* must be zero                                     */
+} wlbm_params;
+
+/* Fill *p with defaults: 64 x 64, q = 16, uniform directions, MFP 16, f = 1,
+ * correction on, all edges periodic, wall temperatures 0, automatic tiling. */
+void wlbm_default_params(wlbm_params* p);
+
+/* Bytes of device workspace needed for the lattice described by *p.  Host
+ * only; valid without a GPU.  Returns WLBM_EINVAL for invalid parameters and
+ * WLBM_EUNSTABLE if the uniform corrected weight exceeds 1. */
+wlbm_status wlbm_workspace_bytes(const wlbm_params* p, size_t* bytes);
+
+/* Create a lattice in the caller's workspace d_workspace (at least
+ * wlbm_workspace_bytes bytes, 256-byte aligned).  Builds the direction tables
+ * and relaxation constants (Sec. 2.2-2.5), clears the workspace on `stream`,
+ * and leaves all populations zero.  No step is taken.  *out receives the
+ * handle, owned by the caller until wlbm_destroy. */
+wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes,
+                        void* stream, wlbm_lattice** out);
+
+/* Change the stream used by later calls. */
+wlbm_status wlbm_set_stream(wlbm_lattice* lat, void* stream);
+
+/* Initial condition e_i = w_i T0 (Sec. 2.4: the weights set initial and
+ * boundary conditions), then the blackbody walls are imposed.  d_T0 is a
+ * device [ny][nx] float array, read in stream order. */
+wlbm_status wlbm_set_temperature(wlbm_lattice* lat, const float* d_T0);
+
+/* Set all populations from a device [q][ny][nx] array, then impose the
+ * blackbody walls. */
+wlbm_status wlbm_set_populations(wlbm_lattice* lat, const float* d_e);
+
+/* Per-cell mean free path in cells (device [ny][nx]); each cell then relaxes
+ * with its own corrected weight.  NULL returns to the uniform MFP of the
+ * parameters.  Waits for the stream; returns WLBM_EUNSTABLE (and keeps the
+ * previous field) if any corrected weight exceeds 1 or is not finite, or if
+ * an MFP is not positive. */
+wlbm_status wlbm_set_mfp_field(wlbm_lattice* lat, const float* d_mfp);
+
+/* Change the blackbody wall temperatures (Sec. 2.6 allows time-dependent
+ * boundary values).  Takes effect from the next step. */
+wlbm_status wlbm_set_wall_temperatures(wlbm_lattice* lat, double t_x_lo, double t_x_hi,
+                                       double t_y_lo, double t_y_hi);
+
+/* Number of trailing steps of each wlbm_step call over which the heat flux is
+ * accumulated for wlbm_read_heat_flux(..., averaged = 1); 0 disables it
+ * (default).  Sec. 3.4 averages the flux over ten steps. */
+wlbm_status wlbm_set_flux_window(wlbm_lattice* lat, int32_t window);
+
+/* Advance nsteps >= 0 time steps of the worm-LBM: for every cell and
+ * direction, BGK relaxation towards w_i sum_j e_j with the corrected weight
+ * and streaming along the worm path with TAS pauses (Eq. algorithm,
+ * Eq. worm-paths), followed by the wall conditions.  The step count after
+ * the call must stay below 2^31. */
+wlbm_status wlbm_step(wlbm_lattice* lat, int64_t nsteps);
+
+/* Pseudo-temperature T = sum_i e_i (Eq. pseudo-T, linear gray model) into a
+ * device [ny][nx] array. */
+wlbm_status wlbm_read_temperature(wlbm_lattice* lat, float* d_T);
+
+/* Heat flux q = sum_i e_i s_i (Eq. q_corr, v_g = 1) into device [ny][nx]
+ * arrays.  averaged = 0: the current state.  averaged = 1: the mean over the
+ * trailing flux window of the last wlbm_step call (WLBM_ESTATE if that call
+ * ran fewer steps than the window, or no window is set). */
+wlbm_status wlbm_read_heat_flux(wlbm_lattice* lat, float* d_qx, float* d_qy, int32_t averaged);
+
+/* Copy all populations into a device [q][ny][nx] array. */
+wlbm_status wlbm_read_populations(wlbm_lattice* lat, float* d_e);
+
+/* Totals over the lattice, accumulated in float64 in a fixed order (so the
+ * result is reproducible): energy = sum_x T(x), qx_sum and qy_sum = sum_x q(x).
+ * Waits for the stream.  WLBM_ENONFINITE if any of them is not finite.
+ * Output pointers may be NULL. */
+wlbm_status wlbm_read_totals(wlbm_lattice* lat, double* energy, double* qx_sum, double* qy_sum);
+
+/* Host-side tables, valid without a GPU (they need only the parameters). */
+
+/* Unit vectors (sx, sy) and weights w of the q directions, host [q] arrays
+ * (any may be NULL). */
+wlbm_status wlbm_get_directions(const wlbm_params* p, double* sx, double* sy, double* w);
+
+/* Grid-MFP correction Lambda_corr = Q / sum_i c_i (Eq. W-correction-factor-
+ * gereralized), W = 1/MFP and the corrected weight (Eq. W-correction). */
+wlbm_status wlbm_get_constants(const wlbm_params* p, double* lambda_corr, double* w,
+                               double* w_corr);
+
+/* Worm/TAS schedule of steps step0+1 .. step0+n into a host [n][q] int8 array:
+ * the D2Q8 move 1..8 (E, N, W, S, NE, NW, SW, SE) pending for each direction,
+ * positive if the DDED hops on that step, negative if it pauses (Sec. 2.3
+ * Eq. algorithm, Sec. 2.5 Eq. worm-paths).  If pos is not NULL it receives
+ * the host [n][q][2] int64 worm positions after each step. */
+wlbm_status wlbm_get_schedule(const wlbm_params* p, int64_t step0, int64_t n, int8_t* moves,
+                              int64_t* pos);
+
+/* Steps taken since creation (or -1 for NULL). */
+int64_t wlbm_step_count(const wlbm_lattice* lat);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* wlbm_last_error(void);
+
+/* Release the handle and its pinned host memory after waiting for its stream.
+ * The workspace may be reused afterwards.  NULL is accepted. */
+wlbm_status wlbm_destroy(wlbm_lattice* lat);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WORMLBM_H */

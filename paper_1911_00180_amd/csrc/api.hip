@@ -1,0 +1,599 @@
+// C-ABI of libwormlbm.so (declared in include/wormlbm.h).
+//
+// A lattice handle owns the host tables (direction set, weights, corrected
+// relaxation weight), the host TAS state and two pinned staging buffers for
+// schedule uploads; all device memory is the caller's workspace, carved into
+// the regions below.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/wormlbm.h"
+#include "device.hpp"
+#include "tables.hpp"
+
+using namespace wlbm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+wlbm_status fail(wlbm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(WLBM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));            \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kReduceBlocks = 1024;
+constexpr int kDefaultChunk = 256;
+constexpr int64_t kMaxSteps = (int64_t(1) << 31) - 1;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Byte offsets of the workspace regions.
+struct Carve {
+  size_t e[2], E[2], Wf, qsx, qsy, partials, totals, flag, sched, wtab, sxtab, sytab, total;
+};
+
+int chunk_steps(const wlbm_params& p) { return p.sched_chunk ? p.sched_chunk : kDefaultChunk; }
+
+Carve carve(const wlbm_params& p) {
+  Carve c{};
+  const size_t plane = size_t(padded_plane(p.nx, p.ny)) * sizeof(float);
+  const size_t cells = size_t(p.nx) * size_t(p.ny) * sizeof(float);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  c.e[0] = take(plane * size_t(p.q));
+  c.e[1] = take(plane * size_t(p.q));
+  c.E[0] = take(plane);
+  c.E[1] = take(plane);
+  c.Wf = take(plane);
+  c.qsx = take(cells);
+  c.qsy = take(cells);
+  c.partials = take(size_t(kReduceBlocks) * 3 * sizeof(double));
+  c.totals = take(4 * sizeof(double));
+  c.flag = take(sizeof(int));
+  c.sched = take(size_t(2) * chunk_steps(p) * size_t(p.q));
+  c.wtab = take(size_t(p.q) * sizeof(float));
+  c.sxtab = take(size_t(p.q) * sizeof(float));
+  c.sytab = take(size_t(p.q) * sizeof(float));
+  c.total = off;
+  return c;
+}
+
+wlbm_status validate(const wlbm_params* p) {
+  if (!p) return fail(WLBM_EINVAL, "params is NULL");
+  if (p->nx < 1 || p->ny < 1 || p->nx > (1 << 20) || p->ny > (1 << 20))
+    return fail(WLBM_EINVAL, "nx, ny must be in 1..2^20 (got %d, %d)", p->nx, p->ny);
+  if (p->q < 8 || p->q > kMaxQ || p->q % 8 != 0)
+    return fail(WLBM_EINVAL, "q must be a multiple of 8 in 8..%d (got %d)", kMaxQ, p->q);
+  if (p->dirs != WLBM_DIRS_UNIFORM && p->dirs != WLBM_DIRS_RING)
+    return fail(WLBM_EINVAL, "unknown direction set %d", p->dirs);
+  if (p->x_edge != WLBM_EDGE_PERIODIC && p->x_edge != WLBM_EDGE_BLACKBODY)
+    return fail(WLBM_EINVAL, "x edges must be periodic or blackbody (got %d)", p->x_edge);
+  if (p->y_edge != WLBM_EDGE_PERIODIC && p->y_edge != WLBM_EDGE_BLACKBODY &&
+      p->y_edge != WLBM_EDGE_DIFFUSE)
+    return fail(WLBM_EINVAL, "y edges must be periodic, blackbody or diffuse (got %d)",
+                p->y_edge);
+  if (!(p->mfp_cells > 0.0)) return fail(WLBM_EINVAL, "mfp_cells must be > 0");
+  if (p->emulate_3d != 0 && p->emulate_3d != 1) return fail(WLBM_EINVAL, "emulate_3d is 0 or 1");
+  if (p->mfp_correction != 0 && p->mfp_correction != 1)
+    return fail(WLBM_EINVAL, "mfp_correction is 0 or 1");
+  if (p->tile_x != 0 && p->tile_x != 64 && p->tile_x != 128 && p->tile_x != 256)
+    return fail(WLBM_EINVAL, "tile_x must be 0, 64, 128 or 256");
+  if (p->rows_per_thread != 0 && p->rows_per_thread != 1 && p->rows_per_thread != 2 &&
+      p->rows_per_thread != 4 && p->rows_per_thread != 8)
+    return fail(WLBM_EINVAL, "rows_per_thread must be 0, 1, 2, 4 or 8");
+  if (p->sched_chunk != 0 && (p->sched_chunk < 16 || p->sched_chunk > 65536))
+    return fail(WLBM_EINVAL, "sched_chunk must be 0 or 16..65536");
+  for (int k = 0; k < 5; ++k)
+    if (p->reserved[k] != 0) return fail(WLBM_EINVAL, "reserved fields must be zero");
+  if (!std::isfinite(p->t_x_lo) || !std::isfinite(p->t_x_hi) || !std::isfinite(p->t_y_lo) ||
+      !std::isfinite(p->t_y_hi))
+    return fail(WLBM_EINVAL, "wall temperatures must be finite");
+  // 32-bit byte offsets inside one plane
+  if ((padded_plane(p->nx, p->ny) + 2 * (padded_pitch(p->nx) + 1)) * int64_t(sizeof(float)) >=
+      (int64_t(1) << 32))
+    return fail(WLBM_EINVAL, "lattice too large: one padded plane must stay below 4 GiB");
+  return WLBM_OK;
+}
+
+double uniform_wcorr(const wlbm_params& p, double lam, double* W_out) {
+  const double W = std::isinf(p.mfp_cells) ? 0.0 : 1.0 / p.mfp_cells;
+  if (W_out) *W_out = W;
+  return corrected_weight(W, lam, p.emulate_3d != 0, p.mfp_correction != 0);
+}
+
+}  // namespace
+
+struct wlbm_lattice {
+  wlbm_params p{};
+  DirSet dirs;
+  TasState tas;
+  Geometry g{};
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  Carve c{};
+  int cur = 0;              // population buffer holding the current state
+  float W = 0.f;            // uniform corrected weight
+  bool per_cell = false;    // per-cell weight field active
+  int tile_x = 64, rows = 4;
+  int chunk = kDefaultChunk;
+  uint8_t* pinned[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool ev_pending[2] = {false, false};
+  int64_t chunk_counter = 0;
+  int flux_window = 0;
+  bool flux_valid = false;
+  bool broken = false;
+  Walls walls{};
+
+  float* ptr(size_t off) { return reinterpret_cast<float*>(ws + off); }
+};
+
+namespace {
+
+wlbm_status check_lat(const wlbm_lattice* l) {
+  if (!l) return fail(WLBM_EINVAL, "lattice is NULL");
+  if (l->broken) return fail(WLBM_ESTATE, "lattice is unusable after an earlier HIP error");
+  return WLBM_OK;
+}
+
+void auto_tiling(wlbm_lattice* l) {
+  l->tile_x = l->p.tile_x ? l->p.tile_x : 64;
+  l->rows = l->p.rows_per_thread ? l->p.rows_per_thread : 4;
+  // a narrow lattice wastes lanes on wide tiles
+  if (!l->p.tile_x) {
+    if (l->p.nx >= 1024) l->tile_x = 64;
+    if (l->p.nx <= 64) l->tile_x = 64;
+  }
+  if (!l->p.rows_per_thread) {
+    const int ty = (kBlock / l->tile_x);
+    if (l->p.ny < ty * 4) l->rows = 1;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void wlbm_default_params(wlbm_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->nx = 64;
+  p->ny = 64;
+  p->q = 16;
+  p->dirs = WLBM_DIRS_UNIFORM;
+  p->mfp_cells = 16.0;
+  p->emulate_3d = 0;
+  p->mfp_correction = 1;
+  p->x_edge = WLBM_EDGE_PERIODIC;
+  p->y_edge = WLBM_EDGE_PERIODIC;
+}
+
+wlbm_status wlbm_workspace_bytes(const wlbm_params* p, size_t* bytes) {
+  wlbm_status st = validate(p);
+  if (st) return st;
+  if (!bytes) return fail(WLBM_EINVAL, "bytes is NULL");
+  try {
+    DirSet d = build_dirs(p->q, p->dirs);
+    if (uniform_wcorr(*p, d.lambda_corr, nullptr) > 1.0)
+      return fail(WLBM_EUNSTABLE, "corrected relaxation weight %.17g exceeds 1 (App. A)",
+                  uniform_wcorr(*p, d.lambda_corr, nullptr));
+  } catch (const std::exception& e) {
+    return fail(WLBM_EINVAL, "%s", e.what());
+  }
+  *bytes = carve(*p).total;
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_get_directions(const wlbm_params* p, double* sx, double* sy, double* w) {
+  wlbm_status st = validate(p);
+  if (st) return st;
+  try {
+    DirSet d = build_dirs(p->q, p->dirs);
+    for (int i = 0; i < p->q; ++i) {
+      if (sx) sx[i] = d.sx[i];
+      if (sy) sy[i] = d.sy[i];
+      if (w) w[i] = d.w[i];
+    }
+  } catch (const std::exception& e) {
+    return fail(WLBM_EINVAL, "%s", e.what());
+  }
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_get_constants(const wlbm_params* p, double* lambda_corr, double* w,
+                               double* w_corr) {
+  wlbm_status st = validate(p);
+  if (st) return st;
+  try {
+    DirSet d = build_dirs(p->q, p->dirs);
+    double W;
+    const double wc = uniform_wcorr(*p, d.lambda_corr, &W);
+    if (lambda_corr) *lambda_corr = d.lambda_corr;
+    if (w) *w = W;
+    if (w_corr) *w_corr = wc;
+  } catch (const std::exception& e) {
+    return fail(WLBM_EINVAL, "%s", e.what());
+  }
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_get_schedule(const wlbm_params* p, int64_t step0, int64_t n, int8_t* moves,
+                              int64_t* pos) {
+  wlbm_status st = validate(p);
+  if (st) return st;
+  if (step0 < 0 || n < 0 || step0 + n > kMaxSteps)
+    return fail(WLBM_EINVAL, "steps must satisfy 0 <= step0, 0 <= n, step0 + n < 2^31");
+  if (n > 0 && !moves) return fail(WLBM_EINVAL, "moves is NULL");
+  try {
+    DirSet d = build_dirs(p->q, p->dirs);
+    TasState s;
+    s.reset(p->q);
+    std::vector<int8_t> dx(p->q), dy(p->q);
+    std::vector<uint8_t> hop(p->q);
+    for (int64_t k = 0; k < step0 + n; ++k) {
+      tas_advance(d, s, dx.data(), dy.data(), hop.data());
+      if (k < step0) continue;
+      const int64_t row = k - step0;
+      for (int i = 0; i < p->q; ++i) {
+        const int idx = d2q8_index(dx[i], dy[i]);
+        moves[row * p->q + i] = int8_t(hop[i] ? idx : -idx);
+        if (pos) {
+          pos[(row * p->q + i) * 2] = s.px[i];
+          pos[(row * p->q + i) * 2 + 1] = s.py[i];
+        }
+      }
+    }
+  } catch (const std::exception& e) {
+    return fail(WLBM_EINVAL, "%s", e.what());
+  }
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes, void* stream,
+                        wlbm_lattice** out) {
+  if (!out) return fail(WLBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  wlbm_status st = wlbm_workspace_bytes(p, &need);
+  if (st) return st;
+  if (!d_workspace) return fail(WLBM_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
+    return fail(WLBM_EINVAL, "workspace must be 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(WLBM_ENOMEM, "workspace too small: %zu bytes given, %zu needed", ws_bytes, need);
+
+  wlbm_lattice* l = new (std::nothrow) wlbm_lattice();
+  if (!l) return fail(WLBM_ENOMEM, "host allocation failed");
+  try {
+    l->p = *p;
+    l->dirs = build_dirs(p->q, p->dirs);
+  } catch (const std::exception& e) {
+    delete l;
+    return fail(WLBM_EINVAL, "%s", e.what());
+  }
+  l->tas.reset(p->q);
+  l->stream = static_cast<hipStream_t>(stream);
+  l->ws = static_cast<char*>(d_workspace);
+  l->c = carve(*p);
+  l->chunk = chunk_steps(*p);
+  l->W = float(uniform_wcorr(*p, l->dirs.lambda_corr, nullptr));
+  l->walls = {float(p->t_x_lo), float(p->t_x_hi), float(p->t_y_lo), float(p->t_y_hi)};
+  l->g = {p->nx, p->ny, p->q, padded_pitch(p->nx), padded_plane(p->nx, p->ny), p->x_edge,
+          p->y_edge};
+  auto_tiling(l);
+
+  auto cleanup = [&](wlbm_status s) {
+    for (int k = 0; k < 2; ++k) {
+      if (l->pinned[k]) (void)hipHostFree(l->pinned[k]);
+      if (l->ev[k]) (void)hipEventDestroy(l->ev[k]);
+    }
+    delete l;
+    return s;
+  };
+  const size_t stage = std::max<size_t>(size_t(l->chunk) * p->q, 3 * size_t(p->q) * sizeof(float));
+  for (int k = 0; k < 2; ++k) {
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&l->pinned[k]), stage, hipHostMallocDefault);
+    if (e != hipSuccess) {
+      wlbm_status s = fail(WLBM_ENOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
+      return cleanup(s);
+    }
+    e = hipEventCreateWithFlags(&l->ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      wlbm_status s = fail(WLBM_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
+      return cleanup(s);
+    }
+  }
+  // Clear the workspace (ghosts of non-periodic edges must read zero) and
+  // upload the direction tables as float32.
+  hipError_t e = hipMemsetAsync(l->ws, 0, l->c.total, l->stream);
+  float* tabs = reinterpret_cast<float*>(l->pinned[0]);
+  for (int i = 0; i < p->q; ++i) {
+    tabs[i] = float(l->dirs.w[i]);
+    tabs[p->q + i] = float(l->dirs.sx[i]);
+    tabs[2 * p->q + i] = float(l->dirs.sy[i]);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(l->ws + l->c.wtab, tabs, p->q * sizeof(float), hipMemcpyHostToDevice,
+                       l->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(l->ws + l->c.sxtab, tabs + p->q, p->q * sizeof(float),
+                       hipMemcpyHostToDevice, l->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(l->ws + l->c.sytab, tabs + 2 * p->q, p->q * sizeof(float),
+                       hipMemcpyHostToDevice, l->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(l->stream);
+  if (e != hipSuccess) {
+    wlbm_status s = fail(WLBM_EHIP, "workspace set-up failed: %s", hipGetErrorString(e));
+    return cleanup(s);
+  }
+  *out = l;
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_set_stream(wlbm_lattice* l, void* stream) {
+  if (!l) return fail(WLBM_EINVAL, "lattice is NULL");
+  l->stream = static_cast<hipStream_t>(stream);
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_set_temperature(wlbm_lattice* l, const float* d_T0) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (!d_T0) return fail(WLBM_EINVAL, "T0 is NULL");
+  HIP_TRY(launch_init_temperature(l->g, d_T0, l->ptr(l->c.e[l->cur]), l->ptr(l->c.E[l->cur]),
+                                  l->ptr(l->c.wtab), l->walls, l->stream));
+  l->flux_valid = false;
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_set_populations(wlbm_lattice* l, const float* d_e) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (!d_e) return fail(WLBM_EINVAL, "populations pointer is NULL");
+  HIP_TRY(launch_init_populations(l->g, d_e, l->ptr(l->c.e[l->cur]), l->ptr(l->c.E[l->cur]),
+                                  l->ptr(l->c.wtab), l->walls, l->stream));
+  l->flux_valid = false;
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_set_mfp_field(wlbm_lattice* l, const float* d_mfp) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (!d_mfp) {
+    l->per_cell = false;
+    return WLBM_OK;
+  }
+  const double f = l->p.emulate_3d ? 1.5 : 1.0;
+  int* flag = reinterpret_cast<int*>(l->ws + l->c.flag);
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), l->stream));
+  HIP_TRY(launch_check_mfp(l->g, d_mfp, l->dirs.lambda_corr, f, l->p.mfp_correction, flag,
+                           l->stream));
+  int hflag = 0;
+  HIP_TRY(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, l->stream));
+  HIP_TRY(hipStreamSynchronize(l->stream));
+  if (hflag)
+    return fail(WLBM_EUNSTABLE,
+                "MFP field rejected: a value is not positive, or a corrected weight is above 1 "
+                "or not finite (App. A)");
+  HIP_TRY(launch_write_wfield(l->g, d_mfp, l->dirs.lambda_corr, f, l->p.mfp_correction,
+                              l->ptr(l->c.Wf), l->stream));
+  l->per_cell = true;
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_set_wall_temperatures(wlbm_lattice* l, double txl, double txh, double tyl,
+                                       double tyh) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (!std::isfinite(txl) || !std::isfinite(txh) || !std::isfinite(tyl) || !std::isfinite(tyh))
+    return fail(WLBM_EINVAL, "wall temperatures must be finite");
+  l->walls = {float(txl), float(txh), float(tyl), float(tyh)};
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_set_flux_window(wlbm_lattice* l, int32_t window) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (window < 0) return fail(WLBM_EINVAL, "flux window must be >= 0");
+  l->flux_window = window;
+  l->flux_valid = false;
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_step(wlbm_lattice* l, int64_t nsteps) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (nsteps < 0) return fail(WLBM_EINVAL, "nsteps must be >= 0");
+  if (l->tas.n + nsteps > kMaxSteps) return fail(WLBM_EINVAL, "step count would exceed 2^31 - 1");
+  if (nsteps == 0) return WLBM_OK;
+  const int q = l->p.q;
+  const int64_t flux_from = l->flux_window > 0 ? nsteps - l->flux_window : nsteps;
+  std::vector<int8_t> dx(q), dy(q);
+  std::vector<uint8_t> hop(q);
+  std::vector<float> insums;
+  StepArgs a{};
+  a.Wf = l->ptr(l->c.Wf);
+  a.qsx = l->ptr(l->c.qsx);
+  a.qsy = l->ptr(l->c.qsy);
+  a.wtab = l->ptr(l->c.wtab);
+  a.sxtab = l->ptr(l->c.sxtab);
+  a.sytab = l->ptr(l->c.sytab);
+  a.W = l->W;
+  a.t_x_lo = l->walls.x_lo;
+  a.t_x_hi = l->walls.x_hi;
+  a.t_y_lo = l->walls.y_lo;
+  a.t_y_hi = l->walls.y_hi;
+  a.nx = l->g.nx;
+  a.ny = l->g.ny;
+  a.q = q;
+  a.pitch = l->g.pitch;
+  a.plane = l->g.plane;
+  a.x_edge = l->g.x_edge;
+  a.y_edge = l->g.y_edge;
+  a.tiles_x = tiles_x_for(l->g.nx, l->tile_x);
+  a.ntiles = a.tiles_x * tiles_y_for(l->g.ny, l->tile_x, l->rows);
+
+  int64_t done = 0;
+  while (done < nsteps) {
+    const int cnt = int(std::min<int64_t>(l->chunk, nsteps - done));
+    const int slot = int(l->chunk_counter & 1);
+    if (l->ev_pending[slot]) {
+      hipError_t e = hipEventSynchronize(l->ev[slot]);
+      if (e != hipSuccess) {
+        l->broken = true;
+        return fail(WLBM_EHIP, "hipEventSynchronize failed: %s", hipGetErrorString(e));
+      }
+      l->ev_pending[slot] = false;
+    }
+    // Build the schedule rows of this chunk (Sec. 2.3, Sec. 2.5) and the
+    // per-step sums of inward weights used by diffuse walls.
+    uint8_t* rows = l->pinned[slot];
+    insums.assign(size_t(cnt) * 4, 0.f);
+    for (int j = 0; j < cnt; ++j) {
+      tas_advance(l->dirs, l->tas, dx.data(), dy.data(), hop.data());
+      double lo_h = 0, lo_a = 0, hi_h = 0, hi_a = 0;
+      for (int i = 0; i < q; ++i) {
+        rows[size_t(j) * q + i] = pack_code(dx[i], dy[i], hop[i]);
+        if (dy[i] == 1) {
+          lo_a += l->dirs.w[i];
+          if (hop[i]) lo_h += l->dirs.w[i];
+        } else if (dy[i] == -1) {
+          hi_a += l->dirs.w[i];
+          if (hop[i]) hi_h += l->dirs.w[i];
+        }
+      }
+      insums[4 * j] = float(lo_h);
+      insums[4 * j + 1] = float(lo_a);
+      insums[4 * j + 2] = float(hi_h);
+      insums[4 * j + 3] = float(hi_a);
+    }
+    uint8_t* dev_rows = reinterpret_cast<uint8_t*>(l->ws + l->c.sched) + size_t(slot) * l->chunk * q;
+    hipError_t e = hipMemcpyAsync(dev_rows, rows, size_t(cnt) * q, hipMemcpyHostToDevice, l->stream);
+    if (e == hipSuccess) e = hipEventRecord(l->ev[slot], l->stream);
+    if (e != hipSuccess) {
+      l->broken = true;
+      return fail(WLBM_EHIP, "schedule upload failed: %s", hipGetErrorString(e));
+    }
+    l->ev_pending[slot] = true;
+    ++l->chunk_counter;
+    for (int j = 0; j < cnt; ++j) {
+      const int64_t k = done + j;
+      const bool flux = k >= flux_from;
+      a.codes = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j) * q);
+      a.in_lo_hop = insums[4 * j];
+      a.in_lo_all = insums[4 * j + 1];
+      a.in_hi_hop = insums[4 * j + 2];
+      a.in_hi_all = insums[4 * j + 3];
+      a.e_in = l->ptr(l->c.e[l->cur]);
+      a.e_out = l->ptr(l->c.e[1 - l->cur]);
+      a.E_in = l->ptr(l->c.E[l->cur]);
+      a.E_out = l->ptr(l->c.E[1 - l->cur]);
+      a.q_first = (flux && k == flux_from) ? 1 : 0;
+      e = launch_step(a, l->tile_x, l->rows, l->per_cell, flux, l->stream);
+      if (e != hipSuccess) {
+        l->broken = true;
+        return fail(WLBM_EHIP, "step kernel launch failed: %s", hipGetErrorString(e));
+      }
+      l->cur = 1 - l->cur;
+    }
+    done += cnt;
+  }
+  l->flux_valid = l->flux_window > 0 && nsteps >= l->flux_window;
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_read_temperature(wlbm_lattice* l, float* d_T) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (!d_T) return fail(WLBM_EINVAL, "T is NULL");
+  HIP_TRY(launch_read_field(l->g, l->ptr(l->c.E[l->cur]), d_T, l->stream));
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_read_heat_flux(wlbm_lattice* l, float* d_qx, float* d_qy, int32_t averaged) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (!d_qx || !d_qy) return fail(WLBM_EINVAL, "flux outputs must not be NULL");
+  if (averaged) {
+    if (!l->flux_valid)
+      return fail(WLBM_ESTATE, "no complete flux window: set one and step at least that far");
+    HIP_TRY(launch_scale_pair(l->g.nx * l->g.ny, l->ptr(l->c.qsx), l->ptr(l->c.qsy),
+                              1.0f / float(l->flux_window), d_qx, d_qy, l->stream));
+  } else {
+    HIP_TRY(launch_read_flux(l->g, l->ptr(l->c.e[l->cur]), l->ptr(l->c.sxtab),
+                             l->ptr(l->c.sytab), d_qx, d_qy, l->stream));
+  }
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_read_populations(wlbm_lattice* l, float* d_e) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (!d_e) return fail(WLBM_EINVAL, "populations pointer is NULL");
+  HIP_TRY(launch_read_populations(l->g, l->ptr(l->c.e[l->cur]), d_e, l->stream));
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_read_totals(wlbm_lattice* l, double* energy, double* qx_sum, double* qy_sum) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  double* dev = reinterpret_cast<double*>(l->ws + l->c.totals);
+  HIP_TRY(launch_totals(l->g, l->ptr(l->c.e[l->cur]), l->ptr(l->c.E[l->cur]),
+                        l->ptr(l->c.sxtab), l->ptr(l->c.sytab),
+                        reinterpret_cast<double*>(l->ws + l->c.partials), kReduceBlocks, dev,
+                        l->stream));
+  double h[3];
+  HIP_TRY(hipMemcpyAsync(h, dev, sizeof(h), hipMemcpyDeviceToHost, l->stream));
+  HIP_TRY(hipStreamSynchronize(l->stream));
+  if (energy) *energy = h[0];
+  if (qx_sum) *qx_sum = h[1];
+  if (qy_sum) *qy_sum = h[2];
+  if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !std::isfinite(h[2]))
+    return fail(WLBM_ENONFINITE, "non-finite totals: energy %g, qx %g, qy %g", h[0], h[1], h[2]);
+  return WLBM_OK;
+}
+
+int64_t wlbm_step_count(const wlbm_lattice* l) { return l ? l->tas.n : -1; }
+
+const char* wlbm_last_error(void) { return g_last_error.c_str(); }
+
+wlbm_status wlbm_destroy(wlbm_lattice* l) {
+  if (!l) return WLBM_OK;
+  hipError_t e = hipStreamSynchronize(l->stream);
+  for (int k = 0; k < 2; ++k) {
+    if (l->pinned[k]) (void)hipHostFree(l->pinned[k]);
+    if (l->ev[k]) (void)hipEventDestroy(l->ev[k]);
+  }
+  delete l;
+  if (e != hipSuccess) return fail(WLBM_EHIP, "stream sync at destroy: %s", hipGetErrorString(e));
+  return WLBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,99 @@
+// Device-side data layout and kernel launch interface of the worm-LBM
+// library.  Shared by kernels.hip and api.hip only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace wlbm {
+
+// Padded HBM layout of every per-cell field (populations, E, W field).
+// A field plane holds rows y = -1 .. ny and columns x = -1 .. nx, where the
+// rows/columns -1 and nx (ny) are ghosts: for a periodic edge they hold a
+// copy of the opposite edge written by the producer of that cell, otherwise
+// they stay zero.  Cell (x, y) sits at (y + 1) * pitch + kXOff + x, so that
+// x = 0 starts a 128-byte line and a wave's 64 consecutive cells are two
+// whole lines.  Populations are [q] such planes (structure of arrays).
+constexpr int kXOff = 32;
+constexpr int kBlock = 256;
+constexpr int kMaxQ = 1024;
+
+enum Edge { kPeriodic = 0, kBlackbody = 1, kDiffuse = 2 };
+
+inline int padded_pitch(int nx) { return ((nx + kXOff + 1 + 31) / 32) * 32; }
+inline int64_t padded_plane(int nx, int ny) { return int64_t(ny + 2) * padded_pitch(nx); }
+
+// Schedule code of one direction on one step: bits 0-1 dx+1, bits 2-3 dy+1,
+// bit 4 hop.  Rows of q bytes, read four directions per 32-bit word.
+inline uint8_t pack_code(int dx, int dy, int hop) {
+  return uint8_t((dx + 1) | ((dy + 1) << 2) | (hop << 4));
+}
+
+struct StepArgs {
+  const float* e_in;
+  float* e_out;
+  const float* E_in;
+  float* E_out;
+  const float* Wf;        // padded per-cell corrected weight (per-cell mode)
+  float* qsx;             // heat-flux window sums, [ny][nx] (flux mode)
+  float* qsy;
+  const uint32_t* codes;  // schedule row of this step
+  const float* wtab;      // [q] weights
+  const float* sxtab;     // [q] unit vectors
+  const float* sytab;
+  float W;                // uniform corrected weight
+  // Diffuse walls: sums of w_i over the directions whose pending move points
+  // into the domain through the lo (dy = +1) / hi (dy = -1) wall on this
+  // step, over the hopping ones and over all of them.
+  float in_lo_hop, in_lo_all, in_hi_hop, in_hi_all;
+  float t_x_lo, t_x_hi, t_y_lo, t_y_hi;
+  int nx, ny, q, pitch;
+  long long plane;
+  int x_edge, y_edge;
+  int tiles_x, ntiles;
+  int q_first;            // flux mode: 1 on the first step of the window
+};
+
+struct Geometry {
+  int nx, ny, q, pitch;
+  long long plane;
+  int x_edge, y_edge;
+};
+
+struct Walls {
+  float x_lo, x_hi, y_lo, y_hi;
+};
+
+// Collide-and-stream of one time step.  tile_x in {64, 128, 256}, rows in
+// {1, 2, 4, 8}; per_cell selects the per-cell weight field; flux accumulates
+// the heat flux into qsx/qsy.
+hipError_t launch_step(const StepArgs& a, int tile_x, int rows, bool per_cell, bool flux,
+                       hipStream_t s);
+int tiles_x_for(int nx, int tile_x);
+int tiles_y_for(int ny, int tile_x, int rows);
+
+// e_i = w_i T0 (T0 unpadded [ny][nx]), blackbody walls, E, ghosts.
+hipError_t launch_init_temperature(const Geometry& g, const float* T0, float* e, float* E,
+                                   const float* wtab, Walls walls, hipStream_t s);
+// e from an unpadded [q][ny][nx] array, blackbody walls, E, ghosts.
+hipError_t launch_init_populations(const Geometry& g, const float* src, float* e, float* E,
+                                   const float* wtab, Walls walls, hipStream_t s);
+hipError_t launch_read_populations(const Geometry& g, const float* e, float* dst, hipStream_t s);
+hipError_t launch_read_field(const Geometry& g, const float* f, float* dst, hipStream_t s);
+hipError_t launch_read_flux(const Geometry& g, const float* e, const float* sxtab,
+                            const float* sytab, float* qx, float* qy, hipStream_t s);
+hipError_t launch_scale_pair(int n, const float* ax, const float* ay, float scale, float* bx,
+                             float* by, hipStream_t s);
+// Totals in float64: out[0] = sum E, out[1] = sum q_x, out[2] = sum q_y.
+hipError_t launch_totals(const Geometry& g, const float* e, const float* E, const float* sxtab,
+                         const float* sytab, double* partials, int max_blocks, double* out,
+                         hipStream_t s);
+// Per-cell corrected weight from an MFP field: check pass (sets *flag on a
+// non-positive MFP or an unstable/non-finite weight), then write pass.
+hipError_t launch_check_mfp(const Geometry& g, const float* mfp, double lam, double f, int corr,
+                            int* flag, hipStream_t s);
+hipError_t launch_write_wfield(const Geometry& g, const float* mfp, double lam, double f,
+                               int corr, float* Wf, hipStream_t s);
+
+}  // namespace wlbm

@@ -1,0 +1,631 @@
+// HIP kernels of the worm-LBM for gfx950 (MI355X).
+//
+// The hot kernel k_step advances one time step for every cell and direction:
+// BGK relaxation of the directional energy densities e_i towards w_i E, with
+// E = sum_i e_i and the corrected relaxation weight, and streaming along each
+// direction's worm path with TAS pauses (arXiv:1911.00180, Sec. 2.2 Eq.
+// lbm-energy, Sec. 2.3 Eq. algorithm, Sec. 2.5), followed by the wall
+// conditions of Sec. 2.6.
+//
+// It is written in pull form: the thread that owns cell y gathers, for each
+// direction i with pending worm move s_i (and DDED shift h_i = s_i on a hop,
+// 0 on a pause),
+//     out_i(y) = (1 - W(y - h_i)) e_i(y - h_i) + W(y - s_i) w_i E(y - s_i)
+// and at the same time sums E'(y) = sum_i out_i(y) for the next step, so each
+// population is read once and written once per step (the path is HBM-bound;
+// there is no contraction and no MFMA).  E of the previous step is staged in
+// LDS with a one-cell halo; the schedule row is read through the scalar cache.
+#include "device.hpp"
+
+#include <cmath>
+
+namespace wlbm {
+namespace {
+
+// Workgroups are dispatched to the eight XCDs round-robin.  Remap the block
+// index so that each XCD walks one contiguous range of tiles: neighbouring
+// tiles, which share the cache lines of x-shifted rows and the E halo, then
+// run close in time on the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int per = n >> 3;
+  if (b < (per << 3)) return (b & 7) * per + (b >> 3);
+  return b;
+}
+
+__device__ __forceinline__ long long cell(int x, int y, int pitch) {
+  return (long long)(y + 1) * pitch + kXOff + x;
+}
+
+// Buffer resources: the plane base lives in scalar registers, each lane adds
+// a 32-bit byte offset.  This keeps one VGPR per cell for addressing (the
+// compiler cannot turn per-direction plane strides into 64-bit per-lane
+// pointers) and every access is range-checked by the hardware.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+constexpr int kRsrcWord3 = 0x00020000;
+
+__device__ __forceinline__ rsrc_t make_rsrc(const float* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, (int)bytes,
+                                           kRsrcWord3);
+}
+__device__ __forceinline__ float buf_load(rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+}
+__device__ __forceinline__ void buf_store(float v, rsrc_t r, uint32_t voff) {
+  __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, 0, 0);
+}
+
+// Tables that every lane reads at the same index (schedule codes, weights,
+// unit vectors) are read through the scalar cache.
+#define WLBM_CONST __attribute__((address_space(4)))
+template <class T>
+__device__ __forceinline__ const WLBM_CONST T* scalar_ptr(const T* p) {
+  return (const WLBM_CONST T*)p;
+}
+
+// Store a cell value and, for periodic edges, its ghost copies.
+__device__ __forceinline__ void store_ghosted(float* __restrict__ plane, int x, int y, float v,
+                                              int nx, int ny, int pitch, bool px, bool py) {
+  plane[cell(x, y, pitch)] = v;
+  int gx[2], gy[2], ngx = 0, ngy = 0;
+  if (px) {
+    if (x == 0) gx[ngx++] = nx;
+    if (x == nx - 1) gx[ngx++] = -1;
+  }
+  if (py) {
+    if (y == 0) gy[ngy++] = ny;
+    if (y == ny - 1) gy[ngy++] = -1;
+  }
+  for (int a = 0; a < ngx; ++a) plane[cell(gx[a], y, pitch)] = v;
+  for (int b = 0; b < ngy; ++b) plane[cell(x, gy[b], pitch)] = v;
+  for (int a = 0; a < ngx; ++a)
+    for (int b = 0; b < ngy; ++b) plane[cell(gx[a], gy[b], pitch)] = v;
+}
+
+// Blackbody walls (Sec. 2.6, Eq. isotropic): the DDEDs of a wall cell are
+// w_i T_wall.  y walls first, then x walls, so the x walls win at corners.
+__device__ __forceinline__ float blackbody(float v, float wi, int x, int y, int nx, int ny,
+                                           int x_edge, int y_edge, float txl, float txh,
+                                           float tyl, float tyh) {
+  if (y_edge == kBlackbody) {
+    if (y == ny - 1)
+      v = wi * tyh;
+    else if (y == 0)
+      v = wi * tyl;
+  }
+  if (x_edge == kBlackbody) {
+    if (x == nx - 1)
+      v = wi * txh;
+    else if (x == 0)
+      v = wi * txl;
+  }
+  return v;
+}
+
+__device__ __forceinline__ void decode(uint32_t code, int& dx, int& dy, bool& hop) {
+  dx = int(code & 3u) - 1;
+  dy = int((code >> 2) & 3u) - 1;
+  hop = (code >> 4) & 1u;
+}
+
+template <int TX, int R>
+struct TileShape {
+  static constexpr int TR = kBlock / TX;  // thread rows per block
+  static constexpr int TY = TR * R;       // tile height in cells
+  static constexpr int LP = TX + 2;       // LDS row pitch (one halo column each side)
+  static constexpr int LH = TY + 2;       // LDS rows (one halo row each side)
+  static constexpr int D = R >= 4 ? 4 : 8;  // directions per load group (D*R loads in flight)
+};
+
+// Boundary node of a diffuse wall (Sec. 2.6, Eq. adiabatic-diffuse): the node
+// at column X behind the lo (wall 0, row -1) or hi (wall 1, row ny) wall
+// absorbs what streams into it on this step and re-emits it isotropically,
+// as inward DDEDs w_i T_g.  A direction with an inward pending move delivers
+// w_i T_g on a hop and w_i W_g T_g (its EED part) on a pause; T_g is chosen so
+// that the node emits exactly what it absorbed.  Returns T_g and W_g T_g.
+// The node below/above a blackbody column belongs to the blackbody wall.
+template <bool WF>
+__device__ void boundary_node(const StepArgs& a, int wall, int X, float& tg, float& wtg) {
+  const int yrow = wall == 0 ? 0 : a.ny - 1;
+  const int out_dy = wall == 0 ? -1 : 1;
+  if (a.x_edge == kBlackbody) {
+    if (X < 0 || X >= a.nx) {
+      tg = wtg = 0.f;
+      return;
+    }
+    if (X == 0 || X == a.nx - 1) {
+      const float Wg = WF ? a.Wf[cell(X, yrow, a.pitch)] : a.W;
+      tg = (X == a.nx - 1) ? a.t_x_hi : a.t_x_lo;
+      wtg = Wg * tg;
+      return;
+    }
+  } else {
+    X = ((X % a.nx) + a.nx) % a.nx;
+  }
+  const float Wg = WF ? a.Wf[cell(X, yrow, a.pitch)] : a.W;
+  float R = 0.f;
+  for (int i = 0; i < a.q; ++i) {
+    const uint32_t code = (a.codes[i >> 2] >> (8 * (i & 3))) & 0xffu;
+    int dx, dy;
+    bool hop;
+    decode(code, dx, dy, hop);
+    if (dy != out_dy) continue;
+    // source cell of the packet; for a periodic x edge the ghost columns
+    // hold the wrapped values, for a blackbody edge X - dx stays inside
+    const long long o = cell(X - dx, yrow, a.pitch);
+    const float Ws = WF ? a.Wf[o] : a.W;
+    const float e = a.e_in[(long long)i * a.plane + o];
+    if (hop) R += fmaf(-Ws, e, e);
+    R = fmaf(Ws * a.wtab[i], a.E_in[o], R);
+  }
+  const float hs = wall == 0 ? a.in_lo_hop : a.in_hi_hop;
+  const float as = wall == 0 ? a.in_lo_all : a.in_hi_all;
+  const float C = fmaf(Wg, as - hs, hs);
+  tg = R / C;
+  wtg = Wg * tg;
+}
+
+// The per-cell sweep over all directions.  EDGE tiles touch a domain edge or
+// are ragged: they mask cells outside the lattice, apply the wall
+// conditions and write the ghost copies of periodic edges.  Interior tiles
+// need none of that: every source cell of a pull lies inside the padded
+// arrays, with no wrap arithmetic.
+template <int TX, int R, bool WF, bool FLUX, bool EDGE>
+__device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const float* sW,
+                                      const float* sTg, const float* sWTg, int x0, int y0) {
+  using T = TileShape<TX, R>;
+  constexpr int D = T::D;
+  const WLBM_CONST uint32_t* codes = scalar_ptr(a.codes);
+  const WLBM_CONST float* wtab = scalar_ptr(a.wtab);
+  const WLBM_CONST float* sxtab = scalar_ptr(a.sxtab);
+  const WLBM_CONST float* sytab = scalar_ptr(a.sytab);
+  const int lx = threadIdx.x % TX;
+  const int ly = threadIdx.x / TX;
+  const int x = x0 + lx;
+  const int yb = y0 + ly * R;
+  const bool px = a.x_edge == kPeriodic;
+  const bool py = a.y_edge == kPeriodic;
+  const int pitch = a.pitch;
+  const long long plane = a.plane;
+  // source window of a direction: its plane plus one row and column either
+  // side, so that the shifted offset below is never negative
+  const uint32_t win_bytes = uint32_t((plane + 2 * (pitch + 1)) * 4);
+  const uint32_t plane_bytes = uint32_t(plane * 4);
+
+  uint32_t boff[R];
+  bool ok[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    ok[r] = !EDGE || (x < a.nx && yb + r < a.ny);
+    // lanes outside a ragged lattice read a valid cell and store nothing
+    boff[r] = uint32_t(cell(ok[r] ? x : 0, ok[r] ? yb + r : 0, pitch) * 4);
+  }
+  const int lc = (ly * R + 1) * T::LP + lx + 1;
+
+  float Eacc[R], qx[R], qy[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) Eacc[r] = qx[r] = qy[r] = 0.f;
+
+  for (int i0 = 0; i0 < a.q; i0 += D) {
+    uint32_t words[D / 4];
+#pragma unroll
+    for (int k = 0; k < D / 4; ++k) words[k] = codes[(i0 >> 2) + k];
+    float v[D][R];
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      int dx, dy;
+      bool hop;
+      decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
+      const int sh = hop ? dy * pitch + dx : 0;
+      const rsrc_t rs = make_rsrc(a.e_in + (long long)(i0 + d) * plane - (pitch + 1), win_bytes);
+      const uint32_t soff = uint32_t((pitch + 1 - sh) * 4);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[d][r] = buf_load(rs, boff[r], soff);
+    }
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+      const int i = i0 + d;
+      int dx, dy;
+      bool hop;
+      decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
+      const float wi = wtab[i];
+      const rsrc_t ro = make_rsrc(a.e_out + (long long)i * plane, plane_bytes);
+      const int ls = lc - (dy * T::LP + dx);
+      const int lh = hop ? ls : lc;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float e = v[d][r];
+        const float Es = sE[ls + r * T::LP];
+        float out;
+        if constexpr (!WF) {
+          // e + W (w_i E - e): the rounding error stays relative to the
+          // (small) change, so a nearly ballistic run does not drift
+          out = fmaf(a.W, fmaf(wi, Es, -e), e);
+        } else {
+          // sE holds W E; sW holds W of each cell
+          const float Wh = sW[lh + r * T::LP];
+          out = e + fmaf(wi, Es, -(Wh * e));
+        }
+        if constexpr (EDGE) {
+          if (!ok[r]) continue;
+          const int y = yb + r;
+          if (a.y_edge == kDiffuse) {
+            if (y == 0 && dy == 1) out = fmaf(wi, (hop ? sTg : sWTg)[lx + 1 - dx], out);
+            if (y == a.ny - 1 && dy == -1)
+              out = fmaf(wi, (hop ? sTg : sWTg)[T::LP + lx + 1 - dx], out);
+          }
+          out = blackbody(out, wi, x, y, a.nx, a.ny, a.x_edge, a.y_edge, a.t_x_lo, a.t_x_hi,
+                          a.t_y_lo, a.t_y_hi);
+          if ((px && (x == 0 || x == a.nx - 1)) || (py && (y == 0 || y == a.ny - 1)))
+            store_ghosted(a.e_out + (long long)i * plane, x, y, out, a.nx, a.ny, pitch, px, py);
+          else
+            buf_store(out, ro, boff[r]);
+        } else {
+          buf_store(out, ro, boff[r]);
+        }
+        Eacc[r] += out;
+        if constexpr (FLUX) {
+          qx[r] = fmaf(out, sxtab[i], qx[r]);
+          qy[r] = fmaf(out, sytab[i], qy[r]);
+        }
+      }
+    }
+  }
+
+  const rsrc_t rE = make_rsrc(a.E_out, plane_bytes);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (EDGE && !ok[r]) continue;
+    const int y = yb + r;
+    if (EDGE && ((px && (x == 0 || x == a.nx - 1)) || (py && (y == 0 || y == a.ny - 1))))
+      store_ghosted(a.E_out, x, y, Eacc[r], a.nx, a.ny, pitch, px, py);
+    else
+      buf_store(Eacc[r], rE, boff[r]);
+    if constexpr (FLUX) {
+      const long long o = (long long)y * a.nx + x;
+      if (a.q_first) {
+        a.qsx[o] = qx[r];
+        a.qsy[o] = qy[r];
+      } else {
+        a.qsx[o] += qx[r];
+        a.qsy[o] += qy[r];
+      }
+    }
+  }
+}
+
+template <int TX, int R, bool WF, bool FLUX>
+__global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
+  using T = TileShape<TX, R>;
+  __shared__ float sE[T::LH * T::LP];
+  __shared__ float sW[WF ? T::LH * T::LP : 1];
+  __shared__ float sTg[2 * T::LP];
+  __shared__ float sWTg[2 * T::LP];
+
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = t % a.tiles_x;
+  const int ty = t / a.tiles_x;
+  const int x0 = tx * TX;
+  const int y0 = ty * T::TY;
+
+  // Stage E (per-cell mode: W E) and W of the tile plus a one-cell halo.
+  // Ghost rows/columns give the wrapped values of periodic edges and zero
+  // beyond walls; cells past the ragged end of the lattice read as zero.
+  for (int k = threadIdx.x; k < T::LH * T::LP; k += kBlock) {
+    const int rr = k / T::LP;
+    const int cc = k - rr * T::LP;
+    const int gx = x0 - 1 + cc;
+    const int gy = y0 - 1 + rr;
+    float ev = 0.f, wv = 0.f;
+    if (gx <= a.nx && gy <= a.ny) {
+      const long long o = cell(gx, gy, a.pitch);
+      ev = a.E_in[o];
+      if constexpr (WF) {
+        wv = a.Wf[o];
+        ev *= wv;
+      }
+    }
+    sE[k] = ev;
+    if constexpr (WF) sW[k] = wv;
+  }
+  const bool edge = x0 == 0 || x0 + TX >= a.nx || y0 == 0 || y0 + T::TY >= a.ny;
+  if (edge && a.y_edge == kDiffuse) {
+    const bool lo = y0 == 0;
+    const bool hi = a.ny - 1 < y0 + T::TY;
+    for (int k = threadIdx.x; k < 2 * T::LP; k += kBlock) {
+      const int wall = k / T::LP;
+      if (wall == 0 ? !lo : !hi) continue;
+      float tg, wtg;
+      boundary_node<WF>(a, wall, x0 - 1 + (k - wall * T::LP), tg, wtg);
+      sTg[k] = tg;
+      sWTg[k] = wtg;
+    }
+  }
+  __syncthreads();
+  if (edge)
+    sweep<TX, R, WF, FLUX, true>(a, sE, sW, sTg, sWTg, x0, y0);
+  else
+    sweep<TX, R, WF, FLUX, false>(a, sE, sW, sTg, sWTg, x0, y0);
+}
+
+template <int TX, int R, bool WF, bool FLUX>
+hipError_t launch_tmpl(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_step<TX, R, WF, FLUX>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int TX, int R>
+hipError_t launch_tr(const StepArgs& a, bool wf, bool fl, hipStream_t s) {
+  if (wf) return fl ? launch_tmpl<TX, R, true, true>(a, s) : launch_tmpl<TX, R, true, false>(a, s);
+  return fl ? launch_tmpl<TX, R, false, true>(a, s) : launch_tmpl<TX, R, false, false>(a, s);
+}
+
+template <int TX>
+hipError_t launch_t(const StepArgs& a, int rows, bool wf, bool fl, hipStream_t s) {
+  switch (rows) {
+    case 1: return launch_tr<TX, 1>(a, wf, fl, s);
+    case 2: return launch_tr<TX, 2>(a, wf, fl, s);
+    case 4: return launch_tr<TX, 4>(a, wf, fl, s);
+    case 8: return launch_tr<TX, 8>(a, wf, fl, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Set-up, readout and reduction kernels
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_init_temperature(const Geometry g, const float* T0,
+                                                            float* e, float* E,
+                                                            const float* wtab, Walls w) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= (long long)g.nx * g.ny) return;
+  const int x = int(c % g.nx);
+  const int y = int(c / g.nx);
+  const bool px = g.x_edge == kPeriodic, py = g.y_edge == kPeriodic;
+  const float T = T0[c];
+  float sum = 0.f;
+  for (int i = 0; i < g.q; ++i) {
+    const float wi = wtab[i];
+    const float v = blackbody(wi * T, wi, x, y, g.nx, g.ny, g.x_edge, g.y_edge, w.x_lo, w.x_hi,
+                              w.y_lo, w.y_hi);
+    store_ghosted(e + (long long)i * g.plane, x, y, v, g.nx, g.ny, g.pitch, px, py);
+    sum += v;
+  }
+  store_ghosted(E, x, y, sum, g.nx, g.ny, g.pitch, px, py);
+}
+
+__global__ __launch_bounds__(kBlock) void k_init_populations(const Geometry g, const float* src,
+                                                            float* e, float* E,
+                                                            const float* wtab, Walls w) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long ncell = (long long)g.nx * g.ny;
+  if (c >= ncell) return;
+  const int x = int(c % g.nx);
+  const int y = int(c / g.nx);
+  const bool px = g.x_edge == kPeriodic, py = g.y_edge == kPeriodic;
+  float sum = 0.f;
+  for (int i = 0; i < g.q; ++i) {
+    const float v = blackbody(src[(long long)i * ncell + c], wtab[i], x, y, g.nx, g.ny,
+                              g.x_edge, g.y_edge, w.x_lo, w.x_hi, w.y_lo, w.y_hi);
+    store_ghosted(e + (long long)i * g.plane, x, y, v, g.nx, g.ny, g.pitch, px, py);
+    sum += v;
+  }
+  store_ghosted(E, x, y, sum, g.nx, g.ny, g.pitch, px, py);
+}
+
+__global__ __launch_bounds__(kBlock) void k_read_populations(const Geometry g, const float* e,
+                                                            float* dst) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  const long long ncell = (long long)g.nx * g.ny;
+  if (c >= ncell) return;
+  const int i = blockIdx.y;
+  const int x = int(c % g.nx);
+  const int y = int(c / g.nx);
+  dst[(long long)i * ncell + c] = e[(long long)i * g.plane + cell(x, y, g.pitch)];
+}
+
+__global__ __launch_bounds__(kBlock) void k_read_field(const Geometry g, const float* f,
+                                                      float* dst) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= (long long)g.nx * g.ny) return;
+  dst[c] = f[cell(int(c % g.nx), int(c / g.nx), g.pitch)];
+}
+
+__global__ __launch_bounds__(kBlock) void k_read_flux(const Geometry g, const float* e,
+                                                     const float* sxtab, const float* sytab,
+                                                     float* qx, float* qy) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= (long long)g.nx * g.ny) return;
+  const long long o = cell(int(c % g.nx), int(c / g.nx), g.pitch);
+  float ax = 0.f, ay = 0.f;
+  for (int i = 0; i < g.q; ++i) {
+    const float v = e[(long long)i * g.plane + o];
+    ax = fmaf(v, sxtab[i], ax);
+    ay = fmaf(v, sytab[i], ay);
+  }
+  qx[c] = ax;
+  qy[c] = ay;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale_pair(int n, const float* ax, const float* ay,
+                                                      float s, float* bx, float* by) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= n) return;
+  bx[c] = ax[c] * s;
+  by[c] = ay[c] * s;
+}
+
+// Deterministic block sum of three doubles in shared memory.
+__device__ void block_sum3(double* sh, double a, double b, double c, double* out) {
+  sh[threadIdx.x] = a;
+  sh[kBlock + threadIdx.x] = b;
+  sh[2 * kBlock + threadIdx.x] = c;
+  __syncthreads();
+  for (int s = kBlock / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      sh[threadIdx.x] += sh[threadIdx.x + s];
+      sh[kBlock + threadIdx.x] += sh[kBlock + threadIdx.x + s];
+      sh[2 * kBlock + threadIdx.x] += sh[2 * kBlock + threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = sh[0];
+    out[1] = sh[kBlock];
+    out[2] = sh[2 * kBlock];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_totals_partial(const Geometry g, const float* e,
+                                                          const float* E, const float* sxtab,
+                                                          const float* sytab,
+                                                          double* partials) {
+  __shared__ double sh[3 * kBlock];
+  const long long ncell = (long long)g.nx * g.ny;
+  double se = 0.0, sqx = 0.0, sqy = 0.0;
+  for (long long c = (long long)blockIdx.x * kBlock + threadIdx.x; c < ncell;
+       c += (long long)gridDim.x * kBlock) {
+    const long long o = cell(int(c % g.nx), int(c / g.nx), g.pitch);
+    se += double(E[o]);
+    double ax = 0.0, ay = 0.0;
+    for (int i = 0; i < g.q; ++i) {
+      const double v = e[(long long)i * g.plane + o];
+      ax += v * double(sxtab[i]);
+      ay += v * double(sytab[i]);
+    }
+    sqx += ax;
+    sqy += ay;
+  }
+  block_sum3(sh, se, sqx, sqy, partials + 3 * blockIdx.x);
+}
+
+__global__ __launch_bounds__(kBlock) void k_totals_final(const double* partials, int nb,
+                                                        double* out) {
+  __shared__ double sh[3 * kBlock];
+  double a = 0.0, b = 0.0, c = 0.0;
+  for (int k = threadIdx.x; k < nb; k += kBlock) {
+    a += partials[3 * k];
+    b += partials[3 * k + 1];
+    c += partials[3 * k + 2];
+  }
+  block_sum3(sh, a, b, c, out);
+}
+
+__device__ __forceinline__ double corrected(double mfp, double lam, double f, int corr) {
+  const double W = isinf(mfp) ? 0.0 : 1.0 / mfp;
+  if (!corr) return W;
+  return f * ((1.0 - W) * W + W * (W * lam));
+}
+
+__global__ __launch_bounds__(kBlock) void k_check_mfp(const Geometry g, const float* mfp,
+                                                     double lam, double f, int corr, int* flag) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= (long long)g.nx * g.ny) return;
+  const double m = mfp[c];
+  bool bad = !(m > 0.0);
+  if (!bad) {
+    const double wc = corrected(m, lam, f, corr);
+    bad = !(wc <= 1.0) || !isfinite(wc);
+  }
+  if (bad) *flag = 1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_write_wfield(const Geometry g, const float* mfp,
+                                                        double lam, double f, int corr,
+                                                        float* Wf) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= (long long)g.nx * g.ny) return;
+  const int x = int(c % g.nx);
+  const int y = int(c / g.nx);
+  store_ghosted(Wf, x, y, float(corrected(mfp[c], lam, f, corr)), g.nx, g.ny, g.pitch,
+                g.x_edge == kPeriodic, g.y_edge == kPeriodic);
+}
+
+unsigned cell_blocks(const Geometry& g) {
+  return unsigned(((long long)g.nx * g.ny + kBlock - 1) / kBlock);
+}
+
+}  // namespace
+
+int tiles_x_for(int nx, int tile_x) { return (nx + tile_x - 1) / tile_x; }
+int tiles_y_for(int ny, int tile_x, int rows) {
+  const int ty = (kBlock / tile_x) * rows;
+  return (ny + ty - 1) / ty;
+}
+
+hipError_t launch_step(const StepArgs& a, int tile_x, int rows, bool per_cell, bool flux,
+                       hipStream_t s) {
+  switch (tile_x) {
+    case 64: return launch_t<64>(a, rows, per_cell, flux, s);
+    case 128: return launch_t<128>(a, rows, per_cell, flux, s);
+    case 256: return launch_t<256>(a, rows, per_cell, flux, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_init_temperature(const Geometry& g, const float* T0, float* e, float* E,
+                                   const float* wtab, Walls walls, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_temperature, dim3(cell_blocks(g)), dim3(kBlock), 0, s, g, T0, e, E,
+                     wtab, walls);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_populations(const Geometry& g, const float* src, float* e, float* E,
+                                   const float* wtab, Walls walls, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_populations, dim3(cell_blocks(g)), dim3(kBlock), 0, s, g, src, e, E,
+                     wtab, walls);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_populations(const Geometry& g, const float* e, float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_read_populations, dim3(cell_blocks(g), g.q), dim3(kBlock), 0, s, g, e,
+                     dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_field(const Geometry& g, const float* f, float* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_read_field, dim3(cell_blocks(g)), dim3(kBlock), 0, s, g, f, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_read_flux(const Geometry& g, const float* e, const float* sxtab,
+                            const float* sytab, float* qx, float* qy, hipStream_t s) {
+  hipLaunchKernelGGL(k_read_flux, dim3(cell_blocks(g)), dim3(kBlock), 0, s, g, e, sxtab, sytab,
+                     qx, qy);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_pair(int n, const float* ax, const float* ay, float scale, float* bx,
+                             float* by, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_pair, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, ax, ay,
+                     scale, bx, by);
+  return hipGetLastError();
+}
+
+hipError_t launch_totals(const Geometry& g, const float* e, const float* E, const float* sxtab,
+                         const float* sytab, double* partials, int max_blocks, double* out,
+                         hipStream_t s) {
+  const long long need = ((long long)g.nx * g.ny + kBlock - 1) / kBlock;
+  const int nb = int(need < max_blocks ? need : max_blocks);
+  hipLaunchKernelGGL(k_totals_partial, dim3(nb), dim3(kBlock), 0, s, g, e, E, sxtab, sytab,
+                     partials);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(kBlock), 0, s, partials, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_mfp(const Geometry& g, const float* mfp, double lam, double f, int corr,
+                            int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_mfp, dim3(cell_blocks(g)), dim3(kBlock), 0, s, g, mfp, lam, f, corr,
+                     flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_write_wfield(const Geometry& g, const float* mfp, double lam, double f,
+                               int corr, float* Wf, hipStream_t s) {
+  hipLaunchKernelGGL(k_write_wfield, dim3(cell_blocks(g)), dim3(kBlock), 0, s, g, mfp, lam, f,
+                     corr, Wf);
+  return hipGetLastError();
+}
+
+}  // namespace wlbm

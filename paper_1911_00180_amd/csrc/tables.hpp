@@ -1,0 +1,66 @@
+// Host-side tables of the worm-LBM: direction sets, angular weights, the
+// grid-MFP correction, closed-form worm paths and the integer TAS schedule.
+// Plain C++17, no GPU code; used by the C-ABI layer to build what the kernels
+// read.  Sections and equations are those of arXiv:1911.00180.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace wlbm {
+
+enum DirKind { kUniform = 0, kRing = 1 };
+
+// One direction set D2Q[M x 8] (Sec. 2.4).  For each direction i:
+//   sx, sy      unit vector
+//   w           angular weight (Eq. weight; 1/Q for the uniform set)
+//   speed       net displacement of one worm hop, c_i = 1/max(|sx|,|sy|)
+//   major       axis of the larger component (0 = x, 1 = y; the diagonals,
+//               where both are equal, take x)
+//   sgn_major   sign of the major component (+1/-1)
+//   sgn_minor   sign of the minor component (+1/-1, 0 on an axis)
+//   slope       |minor| / |major| in FP64 (uniform set)
+//   ring_j      |minor| of the integer lattice vector (ring set; |major| = M)
+struct DirSet {
+  int q = 0;
+  int kind = kUniform;
+  int m = 0;
+  std::vector<double> sx, sy, w, speed, slope;
+  std::vector<int> major, sgn_major, sgn_minor;
+  std::vector<int64_t> ring_j;
+  double lambda_corr = 0.0;  // Q / sum_i speed_i (Eq. W-correction-factor-gereralized)
+};
+
+DirSet build_dirs(int q, int kind);
+
+// Corrected relaxation weight of Eq. W-correction; f = 3/2 when a 2D run
+// emulates 3D, the plain W when the correction is switched off.
+double corrected_weight(double W, double lambda_corr, bool emulate_3d, bool correction);
+
+// Coordinate along the minor axis (in magnitude) of the worm after k hops.
+// The worm takes the D2Q8 move whose landing point is nearest to the ray
+// point with major coordinate k (Eq. worm-paths), ties going to the diagonal
+// move; its minor coordinate is therefore k*t rounded half up.  For the ring
+// set t = j/M and the rounding is done in integers.
+int64_t worm_minor(const DirSet& d, int i, int64_t k);
+
+// The k-th (1-based) worm move of direction i as a D2Q8 step (dx, dy).
+void worm_move(const DirSet& d, int i, int64_t k, int* dx, int* dy);
+
+// D2Q8 index 1..8 (E, N, W, S, NE, NW, SW, SE) of a step (dx, dy).
+int d2q8_index(int dx, int dy);
+
+// Time-adaptive scheme state (Sec. 2.3, Sec. 2.5): per direction the worm
+// position P_i and the number k_i of executed worm moves; n = steps done.
+struct TasState {
+  std::vector<int64_t> px, py, k;
+  int64_t n = 0;
+  void reset(int q);
+};
+
+// One step of the schedule (step n = st.n + 1): for each direction the
+// pending move s_i and whether the DDED hops, hop iff |P_i + s_i|^2 <= (n+1)^2
+// in exact integers; on a hop P_i and k_i advance.  Outputs are [q] arrays.
+void tas_advance(const DirSet& d, TasState& st, int8_t* dx, int8_t* dy, uint8_t* hop);
+
+}  // namespace wlbm

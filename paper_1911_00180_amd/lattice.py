@@ -1,0 +1,108 @@
+"""A worm-LBM lattice on one GPU, with PyTorch providing device memory and the
+stream.  Thin convenience layer over the C-ABI binding: it allocates the
+workspace and output tensors and passes their pointers; every step of the
+method runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import wormlbm as W
+
+
+class Lattice:
+    def __init__(self, nx: int, ny: int, q: int, mfp: float = float("inf"),
+                 device: str | torch.device = "cuda", **kw):
+        self.params = W.make_params(nx, ny, q, mfp=mfp, **kw)
+        self.nx, self.ny, self.q = nx, ny, q
+        self.device = torch.device(device)
+        nbytes = W.wlbm_workspace_bytes(self.params)
+        # the caching allocator returns at least 512-byte aligned blocks
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = W.wlbm_create(self.params, self.workspace.data_ptr(), nbytes,
+                                    self._stream())
+        self._mfp_field = None
+
+    def _stream(self) -> int:
+        return torch.cuda.current_stream(self.device).cuda_stream
+
+    def _sync_stream(self) -> None:
+        W.wlbm_set_stream(self.handle, self._stream())
+
+    def _field(self, t: torch.Tensor, shape) -> torch.Tensor:
+        t = torch.as_tensor(t, dtype=torch.float32, device=self.device).contiguous()
+        if tuple(t.shape) != tuple(shape):
+            raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
+
+    # -- state ---------------------------------------------------------------
+    def set_temperature(self, T0) -> None:
+        self._sync_stream()
+        t = self._field(T0, (self.ny, self.nx))
+        W.wlbm_set_temperature(self.handle, t.data_ptr())
+        self._keep = t
+
+    def set_populations(self, e) -> None:
+        self._sync_stream()
+        t = self._field(e, (self.q, self.ny, self.nx))
+        W.wlbm_set_populations(self.handle, t.data_ptr())
+        self._keep = t
+
+    def set_mfp_field(self, mfp) -> None:
+        self._sync_stream()
+        if mfp is None:
+            W.wlbm_set_mfp_field(self.handle, None)
+            self._mfp_field = None
+            return
+        t = self._field(mfp, (self.ny, self.nx))
+        W.wlbm_set_mfp_field(self.handle, t.data_ptr())
+        self._mfp_field = t
+
+    def set_wall_temperatures(self, t_x_lo=0.0, t_x_hi=0.0, t_y_lo=0.0, t_y_hi=0.0) -> None:
+        W.wlbm_set_wall_temperatures(self.handle, t_x_lo, t_x_hi, t_y_lo, t_y_hi)
+
+    def set_flux_window(self, window: int) -> None:
+        W.wlbm_set_flux_window(self.handle, window)
+
+    def step(self, n: int = 1) -> None:
+        self._sync_stream()
+        W.wlbm_step(self.handle, n)
+
+    @property
+    def step_count(self) -> int:
+        return W.wlbm_step_count(self.handle)
+
+    # -- readout -------------------------------------------------------------
+    def temperature(self) -> torch.Tensor:
+        self._sync_stream()
+        T = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        W.wlbm_read_temperature(self.handle, T.data_ptr())
+        return T
+
+    def heat_flux(self, averaged: bool = False):
+        self._sync_stream()
+        qx = torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device)
+        qy = torch.empty_like(qx)
+        W.wlbm_read_heat_flux(self.handle, qx.data_ptr(), qy.data_ptr(), int(averaged))
+        return qx, qy
+
+    def populations(self) -> torch.Tensor:
+        self._sync_stream()
+        e = torch.empty((self.q, self.ny, self.nx), dtype=torch.float32, device=self.device)
+        W.wlbm_read_populations(self.handle, e.data_ptr())
+        return e
+
+    def totals(self):
+        self._sync_stream()
+        return W.wlbm_read_totals(self.handle)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            W.wlbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,246 @@
+"""ctypes binding of libwormlbm.so (C-ABI declared in include/wormlbm.h).
+
+Argument marshalling only: every function forwards to the C function of the
+same name; device pointers are passed as integers (e.g. ``tensor.data_ptr()``)
+and streams as the raw HIP stream handle.  Failing calls raise WormLBMError
+with the library's status and message.  The library is loaded on first use;
+if it has not been built this raises instead of falling back to anything.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int8, c_int32, c_int64, \
+    c_size_t, c_void_p
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwormlbm.so")
+
+WLBM_OK = 0
+WLBM_EINVAL = -1
+WLBM_EUNSTABLE = -2
+WLBM_ENOMEM = -3
+WLBM_EHIP = -4
+WLBM_ENONFINITE = -5
+WLBM_ESTATE = -6
+
+EDGE_PERIODIC, EDGE_BLACKBODY, EDGE_DIFFUSE = 0, 1, 2
+DIRS_UNIFORM, DIRS_RING = 0, 1
+
+STATUS_NAMES = {0: "WLBM_OK", -1: "WLBM_EINVAL", -2: "WLBM_EUNSTABLE", -3: "WLBM_ENOMEM",
+                -4: "WLBM_EHIP", -5: "WLBM_ENONFINITE", -6: "WLBM_ESTATE"}
+
+# every function the header declares, checked by the test suite
+EXPORTS = (
+    "wlbm_default_params", "wlbm_workspace_bytes", "wlbm_create", "wlbm_set_stream",
+    "wlbm_set_temperature", "wlbm_set_populations", "wlbm_set_mfp_field",
+    "wlbm_set_wall_temperatures", "wlbm_set_flux_window", "wlbm_step",
+    "wlbm_read_temperature", "wlbm_read_heat_flux", "wlbm_read_populations",
+    "wlbm_read_totals", "wlbm_get_directions", "wlbm_get_constants", "wlbm_get_schedule",
+    "wlbm_step_count", "wlbm_last_error", "wlbm_destroy",
+)
+
+
+class WlbmParams(ctypes.Structure):
+    """Mirror of struct wlbm_params."""
+    _fields_ = [
+        ("nx", c_int32), ("ny", c_int32), ("q", c_int32), ("dirs", c_int32),
+        ("mfp_cells", c_double),
+        ("emulate_3d", c_int32), ("mfp_correction", c_int32),
+        ("x_edge", c_int32), ("y_edge", c_int32),
+        ("t_x_lo", c_double), ("t_x_hi", c_double), ("t_y_lo", c_double), ("t_y_hi", c_double),
+        ("tile_x", c_int32), ("rows_per_thread", c_int32), ("sched_chunk", c_int32),
+        ("reserved", c_int32 * 5),
+    ]
+
+
+class WormLBMError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libwormlbm.so (once)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_1911_00180_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = POINTER(WlbmParams)
+    sig = {
+        "wlbm_default_params": (None, [P]),
+        "wlbm_workspace_bytes": (c_int, [P, POINTER(c_size_t)]),
+        "wlbm_create": (c_int, [P, c_void_p, c_size_t, c_void_p, POINTER(c_void_p)]),
+        "wlbm_set_stream": (c_int, [c_void_p, c_void_p]),
+        "wlbm_set_temperature": (c_int, [c_void_p, c_void_p]),
+        "wlbm_set_populations": (c_int, [c_void_p, c_void_p]),
+        "wlbm_set_mfp_field": (c_int, [c_void_p, c_void_p]),
+        "wlbm_set_wall_temperatures": (c_int, [c_void_p, c_double, c_double, c_double, c_double]),
+        "wlbm_set_flux_window": (c_int, [c_void_p, c_int32]),
+        "wlbm_step": (c_int, [c_void_p, c_int64]),
+        "wlbm_read_temperature": (c_int, [c_void_p, c_void_p]),
+        "wlbm_read_heat_flux": (c_int, [c_void_p, c_void_p, c_void_p, c_int32]),
+        "wlbm_read_populations": (c_int, [c_void_p, c_void_p]),
+        "wlbm_read_totals": (c_int, [c_void_p, POINTER(c_double), POINTER(c_double),
+                                     POINTER(c_double)]),
+        "wlbm_get_directions": (c_int, [P, POINTER(c_double), POINTER(c_double),
+                                        POINTER(c_double)]),
+        "wlbm_get_constants": (c_int, [P, POINTER(c_double), POINTER(c_double),
+                                       POINTER(c_double)]),
+        "wlbm_get_schedule": (c_int, [P, c_int64, c_int64, POINTER(c_int8), POINTER(c_int64)]),
+        "wlbm_step_count": (c_int64, [c_void_p]),
+        "wlbm_last_error": (c_char_p, []),
+        "wlbm_destroy": (c_int, [c_void_p]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status: int) -> None:
+    if status != WLBM_OK:
+        msg = lib().wlbm_last_error().decode(errors="replace")
+        raise WormLBMError(status, msg)
+
+
+def _ptr(x):
+    """Device or host pointer from an int, a torch tensor or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return c_void_p(x)
+    return c_void_p(x.data_ptr())
+
+
+# -- one wrapper per C function ---------------------------------------------
+def wlbm_default_params() -> WlbmParams:
+    p = WlbmParams()
+    lib().wlbm_default_params(byref(p))
+    return p
+
+
+def wlbm_workspace_bytes(p: WlbmParams) -> int:
+    n = c_size_t(0)
+    _check(lib().wlbm_workspace_bytes(byref(p), byref(n)))
+    return n.value
+
+
+def wlbm_create(p: WlbmParams, d_workspace, ws_bytes: int, stream) -> int:
+    h = c_void_p()
+    _check(lib().wlbm_create(byref(p), _ptr(d_workspace), ws_bytes, c_void_p(stream or 0),
+                             byref(h)))
+    return h.value
+
+
+def wlbm_set_stream(h: int, stream) -> None:
+    _check(lib().wlbm_set_stream(c_void_p(h), c_void_p(stream or 0)))
+
+
+def wlbm_set_temperature(h: int, d_T0) -> None:
+    _check(lib().wlbm_set_temperature(c_void_p(h), _ptr(d_T0)))
+
+
+def wlbm_set_populations(h: int, d_e) -> None:
+    _check(lib().wlbm_set_populations(c_void_p(h), _ptr(d_e)))
+
+
+def wlbm_set_mfp_field(h: int, d_mfp) -> None:
+    _check(lib().wlbm_set_mfp_field(c_void_p(h), _ptr(d_mfp)))
+
+
+def wlbm_set_wall_temperatures(h: int, t_x_lo: float, t_x_hi: float, t_y_lo: float,
+                               t_y_hi: float) -> None:
+    _check(lib().wlbm_set_wall_temperatures(c_void_p(h), t_x_lo, t_x_hi, t_y_lo, t_y_hi))
+
+
+def wlbm_set_flux_window(h: int, window: int) -> None:
+    _check(lib().wlbm_set_flux_window(c_void_p(h), window))
+
+
+def wlbm_step(h: int, nsteps: int) -> None:
+    _check(lib().wlbm_step(c_void_p(h), nsteps))
+
+
+def wlbm_read_temperature(h: int, d_T) -> None:
+    _check(lib().wlbm_read_temperature(c_void_p(h), _ptr(d_T)))
+
+
+def wlbm_read_heat_flux(h: int, d_qx, d_qy, averaged: int = 0) -> None:
+    _check(lib().wlbm_read_heat_flux(c_void_p(h), _ptr(d_qx), _ptr(d_qy), averaged))
+
+
+def wlbm_read_populations(h: int, d_e) -> None:
+    _check(lib().wlbm_read_populations(c_void_p(h), _ptr(d_e)))
+
+
+def wlbm_read_totals(h: int):
+    e, qx, qy = c_double(), c_double(), c_double()
+    _check(lib().wlbm_read_totals(c_void_p(h), byref(e), byref(qx), byref(qy)))
+    return e.value, qx.value, qy.value
+
+
+def wlbm_get_directions(p: WlbmParams):
+    import numpy as np
+    sx, sy, w = (np.zeros(p.q) for _ in range(3))
+    D = POINTER(c_double)
+    _check(lib().wlbm_get_directions(byref(p), sx.ctypes.data_as(D), sy.ctypes.data_as(D),
+                                     w.ctypes.data_as(D)))
+    return sx, sy, w
+
+
+def wlbm_get_constants(p: WlbmParams):
+    lam, w, wc = c_double(), c_double(), c_double()
+    _check(lib().wlbm_get_constants(byref(p), byref(lam), byref(w), byref(wc)))
+    return lam.value, w.value, wc.value
+
+
+def wlbm_get_schedule(p: WlbmParams, step0: int, n: int, positions: bool = False):
+    """(moves [n, q] int8, positions [n, q, 2] int64 or None)."""
+    import numpy as np
+    moves = np.zeros((n, p.q), dtype=np.int8)
+    pos = np.zeros((n, p.q, 2), dtype=np.int64) if positions else None
+    _check(lib().wlbm_get_schedule(
+        byref(p), step0, n, moves.ctypes.data_as(POINTER(c_int8)),
+        pos.ctypes.data_as(POINTER(c_int64)) if positions else None))
+    return moves, pos
+
+
+def wlbm_step_count(h: int) -> int:
+    return lib().wlbm_step_count(c_void_p(h))
+
+
+def wlbm_last_error() -> str:
+    return lib().wlbm_last_error().decode(errors="replace")
+
+
+def wlbm_destroy(h: int) -> None:
+    _check(lib().wlbm_destroy(c_void_p(h)))
+
+
+def make_params(nx: int, ny: int, q: int, mfp: float = float("inf"), dirs: str = "uniform",
+                emulate_3d: bool = False, mfp_correction: bool = True,
+                x_edge: str = "periodic", y_edge: str = "periodic",
+                t_x_lo: float = 0.0, t_x_hi: float = 0.0, t_y_lo: float = 0.0,
+                t_y_hi: float = 0.0, tile_x: int = 0, rows_per_thread: int = 0,
+                sched_chunk: int = 0) -> WlbmParams:
+    """Parameters from keyword arguments (edge and direction names as strings)."""
+    edges = {"periodic": EDGE_PERIODIC, "blackbody": EDGE_BLACKBODY, "diffuse": EDGE_DIFFUSE}
+    p = wlbm_default_params()
+    p.nx, p.ny, p.q = nx, ny, q
+    p.dirs = {"uniform": DIRS_UNIFORM, "ring": DIRS_RING}[dirs]
+    p.mfp_cells = mfp
+    p.emulate_3d = int(emulate_3d)
+    p.mfp_correction = int(mfp_correction)
+    p.x_edge = edges[x_edge]
+    p.y_edge = edges[y_edge]
+    p.t_x_lo, p.t_x_hi, p.t_y_lo, p.t_y_hi = t_x_lo, t_x_hi, t_y_lo, t_y_hi
+    p.tile_x, p.rows_per_thread, p.sched_chunk = tile_x, rows_per_thread, sched_chunk
+    return p
