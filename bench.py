@@ -59,7 +59,7 @@ def recorded_traffic():
         return None
 
 
-def run_gpu(nx, ny, q, mfp, steps, warmup, edges, tile_x=0, rows=0, seed=1911):
+def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911):
     import numpy as np
     import torch
 
@@ -68,8 +68,7 @@ def run_gpu(nx, ny, q, mfp, steps, warmup, edges, tile_x=0, rows=0, seed=1911):
 
     x0, y0 = inputs.seeded_center(seed, nx, ny)
     T0 = inputs.gaussian_pulse(nx, ny, 16.0, x0, y0).astype(np.float32)
-    lat = Lattice(nx, ny, q, mfp=mfp, device="cuda:0", tile_x=tile_x, rows_per_thread=rows,
-                  **edges)
+    lat = Lattice(nx, ny, q, mfp=mfp, device="cuda:0", dir_split=split, **edges)
     lat.set_temperature(torch.from_numpy(T0))
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -128,8 +127,8 @@ def main():
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--kn", type=float, default=0.1, help="Knudsen number vs L = 1024")
-    ap.add_argument("--tile-x", type=int, default=0)
-    ap.add_argument("--rows", type=int, default=0)
+    ap.add_argument("--split", type=int, default=0,
+                    help="waves sharing one cell's directions (0 = library default)")
     ap.add_argument("--large", action="store_true",
                     help="also time the 4096 x 4096, Q = 256 wall-bounded lattice")
     ap.add_argument("--large-steps", type=int, default=200)
@@ -163,8 +162,7 @@ def main():
     nx = ny = 1024
     q = 64
     mfp = args.kn * nx
-    ms, wall, energy = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.tile_x,
-                               args.rows)
+    ms, wall, energy = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.split)
     updates = nx * ny * q * args.steps
     gups = updates / (ms * 1e-3) / 1e9
     ms_step = ms / args.steps

@@ -74,7 +74,8 @@ enum {
 };
 
 typedef struct wlbm_params {
-  int32_t nx, ny;            /* lattice size, 1 .. 2^20 each, nx*ny*q < 2^40     */
+  int32_t nx, ny;            /* lattice size, 1 .. 2^20 each; 8 padded planes    */
+                             /* of (nx+64)*(ny+2) floats must fit in 4 GiB       */
   int32_t q;                 /* number of directions, multiple of 8, 8 .. 1024   */
   int32_t dirs;              /* WLBM_DIRS_*                                      */
   double mfp_cells;          /* uniform MFP in cells (> 0; +inf gives W = 0)     */
@@ -83,10 +84,10 @@ typedef struct wlbm_params {
   int32_t x_edge, y_edge;    /* WLBM_EDGE_*                                      */
   double t_x_lo, t_x_hi;     /* blackbody temperatures at x = 0 and x = nx-1     */
   double t_y_lo, t_y_hi;     /* blackbody temperatures at y = 0 and y = ny-1     */
-  int32_t tile_x;            /* kernel tile width: 0 (auto), 64, 128 or 256      */
-  int32_t rows_per_thread;   /* kernel rows per thread: 0 (auto), 1, 2, 4 or 8   */
+  int32_t dir_split;         /* waves sharing one cell's directions: 0 (auto),   */
+                             /* 1, 2 or 4; q must be a multiple of 8*dir_split   */
   int32_t sched_chunk;       /* steps per schedule upload: 0 (auto) or 16..65536 */
-  int32_t reserved[5];       /* must be zero                                     */
+  int32_t reserved[6];       /* must be zero                                     */
 } wlbm_params;
 
 /* Fill *p with defaults: 64 x 64, q = 16, uniform directions, MFP 16, f = 1,

@@ -162,6 +162,9 @@ def weights(dirs: list[Direction]) -> np.ndarray:
     directions get w = 1/Q, the uniform case of Sec. 2.2.
     """
     q = len(dirs)
+    if all(d.ring_vec is None for d in dirs):
+        # evenly spaced: every gap is 2 pi / Q, so w_j = 1/Q exactly
+        return np.full(q, 1.0 / q)
     phi = [d.angle for d in dirs]
     w = np.empty(q)
     for j in range(q):

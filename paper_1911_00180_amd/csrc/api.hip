@@ -103,22 +103,25 @@ wlbm_status validate(const wlbm_params* p) {
   if (p->emulate_3d != 0 && p->emulate_3d != 1) return fail(WLBM_EINVAL, "emulate_3d is 0 or 1");
   if (p->mfp_correction != 0 && p->mfp_correction != 1)
     return fail(WLBM_EINVAL, "mfp_correction is 0 or 1");
-  if (p->tile_x != 0 && p->tile_x != 64 && p->tile_x != 128 && p->tile_x != 256)
-    return fail(WLBM_EINVAL, "tile_x must be 0, 64, 128 or 256");
-  if (p->rows_per_thread != 0 && p->rows_per_thread != 1 && p->rows_per_thread != 2 &&
-      p->rows_per_thread != 4 && p->rows_per_thread != 8)
-    return fail(WLBM_EINVAL, "rows_per_thread must be 0, 1, 2, 4 or 8");
+  if (p->dir_split != 0 && p->dir_split != 1 && p->dir_split != 2 && p->dir_split != 4)
+    return fail(WLBM_EINVAL, "dir_split must be 0, 1, 2 or 4");
+  if (p->dir_split && p->q % (kMaxGroupPlanes * p->dir_split) != 0)
+    return fail(WLBM_EINVAL, "q = %d cannot be split over %d waves (needs a multiple of %d)",
+                p->q, p->dir_split, kMaxGroupPlanes * p->dir_split);
   if (p->sched_chunk != 0 && (p->sched_chunk < 16 || p->sched_chunk > 65536))
     return fail(WLBM_EINVAL, "sched_chunk must be 0 or 16..65536");
-  for (int k = 0; k < 5; ++k)
+  for (int k = 0; k < 6; ++k)
     if (p->reserved[k] != 0) return fail(WLBM_EINVAL, "reserved fields must be zero");
   if (!std::isfinite(p->t_x_lo) || !std::isfinite(p->t_x_hi) || !std::isfinite(p->t_y_lo) ||
       !std::isfinite(p->t_y_hi))
     return fail(WLBM_EINVAL, "wall temperatures must be finite");
-  // 32-bit byte offsets inside one plane
-  if ((padded_plane(p->nx, p->ny) + 2 * (padded_pitch(p->nx) + 1)) * int64_t(sizeof(float)) >=
+  // 32-bit byte offsets inside one group of direction planes
+  if ((kMaxGroupPlanes * padded_plane(p->nx, p->ny) + 2 * (padded_pitch(p->nx) + 1)) *
+          int64_t(sizeof(float)) >=
       (int64_t(1) << 32))
-    return fail(WLBM_EINVAL, "lattice too large: one padded plane must stay below 4 GiB");
+    return fail(WLBM_EINVAL,
+                "lattice too large: %d padded planes must stay below 4 GiB (nx*ny up to about "
+                "1.3e8 cells)", kMaxGroupPlanes);
   return WLBM_OK;
 }
 
@@ -141,7 +144,7 @@ struct wlbm_lattice {
   int cur = 0;              // population buffer holding the current state
   float W = 0.f;            // uniform corrected weight
   bool per_cell = false;    // per-cell weight field active
-  int tile_x = 64, rows = 4;
+  int split = 1;            // waves sharing the directions of one cell
   int chunk = kDefaultChunk;
   uint8_t* pinned[2] = {nullptr, nullptr};
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -163,19 +166,16 @@ wlbm_status check_lat(const wlbm_lattice* l) {
   return WLBM_OK;
 }
 
-void auto_tiling(wlbm_lattice* l) {
-  l->tile_x = l->p.tile_x ? l->p.tile_x : 64;
-  l->rows = l->p.rows_per_thread ? l->p.rows_per_thread : 4;
-  // a narrow lattice wastes lanes on wide tiles
-  if (!l->p.tile_x) {
-    if (l->p.nx >= 1024) l->tile_x = 64;
-    if (l->p.nx <= 64) l->tile_x = 64;
-  }
-  if (!l->p.rows_per_thread) {
-    const int ty = (kBlock / l->tile_x);
-    if (l->p.ny < ty * 4) l->rows = 1;
-  }
+// Default direction split: as many waves per cell as q allows (up to four),
+// which keeps waves short-lived; measured best on 1024^2 x 64 and
+// 4096^2 x 256 lattices.
+int auto_split(int q) {
+  if (q % (4 * kMaxGroupPlanes) == 0) return 4;
+  if (q % (2 * kMaxGroupPlanes) == 0) return 2;
+  return 1;
 }
+
+void auto_tiling(wlbm_lattice* l) { l->split = l->p.dir_split ? l->p.dir_split : auto_split(l->p.q); }
 
 }  // namespace
 
@@ -457,8 +457,8 @@ wlbm_status wlbm_step(wlbm_lattice* l, int64_t nsteps) {
   a.plane = l->g.plane;
   a.x_edge = l->g.x_edge;
   a.y_edge = l->g.y_edge;
-  a.tiles_x = tiles_x_for(l->g.nx, l->tile_x);
-  a.ntiles = a.tiles_x * tiles_y_for(l->g.ny, l->tile_x, l->rows);
+  a.tiles_x = tiles_x_for(l->g.nx);
+  a.ntiles = a.tiles_x * tiles_y_for(l->g.ny, l->split);
 
   int64_t done = 0;
   while (done < nsteps) {
@@ -516,7 +516,7 @@ wlbm_status wlbm_step(wlbm_lattice* l, int64_t nsteps) {
       a.E_in = l->ptr(l->c.E[l->cur]);
       a.E_out = l->ptr(l->c.E[1 - l->cur]);
       a.q_first = (flux && k == flux_from) ? 1 : 0;
-      e = launch_step(a, l->tile_x, l->rows, l->per_cell, flux, l->stream);
+      e = launch_step(a, l->split, l->per_cell, flux, l->stream);
       if (e != hipSuccess) {
         l->broken = true;
         return fail(WLBM_EHIP, "step kernel launch failed: %s", hipGetErrorString(e));

@@ -65,13 +65,17 @@ struct Walls {
   float x_lo, x_hi, y_lo, y_hi;
 };
 
-// Collide-and-stream of one time step.  tile_x in {64, 128, 256}, rows in
-// {1, 2, 4, 8}; per_cell selects the per-cell weight field; flux accumulates
-// the heat flux into qsx/qsy.
-hipError_t launch_step(const StepArgs& a, int tile_x, int rows, bool per_cell, bool flux,
-                       hipStream_t s);
-int tiles_x_for(int nx, int tile_x);
-int tiles_y_for(int ny, int tile_x, int rows);
+// Collide-and-stream of one time step.  Tiles are 64 cells wide and
+// 4 / split rows tall; the directions of each cell are split over `split`
+// waves (1, 2 or 4; q must be a multiple of 8 * split).  per_cell selects the
+// per-cell weight field; flux accumulates the heat flux into qsx/qsy.  The
+// kernel addresses a batch of kMaxGroupPlanes consecutive direction planes
+// through one buffer descriptor, so that many planes (plus one row and
+// column) must fit in 4 GiB.
+constexpr int kMaxGroupPlanes = 8;
+hipError_t launch_step(const StepArgs& a, int split, bool per_cell, bool flux, hipStream_t s);
+int tiles_x_for(int nx);
+int tiles_y_for(int ny, int split);
 
 // e_i = w_i T0 (T0 unpadded [ny][nx]), blackbody walls, E, ghosts.
 hipError_t launch_init_temperature(const Geometry& g, const float* T0, float* e, float* E,

@@ -47,11 +47,12 @@ __device__ __forceinline__ rsrc_t make_rsrc(const float* p, uint32_t bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(p), (short)0, (int)bytes,
                                            kRsrcWord3);
 }
+// The b32 builtins move 32-bit words; reinterpret (never convert) them.
 __device__ __forceinline__ float buf_load(rsrc_t r, uint32_t voff, uint32_t soff) {
-  return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
-__device__ __forceinline__ void buf_store(float v, rsrc_t r, uint32_t voff) {
-  __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, 0, 0);
+__device__ __forceinline__ void buf_store(float v, rsrc_t r, uint32_t voff, uint32_t soff = 0) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
 }
 
 // Tables that every lane reads at the same index (schedule codes, weights,
@@ -107,13 +108,20 @@ __device__ __forceinline__ void decode(uint32_t code, int& dx, int& dy, bool& ho
   hop = (code >> 4) & 1u;
 }
 
-template <int TX, int R>
+// One kernel block is four waves.  Its tile is 64 cells wide (one wave) and
+// 4 / NW rows tall; the Q directions of each cell are split over NW waves,
+// each taking Q / NW of them in batches of D.  Splitting keeps every wave
+// short-lived, so the grid holds many waves and the drain at the end of a
+// launch is short; the NW partial sums of E' are added in LDS in a fixed
+// order, so results do not depend on timing.
+template <int NW>
 struct TileShape {
-  static constexpr int TR = kBlock / TX;  // thread rows per block
-  static constexpr int TY = TR * R;       // tile height in cells
-  static constexpr int LP = TX + 2;       // LDS row pitch (one halo column each side)
-  static constexpr int LH = TY + 2;       // LDS rows (one halo row each side)
-  static constexpr int D = R >= 4 ? 4 : 8;  // directions per load group (D*R loads in flight)
+  static constexpr int TX = 64;          // tile width in cells (one wave)
+  static constexpr int TY = 4 / NW;      // tile height in cells
+  static constexpr int LP = TX + 2;      // LDS row pitch (one halo column each side)
+  static constexpr int LH = TY + 2;      // LDS rows (one halo row each side)
+  static constexpr int D = kMaxGroupPlanes;  // directions per load batch
+  static_assert(NW == 1 || NW == 2 || NW == 4, "direction split of 1, 2 or 4 waves");
 };
 
 // Boundary node of a diffuse wall (Sec. 2.6, Eq. adiabatic-diffuse): the node
@@ -164,63 +172,74 @@ __device__ void boundary_node(const StepArgs& a, int wall, int X, float& tg, flo
   wtg = Wg * tg;
 }
 
-// The per-cell sweep over all directions.  EDGE tiles touch a domain edge or
-// are ragged: they mask cells outside the lattice, apply the wall
-// conditions and write the ghost copies of periodic edges.  Interior tiles
-// need none of that: every source cell of a pull lies inside the padded
-// arrays, with no wrap arithmetic.
-template <int TX, int R, bool WF, bool FLUX, bool EDGE>
+// Load the populations of directions i0 .. i0+D-1 that stream into the cell
+// at byte offset boff: the DDED of direction i comes from the cell one
+// pending worm move back on a hop and from the cell itself on a pause.  One
+// buffer descriptor covers the batch (direction d is d planes further on)
+// plus one row and column either side, so the shifted offset stays positive.
+template <int D>
+__device__ __forceinline__ void load_batch(const StepArgs& a, int i0, uint32_t boff,
+                                           float (&v)[D]) {
+  const WLBM_CONST uint32_t* codes = scalar_ptr(a.codes);
+  const int pitch = a.pitch;
+  const long long plane = a.plane;
+  const uint32_t win_bytes = uint32_t((D * plane + 2 * (pitch + 1)) * 4);
+  const uint32_t plane_bytes = uint32_t(plane * 4);
+  uint32_t words[D / 4];
+#pragma unroll
+  for (int k = 0; k < D / 4; ++k) words[k] = codes[(i0 >> 2) + k];
+  const rsrc_t rs = make_rsrc(a.e_in + (long long)i0 * plane - (pitch + 1), win_bytes);
+#pragma unroll
+  for (int d = 0; d < D; ++d) {
+    int dx, dy;
+    bool hop;
+    decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
+    const int sh = hop ? dy * pitch + dx : 0;
+    v[d] = buf_load(rs, boff, uint32_t(d * plane_bytes + (pitch + 1 - sh) * 4));
+  }
+}
+
+// The sweep of one wave over its share of the directions for one cell per
+// lane.  EDGE tiles touch a domain edge or are ragged: they mask cells
+// outside the lattice, apply the wall conditions and write the ghost copies
+// of periodic edges.  Interior tiles need none of that: every source cell of
+// a pull lies inside the padded arrays, with no wrap arithmetic.
+template <int NW, bool WF, bool FLUX, bool EDGE>
 __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const float* sW,
-                                      const float* sTg, const float* sWTg, int x0, int y0) {
-  using T = TileShape<TX, R>;
+                                      const float* sTg, const float* sWTg, float* sRed, int x0,
+                                      int y0, uint32_t boff, const float (&v0)[TileShape<NW>::D]) {
+  using T = TileShape<NW>;
   constexpr int D = T::D;
   const WLBM_CONST uint32_t* codes = scalar_ptr(a.codes);
   const WLBM_CONST float* wtab = scalar_ptr(a.wtab);
   const WLBM_CONST float* sxtab = scalar_ptr(a.sxtab);
   const WLBM_CONST float* sytab = scalar_ptr(a.sytab);
-  const int lx = threadIdx.x % TX;
-  const int ly = threadIdx.x / TX;
-  const int x = x0 + lx;
-  const int yb = y0 + ly * R;
+  const int lane = threadIdx.x & 63;
+  // wave-uniform values, kept in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int row = wave / NW;       // cell row of this wave inside the tile
+  const int part = wave % NW;      // which share of the directions
+  const int x = x0 + lane;
+  const int y = y0 + row;
   const bool px = a.x_edge == kPeriodic;
   const bool py = a.y_edge == kPeriodic;
   const int pitch = a.pitch;
   const long long plane = a.plane;
-  // source window of a direction: its plane plus one row and column either
-  // side, so that the shifted offset below is never negative
-  const uint32_t win_bytes = uint32_t((plane + 2 * (pitch + 1)) * 4);
   const uint32_t plane_bytes = uint32_t(plane * 4);
+  const uint32_t batch_bytes = uint32_t(D * plane * 4);
 
-  uint32_t boff[R];
-  bool ok[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    ok[r] = !EDGE || (x < a.nx && yb + r < a.ny);
-    // lanes outside a ragged lattice read a valid cell and store nothing
-    boff[r] = uint32_t(cell(ok[r] ? x : 0, ok[r] ? yb + r : 0, pitch) * 4);
-  }
-  const int lc = (ly * R + 1) * T::LP + lx + 1;
+  const bool ok = !EDGE || (x < a.nx && y < a.ny);
+  const int lc = (row + 1) * T::LP + lane + 1;
+  const bool ghost = EDGE && ok && ((px && (x == 0 || x == a.nx - 1)) ||
+                                    (py && (y == 0 || y == a.ny - 1)));
 
-  float Eacc[R], qx[R], qy[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) Eacc[r] = qx[r] = qy[r] = 0.f;
-
-  for (int i0 = 0; i0 < a.q; i0 += D) {
+  float Eacc = 0.f, qx = 0.f, qy = 0.f;
+  const int share = a.q / NW;
+  auto relax_batch = [&](int i0, const float (&v)[D]) {
     uint32_t words[D / 4];
 #pragma unroll
     for (int k = 0; k < D / 4; ++k) words[k] = codes[(i0 >> 2) + k];
-    float v[D][R];
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-      int dx, dy;
-      bool hop;
-      decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
-      const int sh = hop ? dy * pitch + dx : 0;
-      const rsrc_t rs = make_rsrc(a.e_in + (long long)(i0 + d) * plane - (pitch + 1), win_bytes);
-      const uint32_t soff = uint32_t((pitch + 1 - sh) * 4);
-#pragma unroll
-      for (int r = 0; r < R; ++r) v[d][r] = buf_load(rs, boff[r], soff);
-    }
+    const rsrc_t ro = make_rsrc(a.e_out + (long long)i0 * plane, batch_bytes);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int i = i0 + d;
@@ -228,84 +247,119 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
       bool hop;
       decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
       const float wi = wtab[i];
-      const rsrc_t ro = make_rsrc(a.e_out + (long long)i * plane, plane_bytes);
       const int ls = lc - (dy * T::LP + dx);
-      const int lh = hop ? ls : lc;
+      const float e = v[d];
+      const float Es = sE[ls];
+      float out;
+      if constexpr (!WF) {
+        // e + W (w_i E - e): the rounding error stays relative to the
+        // (small) change, so a nearly ballistic run does not drift
+        out = fmaf(a.W, fmaf(wi, Es, -e), e);
+      } else {
+        // sE holds W E; sW holds W of each cell
+        const float Wh = sW[hop ? ls : lc];
+        out = e + fmaf(wi, Es, -(Wh * e));
+      }
+      if constexpr (EDGE) {
+        if (!ok) continue;
+        if (a.y_edge == kDiffuse) {
+          if (y == 0 && dy == 1) out = fmaf(wi, (hop ? sTg : sWTg)[lane + 1 - dx], out);
+          if (y == a.ny - 1 && dy == -1)
+            out = fmaf(wi, (hop ? sTg : sWTg)[T::LP + lane + 1 - dx], out);
+        }
+        out = blackbody(out, wi, x, y, a.nx, a.ny, a.x_edge, a.y_edge, a.t_x_lo, a.t_x_hi,
+                        a.t_y_lo, a.t_y_hi);
+        if (ghost)
+          store_ghosted(a.e_out + (long long)i * plane, x, y, out, a.nx, a.ny, pitch, px, py);
+        else
+          buf_store(out, ro, boff, d * plane_bytes);
+      } else {
+        buf_store(out, ro, boff, d * plane_bytes);
+      }
+      Eacc += out;
+      if constexpr (FLUX) {
+        qx = fmaf(out, sxtab[i], qx);
+        qy = fmaf(out, sytab[i], qy);
+      }
+    }
+  };
+  // the first batch was loaded before the E tile was staged
+  relax_batch(part * share, v0);
+  for (int i0 = part * share + D; i0 < (part + 1) * share; i0 += D) {
+    float v[D];
+    load_batch<D>(a, i0, boff, v);
+    relax_batch(i0, v);
+  }
+
+  if constexpr (NW > 1) {
+    // partial sums of the NW waves of a row, added in a fixed order
+    constexpr int n = T::TY * 64;
+    const int slot = (part * T::TY + row) * 64 + lane;
+    sRed[slot] = Eacc;
+    if constexpr (FLUX) {
+      sRed[NW * n + slot] = qx;
+      sRed[2 * NW * n + slot] = qy;
+    }
+    __syncthreads();
+    if (part != 0) return;
+    const int base = row * 64 + lane;
+    Eacc = sRed[base];
+    if constexpr (FLUX) {
+      qx = sRed[NW * n + base];
+      qy = sRed[2 * NW * n + base];
+    }
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const float e = v[d][r];
-        const float Es = sE[ls + r * T::LP];
-        float out;
-        if constexpr (!WF) {
-          // e + W (w_i E - e): the rounding error stays relative to the
-          // (small) change, so a nearly ballistic run does not drift
-          out = fmaf(a.W, fmaf(wi, Es, -e), e);
-        } else {
-          // sE holds W E; sW holds W of each cell
-          const float Wh = sW[lh + r * T::LP];
-          out = e + fmaf(wi, Es, -(Wh * e));
-        }
-        if constexpr (EDGE) {
-          if (!ok[r]) continue;
-          const int y = yb + r;
-          if (a.y_edge == kDiffuse) {
-            if (y == 0 && dy == 1) out = fmaf(wi, (hop ? sTg : sWTg)[lx + 1 - dx], out);
-            if (y == a.ny - 1 && dy == -1)
-              out = fmaf(wi, (hop ? sTg : sWTg)[T::LP + lx + 1 - dx], out);
-          }
-          out = blackbody(out, wi, x, y, a.nx, a.ny, a.x_edge, a.y_edge, a.t_x_lo, a.t_x_hi,
-                          a.t_y_lo, a.t_y_hi);
-          if ((px && (x == 0 || x == a.nx - 1)) || (py && (y == 0 || y == a.ny - 1)))
-            store_ghosted(a.e_out + (long long)i * plane, x, y, out, a.nx, a.ny, pitch, px, py);
-          else
-            buf_store(out, ro, boff[r]);
-        } else {
-          buf_store(out, ro, boff[r]);
-        }
-        Eacc[r] += out;
-        if constexpr (FLUX) {
-          qx[r] = fmaf(out, sxtab[i], qx[r]);
-          qy[r] = fmaf(out, sytab[i], qy[r]);
-        }
+    for (int k = 1; k < NW; ++k) {
+      Eacc += sRed[k * n + base];
+      if constexpr (FLUX) {
+        qx += sRed[NW * n + k * n + base];
+        qy += sRed[2 * NW * n + k * n + base];
       }
     }
   }
-
-  const rsrc_t rE = make_rsrc(a.E_out, plane_bytes);
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    if (EDGE && !ok[r]) continue;
-    const int y = yb + r;
-    if (EDGE && ((px && (x == 0 || x == a.nx - 1)) || (py && (y == 0 || y == a.ny - 1))))
-      store_ghosted(a.E_out, x, y, Eacc[r], a.nx, a.ny, pitch, px, py);
-    else
-      buf_store(Eacc[r], rE, boff[r]);
-    if constexpr (FLUX) {
-      const long long o = (long long)y * a.nx + x;
-      if (a.q_first) {
-        a.qsx[o] = qx[r];
-        a.qsy[o] = qy[r];
-      } else {
-        a.qsx[o] += qx[r];
-        a.qsy[o] += qy[r];
-      }
+  if (!ok) return;
+  if (ghost)
+    store_ghosted(a.E_out, x, y, Eacc, a.nx, a.ny, pitch, px, py);
+  else
+    buf_store(Eacc, make_rsrc(a.E_out, plane_bytes), boff);
+  if constexpr (FLUX) {
+    const long long o = (long long)y * a.nx + x;
+    if (a.q_first) {
+      a.qsx[o] = qx;
+      a.qsy[o] = qy;
+    } else {
+      a.qsx[o] += qx;
+      a.qsy[o] += qy;
     }
   }
 }
 
-template <int TX, int R, bool WF, bool FLUX>
-__global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
-  using T = TileShape<TX, R>;
+template <int NW, bool WF, bool FLUX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_step(
+    const StepArgs a) {
+  using T = TileShape<NW>;
   __shared__ float sE[T::LH * T::LP];
   __shared__ float sW[WF ? T::LH * T::LP : 1];
   __shared__ float sTg[2 * T::LP];
   __shared__ float sWTg[2 * T::LP];
+  __shared__ float sRed[NW > 1 ? (FLUX ? 3 : 1) * kBlock : 1];
 
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   const int tx = t % a.tiles_x;
   const int ty = t / a.tiles_x;
-  const int x0 = tx * TX;
+  const int x0 = tx * T::TX;
   const int y0 = ty * T::TY;
+
+  // This thread's cell, and the first batch of its directions, loaded before
+  // the E tile so that both memory round trips overlap.  Lanes outside a
+  // ragged lattice read a valid cell and store nothing.
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int cx = x0 + (threadIdx.x & 63);
+  const int cy = y0 + wave / NW;
+  const bool inside = cx < a.nx && cy < a.ny;
+  const uint32_t boff = uint32_t(cell(inside ? cx : 0, inside ? cy : 0, a.pitch) * 4);
+  float v0[T::D];
+  load_batch<T::D>(a, (wave % NW) * (a.q / NW), boff, v0);
 
   // Stage E (per-cell mode: W E) and W of the tile plus a one-cell halo.
   // Ghost rows/columns give the wrapped values of periodic edges and zero
@@ -327,7 +381,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
     sE[k] = ev;
     if constexpr (WF) sW[k] = wv;
   }
-  const bool edge = x0 == 0 || x0 + TX >= a.nx || y0 == 0 || y0 + T::TY >= a.ny;
+  const bool edge = x0 == 0 || x0 + T::TX >= a.nx || y0 == 0 || y0 + T::TY >= a.ny;
   if (edge && a.y_edge == kDiffuse) {
     const bool lo = y0 == 0;
     const bool hi = a.ny - 1 < y0 + T::TY;
@@ -342,32 +396,21 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs a) {
   }
   __syncthreads();
   if (edge)
-    sweep<TX, R, WF, FLUX, true>(a, sE, sW, sTg, sWTg, x0, y0);
+    sweep<NW, WF, FLUX, true>(a, sE, sW, sTg, sWTg, sRed, x0, y0, boff, v0);
   else
-    sweep<TX, R, WF, FLUX, false>(a, sE, sW, sTg, sWTg, x0, y0);
+    sweep<NW, WF, FLUX, false>(a, sE, sW, sTg, sWTg, sRed, x0, y0, boff, v0);
 }
 
-template <int TX, int R, bool WF, bool FLUX>
+template <int NW, bool WF, bool FLUX>
 hipError_t launch_tmpl(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_step<TX, R, WF, FLUX>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((k_step<NW, WF, FLUX>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 
-template <int TX, int R>
-hipError_t launch_tr(const StepArgs& a, bool wf, bool fl, hipStream_t s) {
-  if (wf) return fl ? launch_tmpl<TX, R, true, true>(a, s) : launch_tmpl<TX, R, true, false>(a, s);
-  return fl ? launch_tmpl<TX, R, false, true>(a, s) : launch_tmpl<TX, R, false, false>(a, s);
-}
-
-template <int TX>
-hipError_t launch_t(const StepArgs& a, int rows, bool wf, bool fl, hipStream_t s) {
-  switch (rows) {
-    case 1: return launch_tr<TX, 1>(a, wf, fl, s);
-    case 2: return launch_tr<TX, 2>(a, wf, fl, s);
-    case 4: return launch_tr<TX, 4>(a, wf, fl, s);
-    case 8: return launch_tr<TX, 8>(a, wf, fl, s);
-    default: return hipErrorInvalidValue;
-  }
+template <int NW>
+hipError_t launch_nw(const StepArgs& a, bool wf, bool fl, hipStream_t s) {
+  if (wf) return fl ? launch_tmpl<NW, true, true>(a, s) : launch_tmpl<NW, true, false>(a, s);
+  return fl ? launch_tmpl<NW, false, true>(a, s) : launch_tmpl<NW, false, false>(a, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -546,18 +589,17 @@ unsigned cell_blocks(const Geometry& g) {
 
 }  // namespace
 
-int tiles_x_for(int nx, int tile_x) { return (nx + tile_x - 1) / tile_x; }
-int tiles_y_for(int ny, int tile_x, int rows) {
-  const int ty = (kBlock / tile_x) * rows;
+int tiles_x_for(int nx) { return (nx + 63) / 64; }
+int tiles_y_for(int ny, int split) {
+  const int ty = 4 / split;
   return (ny + ty - 1) / ty;
 }
 
-hipError_t launch_step(const StepArgs& a, int tile_x, int rows, bool per_cell, bool flux,
-                       hipStream_t s) {
-  switch (tile_x) {
-    case 64: return launch_t<64>(a, rows, per_cell, flux, s);
-    case 128: return launch_t<128>(a, rows, per_cell, flux, s);
-    case 256: return launch_t<256>(a, rows, per_cell, flux, s);
+hipError_t launch_step(const StepArgs& a, int split, bool per_cell, bool flux, hipStream_t s) {
+  switch (split) {
+    case 1: return launch_nw<1>(a, per_cell, flux, s);
+    case 2: return launch_nw<2>(a, per_cell, flux, s);
+    case 4: return launch_nw<4>(a, per_cell, flux, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -13,7 +13,8 @@ import os
 from ctypes import POINTER, byref, c_char_p, c_double, c_int, c_int8, c_int32, c_int64, \
     c_size_t, c_void_p
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwormlbm.so")
+LIB_PATH = os.environ.get(
+    "WORMLBM_LIB", os.path.join(os.path.dirname(os.path.abspath(__file__)), "libwormlbm.so"))
 
 WLBM_OK = 0
 WLBM_EINVAL = -1
@@ -48,8 +49,8 @@ class WlbmParams(ctypes.Structure):
         ("emulate_3d", c_int32), ("mfp_correction", c_int32),
         ("x_edge", c_int32), ("y_edge", c_int32),
         ("t_x_lo", c_double), ("t_x_hi", c_double), ("t_y_lo", c_double), ("t_y_hi", c_double),
-        ("tile_x", c_int32), ("rows_per_thread", c_int32), ("sched_chunk", c_int32),
-        ("reserved", c_int32 * 5),
+        ("dir_split", c_int32), ("sched_chunk", c_int32),
+        ("reserved", c_int32 * 6),
     ]
 
 
@@ -229,7 +230,7 @@ def make_params(nx: int, ny: int, q: int, mfp: float = float("inf"), dirs: str =
                 emulate_3d: bool = False, mfp_correction: bool = True,
                 x_edge: str = "periodic", y_edge: str = "periodic",
                 t_x_lo: float = 0.0, t_x_hi: float = 0.0, t_y_lo: float = 0.0,
-                t_y_hi: float = 0.0, tile_x: int = 0, rows_per_thread: int = 0,
+                t_y_hi: float = 0.0, dir_split: int = 0,
                 sched_chunk: int = 0) -> WlbmParams:
     """Parameters from keyword arguments (edge and direction names as strings)."""
     edges = {"periodic": EDGE_PERIODIC, "blackbody": EDGE_BLACKBODY, "diffuse": EDGE_DIFFUSE}
@@ -242,5 +243,5 @@ def make_params(nx: int, ny: int, q: int, mfp: float = float("inf"), dirs: str =
     p.x_edge = edges[x_edge]
     p.y_edge = edges[y_edge]
     p.t_x_lo, p.t_x_hi, p.t_y_lo, p.t_y_hi = t_x_lo, t_x_hi, t_y_lo, t_y_hi
-    p.tile_x, p.rows_per_thread, p.sched_chunk = tile_x, rows_per_thread, sched_chunk
+    p.dir_split, p.sched_chunk = dir_split, sched_chunk
     return p

@@ -96,6 +96,10 @@ def pin_weights(o):
         for kind in ("uniform", "ring"):
             assert abs(math.fsum(o.weights(o.make_directions(q, kind))) - 1.0) < 1e-14
         assert np.allclose(o.weights(o.make_directions(q, "uniform")), 1.0 / q, rtol=0, atol=1e-15)
+        # the gap rule itself gives 1/Q for evenly spaced directions
+        phi = [2.0 * math.pi * i / q for i in range(q)] + [2.0 * math.pi]
+        gap = [phi[j + 1] - phi[j] for j in range(q)]
+        assert max(abs((gap[j - 1] + gap[j]) / (4 * math.pi) - 1.0 / q) for j in range(q)) < 1e-15
 
 
 # -- Sec. 2.3 Eq. W-correction-factor and its generalisation in Sec. 2.4 ------

@@ -64,7 +64,7 @@ def test_directions_and_constants_against_oracle(q, kind):
     ("nx", 0, W.WLBM_EINVAL), ("ny", -3, W.WLBM_EINVAL), ("x_edge", 2, W.WLBM_EINVAL),
     ("y_edge", 7, W.WLBM_EINVAL), ("mfp_cells", 0.0, W.WLBM_EINVAL),
     ("mfp_cells", float("nan"), W.WLBM_EINVAL), ("mfp_cells", 0.5, W.WLBM_EUNSTABLE),
-    ("tile_x", 96, W.WLBM_EINVAL), ("rows_per_thread", 3, W.WLBM_EINVAL),
+    ("dir_split", 3, W.WLBM_EINVAL), ("dir_split", 8, W.WLBM_EINVAL),
     ("sched_chunk", 5, W.WLBM_EINVAL), ("t_x_lo", float("inf"), W.WLBM_EINVAL),
     ("dirs", 5, W.WLBM_EINVAL), ("emulate_3d", 2, W.WLBM_EINVAL),
 ])
@@ -117,4 +117,21 @@ def test_create_rejects_bad_workspace_without_touching_the_gpu():
     assert ei.value.status == W.WLBM_ENOMEM
     with pytest.raises(W.WormLBMError) as ei:
         W.wlbm_create(p, 256 * 1024 + 4, 1 << 30, 0)
+    assert ei.value.status == W.WLBM_EINVAL
+
+
+def test_size_limit_of_one_direction_group():
+    """Eight padded direction planes are addressed through one 32-bit buffer
+    window: 11000^2 fits, 12000^2 is rejected with a clear error."""
+    W.wlbm_workspace_bytes(W.make_params(11000, 11000, 8, mfp=50.0))
+    with pytest.raises(W.WormLBMError) as ei:
+        W.wlbm_workspace_bytes(W.make_params(12000, 12000, 8, mfp=50.0))
+    assert ei.value.status == W.WLBM_EINVAL
+    assert "too large" in W.wlbm_last_error()
+
+
+def test_direction_split_needs_divisible_q():
+    W.wlbm_workspace_bytes(W.make_params(64, 64, 32, mfp=8.0, dir_split=4))
+    with pytest.raises(W.WormLBMError) as ei:
+        W.wlbm_workspace_bytes(W.make_params(64, 64, 24, mfp=8.0, dir_split=2))
     assert ei.value.status == W.WLBM_EINVAL

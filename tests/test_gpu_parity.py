@@ -2,7 +2,9 @@
 
 Tolerances: the worm/TAS schedule and W = 0 (pure advection) runs are
 bit-exact; otherwise the FP32 fields must satisfy
-max|x32 - x64| <= 1e-5 * max|x64| (temperature, heat flux, populations).
+max|x32 - x64| <= 1e-5 * max|x64| (temperature, populations).  The heat flux
+is a sum of terms of either sign that can cancel to far below their own size
+(|q| <= v_g T), so its error is measured against max|T64|.
 """
 import math
 
@@ -68,7 +70,7 @@ def test_c1_gaussian_64x64_q16():
     assert _rel(lat.temperature().cpu().numpy(), ora.temperature()) <= RTOL
     qx, qy = lat.heat_flux()
     oqx, oqy = ora.heat_flux()
-    scale = max(np.abs(oqx).max(), np.abs(oqy).max())
+    scale = np.abs(ora.temperature()).max()
     assert np.abs(qx.cpu().numpy() - oqx).max() <= RTOL * scale
     assert np.abs(qy.cpu().numpy() - oqy).max() <= RTOL * scale
     e, sqx, sqy = lat.totals()
@@ -110,15 +112,29 @@ def test_walls_ragged(edges, kind, q):
     assert _rel(lat.temperature().cpu().numpy(), ora.temperature()) <= RTOL
 
 
-@pytest.mark.parametrize("tile_x", [64, 128, 256])
-@pytest.mark.parametrize("rows", [1, 2, 4, 8])
-def test_tilings_agree(tile_x, rows):
-    """All kernel tilings give the oracle's answer on a wall-bounded lattice."""
-    nx, ny, q = 300, 70, 16
+@pytest.mark.parametrize("split", [1, 2, 4])
+@pytest.mark.parametrize("edges", [dict(x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0),
+                                   dict(x_edge="periodic", y_edge="periodic")],
+                         ids=["walls", "periodic"])
+def test_direction_splits_agree(split, edges):
+    """Every split of the directions over waves gives the oracle's answer
+    (and the flux window, which is summed across the split, too)."""
+    nx, ny, q = 300, 70, 32
     e0 = inputs.random_populations(3, q, ny, nx)
-    edges = dict(x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0, t_x_hi=0.0)
-    lat, ora = _run_pair(nx, ny, q, 6.0, 40, e0=e0, tile_x=tile_x, rows_per_thread=rows, **edges)
+    lat = _lattice(nx=nx, ny=ny, q=q, mfp=6.0, dir_split=split, **edges)
+    ora = _oracle(nx, ny, q, 6.0, **edges)
+    lat.set_populations(torch.from_numpy(e0))
+    ora.set_populations(e0.astype(np.float64))
+    ora._apply_blackbody(ora.e)
+    lat.set_flux_window(5)
+    lat.step(40)
+    oqx, oqy = ora.run(40, flux_window=5)
     assert _rel(lat.populations().cpu().numpy(), ora.e) <= RTOL
+    assert _rel(lat.temperature().cpu().numpy(), ora.temperature()) <= RTOL
+    qx, qy = lat.heat_flux(averaged=True)
+    scale = np.abs(ora.temperature()).max()
+    assert np.abs(qx.cpu().numpy() - oqx).max() <= RTOL * scale
+    assert np.abs(qy.cpu().numpy() - oqy).max() <= RTOL * scale
 
 
 def test_per_cell_mfp_field():
@@ -156,7 +172,7 @@ def test_flux_window_average():
     lat.step(90)
     qx, qy = lat.heat_flux(averaged=True)
     oqx, oqy = ora.run(90, flux_window=10)
-    scale = np.abs(oqx).max()
+    scale = np.abs(ora.temperature()).max()
     assert np.abs(qx.cpu().numpy() - oqx).max() <= RTOL * scale
     assert np.abs(qy.cpu().numpy() - oqy).max() <= RTOL * scale
     from paper_1911_00180_amd import wormlbm as W
