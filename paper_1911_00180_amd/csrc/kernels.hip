@@ -54,6 +54,14 @@ __device__ __forceinline__ float buf_load(rsrc_t r, uint32_t voff, uint32_t soff
 __device__ __forceinline__ void buf_store(float v, rsrc_t r, uint32_t voff, uint32_t soff = 0) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
 }
+// Population stores are streamed: nothing reads them again in this step, so
+// they carry the non-temporal hint (cache-policy bit 1, "nt" on gfx950),
+// which measurably raises the write throughput of the step.
+constexpr int kStreamStore = 2;
+__device__ __forceinline__ void buf_store_stream(float v, rsrc_t r, uint32_t voff, uint32_t soff) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff,
+                                        kStreamStore);
+}
 
 // Tables that every lane reads at the same index (schedule codes, weights,
 // unit vectors) are read through the scalar cache.
@@ -272,9 +280,9 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
         if (ghost)
           store_ghosted(a.e_out + (long long)i * plane, x, y, out, a.nx, a.ny, pitch, px, py);
         else
-          buf_store(out, ro, boff, d * plane_bytes);
+          buf_store_stream(out, ro, boff, d * plane_bytes);
       } else {
-        buf_store(out, ro, boff, d * plane_bytes);
+        buf_store_stream(out, ro, boff, d * plane_bytes);
       }
       Eacc += out;
       if constexpr (FLUX) {
