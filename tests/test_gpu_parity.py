@@ -258,3 +258,34 @@ def test_full_size_1024_energy_and_sampled_cells():
         ora.run(n)
         want = ora.temperature()[half, half]
         assert abs(T[sy, sx] - want) <= RTOL * max(T0.max(), 1e-30), (sx, sy)
+
+
+@pytest.mark.parametrize("kn", [0.1, 10.0])
+def test_crop_256_q64_4000_steps(kn):
+    """The 256 x 256 periodic crop of the benchmarked workload (Q = 64 evenly
+    spaced, MFP kn * 1024, Gaussian sigma0 = 16 at the seeded centre) run for
+    4000 steps against stored FP64 oracle values (written by
+    tests/golden/make_crop_reference.py): 2048 seeded cells, the row and the
+    column through the centre, and the total energy."""
+    import json
+    import os
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    with open(os.path.join(golden, f"crop256_q64_kn{kn:g}.json")) as f:
+        ref = json.load(f)
+    n, q = 256, 64
+    x0, y0 = inputs.seeded_center(1911, 1024, 1024)
+    cx, cy = x0 % n, y0 % n
+    assert [cx, cy] == ref["center"]
+    T0 = inputs.gaussian_pulse(n, n, 16.0, cx, cy).astype(np.float32)
+    lat = _lattice(nx=n, ny=n, q=q, mfp=ref["mfp"])
+    lat.set_temperature(torch.from_numpy(T0))
+    lat.step(ref["steps"])
+    T = lat.temperature().cpu().numpy().astype(np.float64)
+    tol = RTOL * ref["max_abs_T"]
+    cells = np.asarray(ref["cells"])
+    assert np.abs(T[cells[:, 1], cells[:, 0]] - np.asarray(ref["T_cells"])).max() <= tol
+    assert np.abs(T[cy, :] - np.asarray(ref["T_row"])).max() <= tol
+    assert np.abs(T[:, cx] - np.asarray(ref["T_col"])).max() <= tol
+    assert abs(float(np.abs(T).max()) - ref["max_abs_T"]) <= tol
+    e, _, _ = lat.totals()
+    assert abs(e - ref["energy"]) <= 1e-6 * ref["energy"]

@@ -122,3 +122,64 @@ def test_mutation_is_caught(name):
         assert caught, f"mutation {name} passed every pin"
     finally:
         sys.modules.pop(f"oracle_mutant_{name}", None)
+
+
+ADJOINT = os.path.join(os.path.dirname(ORACLE), "adjoint.py")
+
+ADJOINT_MUTATIONS = {
+    "walls_not_absorbed": (
+        "        lam[:, wall] = 0.0",
+        "        lam[:, wall] *= 1.0"),
+    "eed_gradient_dropped": (
+        "gW += -dd + e_prev.sum(axis=0) * G",
+        "gW += -dd"),
+    "adjoint_hops_on_pause": (
+        "out[j] = (1.0 - W) * _pull(lam[j], hx, hy, c) + W * G",
+        "out[j] = (1.0 - W) * _pull(lam[j], sx, sy, c) + W * G"),
+    "adjoint_equilibrium_unweighted": (
+        "G += lat.w[i] * _pull(lam[i], sx, sy, c)",
+        "G += _pull(lam[i], sx, sy, c) / c.q"),
+    "adjoint_pulls_from_wrong_side": (
+        "return pad[1 + dy:1 + dy + ny, 1 + dx:1 + dx + nx]",
+        "return pad[1 - dy:1 - dy + ny, 1 - dx:1 - dx + nx]"),
+    "seed_without_factor_two": (
+        "np.add.at(s, (py, px), 2.0 * d)",
+        "np.add.at(s, (py, px), d)"),
+    "mfp_chain_rule_wrong": (
+        "dWc = f * (1.0 - 2.0 * Wp + 2.0 * Wp * lat.lam)",
+        "dWc = f * (1.0 - Wp + Wp * lat.lam)"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ADJOINT_MUTATIONS))
+def test_adjoint_mutation_is_caught(name):
+    import test_oracle_adjoint as adj_checks
+    old, new = ADJOINT_MUTATIONS[name]
+    with open(ADJOINT) as f:
+        src = f.read()
+    assert src.count(old) == 1, f"snippet of {name} must occur exactly once"
+    mod = types.ModuleType("oracle.adjoint_mutant")
+    mod.__file__ = ADJOINT
+    mod.__package__ = "oracle"
+    exec(compile(src.replace(old, new), ADJOINT, "exec"), mod.__dict__)
+    saved = adj_checks.adj
+    adj_checks.adj = mod
+    caught = False
+    try:
+        for args in [("blackbody", "blackbody", 16, "ring")]:
+            try:
+                adj_checks.test_transposed_step_equals_jacobian_transpose(*args)
+            except Exception:
+                caught = True
+        for args in [("blackbody", "periodic", False, 16, "uniform"),
+                     ("blackbody", "blackbody", True, 16, "uniform"),
+                     ("periodic", "periodic", False, 24, "ring")]:
+            if caught:
+                break
+            try:
+                adj_checks.test_gradients_match_central_differences(*args)
+            except Exception:
+                caught = True
+    finally:
+        adj_checks.adj = saved
+    assert caught, f"mutation {name} passed every adjoint pin"
