@@ -181,6 +181,94 @@ wlbm_status wlbm_get_constants(const wlbm_params* p, double* lambda_corr, double
 wlbm_status wlbm_get_schedule(const wlbm_params* p, int64_t step0, int64_t n, int8_t* moves,
                               int64_t* pos);
 
+/* ---- Saved states (checkpoints) ------------------------------------------
+ * A state is the lattice's padded population planes followed by its padded
+ * E plane, wlbm_state_bytes bytes, in device memory owned by the caller.  Its
+ * internal layout is not part of this interface; buffers move between calls
+ * of this library only, for lattices created with the same parameters. */
+
+/* Bytes of one saved state (a multiple of 256). */
+wlbm_status wlbm_state_bytes(const wlbm_lattice* lat, size_t* bytes);
+
+/* Copy the current state into d_buf (at least wlbm_state_bytes bytes), in
+ * stream order. */
+wlbm_status wlbm_save_state(wlbm_lattice* lat, void* d_buf, size_t bytes);
+
+/* Make d_buf the current state and `step` the current step count (the
+ * schedule continues from that step; step must be the step the state was
+ * saved at for the result to be the same run).  In stream order. */
+wlbm_status wlbm_load_state(wlbm_lattice* lat, const void* d_buf, size_t bytes, int64_t step);
+
+/* As wlbm_step, and the state after each step is kept: step k (1-based) of
+ * this call writes its output directly into slot k-1 of d_tape, slot j at
+ * d_tape + j * slot_bytes (256-byte aligned, slot_bytes a multiple of 256 and
+ * at least wlbm_state_bytes).  The tape must be zero-filled before its first
+ * use: the library writes only the ghost copies of periodic edges, and the
+ * ghost frame of other edges must read zero.  The last slot is also copied
+ * into the lattice's current state. */
+wlbm_status wlbm_step_tape(wlbm_lattice* lat, int64_t nsteps, void* d_tape, size_t slot_bytes);
+
+/* Temperatures T = sum_i e_i at n probe cells: d_cells is a device [n][2]
+ * int32 array of (x, y), d_T a device [n] float array (NaN for a cell outside
+ * the lattice). */
+wlbm_status wlbm_read_probes(wlbm_lattice* lat, int32_t n, const int32_t* d_cells, float* d_T);
+
+/* ---- Adjoint (reverse mode) ----------------------------------------------
+ * Gradients of a loss L of probe temperatures T^m(p) with respect to the
+ * per-cell mean free path, the initial temperature field and the blackbody
+ * wall temperatures, for periodic and blackbody edges.
+ *
+ * For a fixed relaxation field a time step is affine in the populations
+ * (Sec. 2.3, Eq. algorithm; Sec. 2.6 for the wall overwrite), so the adjoint
+ * lam^m = dL/de^m obeys lam^{m-1} = A_m^T lam^m + dL/de^{m-1}, with lam zero at
+ * blackbody cells after their contribution to the wall gradient is taken.
+ * The reverse pass runs from step M down to 0:
+ *   wlbm_adjoint_begin(lat, ws, bytes, M);
+ *   at every loss step m (from M downwards): wlbm_adjoint_seed(dL/dT^m(p)),
+ *   then wlbm_adjoint_steps(lat, n, states, slot) to go from m to m - n,
+ *   where the states e^{m-n} .. e^{m-1} of the forward run (saved with
+ *   wlbm_save_state or wlbm_step_tape) sit in consecutive slots;
+ *   wlbm_adjoint_read at step 0.
+ * The adjoint workspace is caller-owned device memory of wlbm_adjoint_bytes
+ * bytes that must stay valid until the reverse pass is over; the lattice's
+ * forward state is not used or changed by the reverse pass. */
+
+/* Bytes of the adjoint workspace. */
+wlbm_status wlbm_adjoint_bytes(const wlbm_lattice* lat, size_t* bytes);
+
+/* Start a reverse pass at forward step `step` (the last step of the run):
+ * clears the workspace (256-byte aligned) in stream order, sets lam = 0 and
+ * zeroes the gradient accumulators.  WLBM_EINVAL for diffuse walls. */
+wlbm_status wlbm_adjoint_begin(wlbm_lattice* lat, void* d_ws, size_t bytes, int64_t step);
+
+/* Add dL/dT^m at probe cells for the current adjoint step m: d_cells is a
+ * device [n][2] int32 array of (x, y), d_dT a device [n] float array.  Every
+ * population of the cell receives the value (T = sum_i e_i); at a blackbody
+ * cell it goes to the wall gradient.  Repeated cells add up.  A cell outside
+ * the lattice is skipped and reported as WLBM_EINVAL by wlbm_adjoint_read. */
+wlbm_status wlbm_adjoint_seed(wlbm_lattice* lat, int32_t n, const int32_t* d_cells,
+                              const float* d_dT);
+
+/* Take n reverse steps, from adjoint step m to m - n (0 <= n <= m).  Reverse
+ * step k needs the forward state e^{k-1}: the states of steps m - n .. m - 1
+ * are read from slots 0 .. n-1 of d_states (256-byte aligned, slot_bytes a
+ * multiple of 256, at least wlbm_state_bytes).  The lattice's relaxation
+ * field must be the one of the forward run. */
+wlbm_status wlbm_adjoint_steps(wlbm_lattice* lat, int64_t n, const void* d_states,
+                               size_t slot_bytes);
+
+/* Gradients so far (complete at adjoint step 0); each output may be NULL.
+ * d_g_mfp: device [ny][nx] float, dL/dMFP per cell (the relaxation time in
+ * lattice units; through Eq. W-correction and W = 1/MFP).  d_g_T0: device
+ * [ny][nx] float, sum_i w_i lam_i at the current step, i.e. dL/dT0 at step 0
+ * (e_i^0 = w_i T0).  g_walls: host [4] double, dL/dT of the x_lo, x_hi, y_lo,
+ * y_hi blackbody walls (x walls own the corners; 0 for other edges).  Waits
+ * for the stream. */
+wlbm_status wlbm_adjoint_read(wlbm_lattice* lat, float* d_g_mfp, float* d_g_T0, double* g_walls);
+
+/* Current adjoint step m, or -1 when no reverse pass was begun. */
+int64_t wlbm_adjoint_step_index(const wlbm_lattice* lat);
+
 /* Steps taken since creation (or -1 for NULL). */
 int64_t wlbm_step_count(const wlbm_lattice* lat);
 

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libwormlbm.so")
-SOURCES = ["tables.cpp", "kernels.hip", "api.hip"]
+SOURCES = ["tables.cpp", "kernels.hip", "adjoint.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
@@ -23,6 +23,7 @@ HIPCC_FLAGS = [
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall",
+    "-Wshadow",
     "-Wno-unused-result",
 ]
 

@@ -1,5 +1,5 @@
 // Device-side data layout and kernel launch interface of the worm-LBM
-// library.  Shared by kernels.hip and api.hip only.
+// library.  Shared by the library's .hip sources only.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -98,6 +98,71 @@ hipError_t launch_totals(const Geometry& g, const float* e, const float* E, cons
 hipError_t launch_check_mfp(const Geometry& g, const float* mfp, double lam, double f, int corr,
                             int* flag, hipStream_t s);
 hipError_t launch_write_wfield(const Geometry& g, const float* mfp, double lam, double f,
-                               int corr, float* Wf, hipStream_t s);
+                               int corr, float* Wf, float* Wraw, hipStream_t s);
+
+// Reverse step m of the adjoint: reads lam^m (zero at blackbody cells and
+// beyond non-periodic edges), its eight move-class partial sums H^m and the
+// forward state e^{m-1}, E^{m-1}; writes lam^{m-1} and H^{m-1} (classes by
+// the moves of step m-1) and adds to the float64 per-cell accumulators gW
+// (dL/dW_corr) and gB (wall cells: dL/de^{m-1} summed with the weights).
+struct AdjArgs {
+  const float* lam_in;
+  float* lam_out;
+  const float* H_in;      // 8 padded planes
+  float* H_out;
+  const float* e_prev;    // q padded planes
+  const float* E_prev;    // padded plane
+  const float* Wf;        // per-cell corrected weight (per-cell mode)
+  double* gW;             // [ny][nx]
+  double* gB;             // [ny][nx], wall cells only
+  const uint32_t* codes;       // schedule row of step m
+  const uint32_t* codes_next;  // schedule row of step m-1 (any row for m = 1)
+  const float* wtab;
+  float W;
+  int nx, ny, q, pitch;
+  long long plane;
+  int x_edge, y_edge;
+  int tiles_x, ntiles;
+};
+
+// Adds dL/dT = vals[p] at probe cells (x, y) = cells[2p], cells[2p+1] to
+// lam (all directions) and H (class c gets vals[p] * wcls[c]); at wall cells
+// to gB instead, times wall_w = sum_i w_i.  Sets *flag for a cell outside
+// the lattice.
+struct AdjSeedArgs {
+  float* lam;
+  float* H;
+  double* gB;
+  const int32_t* cells;
+  const float* vals;
+  int* flag;
+  int n;
+  float wcls[8];
+  double wall_w;
+  int nx, ny, q, pitch;
+  long long plane;
+  int x_edge, y_edge;
+};
+
+hipError_t launch_adjoint(const AdjArgs& a, int split, bool per_cell, hipStream_t s);
+hipError_t launch_adj_seed(const AdjSeedArgs& a, hipStream_t s);
+// Per-cell dL/dMFP from dL/dW_corr; Wraw is the [ny][nx] field of W = 1/MFP
+// or NULL for the uniform W_uniform.
+hipError_t launch_adj_grad_mfp(const Geometry& g, const double* gW, const float* Wraw,
+                               double W_uniform, double lam, double f, int corr, float* out,
+                               hipStream_t s);
+hipError_t launch_adj_grad_t0(const Geometry& g, const float* lam, const float* wtab, float* out,
+                              hipStream_t s);
+// out[0..3] = dL/dT of the x_lo, x_hi, y_lo, y_hi walls.
+hipError_t launch_adj_walls(const Geometry& g, const double* gB, double* out, hipStream_t s);
+hipError_t launch_read_probes(const Geometry& g, const float* E, const int32_t* cells, int n,
+                              float* out, hipStream_t s);
+
+// Move class 0..7 of a D2Q8 move, as the adjoint kernel numbers its partial
+// sums (host copy of the device rule).
+inline int host_move_class(int dx, int dy) {
+  const int c = (dx + 1) * 3 + (dy + 1);
+  return c - (c > 4 ? 1 : 0);
+}
 
 }  // namespace wlbm

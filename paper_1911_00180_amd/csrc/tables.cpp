@@ -1,6 +1,8 @@
 // Host-side tables of the worm-LBM (see tables.hpp).
 #include "tables.hpp"
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdlib>
 #include <stdexcept>
@@ -189,6 +191,54 @@ void tas_advance(const DirSet& d, TasState& st, int8_t* dx, int8_t* dy, uint8_t*
     hop[i] = h ? 1 : 0;
   }
   st.n = n;
+}
+
+void tas_restore(const DirSet& d, TasState& st, int64_t n, const int32_t* k) {
+  st.reset(d.q);
+  st.n = n;
+  for (int i = 0; i < d.q; ++i) {
+    const int64_t kk = k[i];
+    const int64_t major = kk * d.sgn_major[i];
+    const int64_t minor = worm_minor(d, i, kk) * d.sgn_minor[i];
+    st.k[i] = kk;
+    st.px[i] = d.major[i] == 0 ? major : minor;
+    st.py[i] = d.major[i] == 0 ? minor : major;
+  }
+}
+
+void ScheduleBook::reset(const DirSet* d) {
+  d_ = d;
+  snaps_.assign(1, std::vector<int32_t>(d->q, 0));
+}
+
+void ScheduleBook::note(const TasState& st) {
+  if (st.n % kSnapEvery != 0) return;
+  const int64_t s = st.n / kSnapEvery;
+  if (s != int64_t(snaps_.size())) return;
+  std::vector<int32_t> k(d_->q);
+  for (int i = 0; i < d_->q; ++i) k[i] = int32_t(st.k[i]);
+  snaps_.push_back(std::move(k));
+}
+
+void ScheduleBook::state_at(int64_t n, TasState& out) {
+  int64_t s = std::min<int64_t>(n / kSnapEvery, int64_t(snaps_.size()) - 1);
+  tas_restore(*d_, out, s * kSnapEvery, snaps_[size_t(s)].data());
+  std::vector<int8_t> dx(d_->q), dy(d_->q);
+  std::vector<uint8_t> hop(d_->q);
+  while (out.n < n) {
+    tas_advance(*d_, out, dx.data(), dy.data(), hop.data());
+    note(out);
+  }
+}
+
+void ScheduleBook::rows(int64_t first, int64_t count, int8_t* dx, int8_t* dy, uint8_t* hop) {
+  TasState st;
+  state_at(first - 1, st);
+  const size_t q = size_t(d_->q);
+  for (int64_t r = 0; r < count; ++r) {
+    tas_advance(*d_, st, dx + r * q, dy + r * q, hop + r * q);
+    note(st);
+  }
 }
 
 }  // namespace wlbm

@@ -63,4 +63,29 @@ struct TasState {
 // in exact integers; on a hop P_i and k_i advance.  Outputs are [q] arrays.
 void tas_advance(const DirSet& d, TasState& st, int8_t* dx, int8_t* dy, uint8_t* hop);
 
+// The state after n steps from the hop counts k_i alone: after k hops the
+// worm of direction i sits at k along its major axis and worm_minor(k) along
+// its minor axis, with the signs of the direction.
+void tas_restore(const DirSet& d, TasState& st, int64_t n, const int32_t* k);
+
+// Schedule rows of any step range, from snapshots of the hop counts taken
+// every kSnapEvery steps (4 q bytes each) as the schedule is first produced;
+// a range is regenerated from the nearest snapshot at or before it.
+class ScheduleBook {
+ public:
+  static constexpr int64_t kSnapEvery = 64;
+  void reset(const DirSet* d);
+  // State after `n` steps.
+  void state_at(int64_t n, TasState& out);
+  // Record the hop counts of `st` if it sits on a snapshot step not yet held.
+  void note(const TasState& st);
+  // dx/dy/hop of steps first .. first + count - 1 (first >= 1) into
+  // [count][q] arrays.
+  void rows(int64_t first, int64_t count, int8_t* dx, int8_t* dy, uint8_t* hop);
+
+ private:
+  const DirSet* d_ = nullptr;
+  std::vector<std::vector<int32_t>> snaps_;  // snaps_[s]: k_i after s * kSnapEvery steps
+};
+
 }  // namespace wlbm

@@ -96,6 +96,38 @@ class Lattice:
         self._sync_stream()
         return W.wlbm_read_totals(self.handle)
 
+    # -- saved states and tapes -----------------------------------------------
+    @property
+    def state_bytes(self) -> int:
+        return W.wlbm_state_bytes(self.handle)
+
+    def new_states(self, n: int) -> torch.Tensor:
+        """n zero-filled state slots, [n, state_bytes] uint8 (a tape)."""
+        return torch.zeros((n, self.state_bytes), dtype=torch.uint8, device=self.device)
+
+    def save_state(self, buf: torch.Tensor) -> None:
+        self._sync_stream()
+        W.wlbm_save_state(self.handle, buf.data_ptr(), buf.numel())
+
+    def load_state(self, buf: torch.Tensor, step: int) -> None:
+        self._sync_stream()
+        W.wlbm_load_state(self.handle, buf.data_ptr(), buf.numel(), step)
+
+    def step_tape(self, n: int, tape: torch.Tensor) -> None:
+        """n steps; the state after step k (1-based) goes to tape[k - 1]."""
+        if tape.dim() != 2 or tape.shape[0] < n or not tape.is_contiguous():
+            raise ValueError("tape must be a contiguous [slots >= n, slot_bytes] tensor")
+        self._sync_stream()
+        W.wlbm_step_tape(self.handle, n, tape.data_ptr(), tape.shape[1])
+
+    def read_probes(self, cells: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """T at cells ([P, 2] int32 (x, y) on the device)."""
+        self._sync_stream()
+        if out is None:
+            out = torch.empty(cells.shape[0], dtype=torch.float32, device=self.device)
+        W.wlbm_read_probes(self.handle, cells.shape[0], cells.data_ptr(), out.data_ptr())
+        return out
+
     def close(self) -> None:
         if getattr(self, "handle", None):
             W.wlbm_destroy(self.handle)

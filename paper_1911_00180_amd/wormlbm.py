@@ -38,6 +38,9 @@ EXPORTS = (
     "wlbm_read_temperature", "wlbm_read_heat_flux", "wlbm_read_populations",
     "wlbm_read_totals", "wlbm_get_directions", "wlbm_get_constants", "wlbm_get_schedule",
     "wlbm_step_count", "wlbm_last_error", "wlbm_destroy",
+    "wlbm_state_bytes", "wlbm_save_state", "wlbm_load_state", "wlbm_step_tape",
+    "wlbm_read_probes", "wlbm_adjoint_bytes", "wlbm_adjoint_begin", "wlbm_adjoint_seed",
+    "wlbm_adjoint_steps", "wlbm_adjoint_read", "wlbm_adjoint_step_index",
 )
 
 
@@ -97,6 +100,17 @@ def lib() -> ctypes.CDLL:
         "wlbm_step_count": (c_int64, [c_void_p]),
         "wlbm_last_error": (c_char_p, []),
         "wlbm_destroy": (c_int, [c_void_p]),
+        "wlbm_state_bytes": (c_int, [c_void_p, POINTER(c_size_t)]),
+        "wlbm_save_state": (c_int, [c_void_p, c_void_p, c_size_t]),
+        "wlbm_load_state": (c_int, [c_void_p, c_void_p, c_size_t, c_int64]),
+        "wlbm_step_tape": (c_int, [c_void_p, c_int64, c_void_p, c_size_t]),
+        "wlbm_read_probes": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
+        "wlbm_adjoint_bytes": (c_int, [c_void_p, POINTER(c_size_t)]),
+        "wlbm_adjoint_begin": (c_int, [c_void_p, c_void_p, c_size_t, c_int64]),
+        "wlbm_adjoint_seed": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
+        "wlbm_adjoint_steps": (c_int, [c_void_p, c_int64, c_void_p, c_size_t]),
+        "wlbm_adjoint_read": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
+        "wlbm_adjoint_step_index": (c_int64, [c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -224,6 +238,57 @@ def wlbm_last_error() -> str:
 
 def wlbm_destroy(h: int) -> None:
     _check(lib().wlbm_destroy(c_void_p(h)))
+
+
+def wlbm_state_bytes(h: int) -> int:
+    n = c_size_t(0)
+    _check(lib().wlbm_state_bytes(c_void_p(h), byref(n)))
+    return n.value
+
+
+def wlbm_save_state(h: int, d_buf, nbytes: int) -> None:
+    _check(lib().wlbm_save_state(c_void_p(h), _ptr(d_buf), nbytes))
+
+
+def wlbm_load_state(h: int, d_buf, nbytes: int, step: int) -> None:
+    _check(lib().wlbm_load_state(c_void_p(h), _ptr(d_buf), nbytes, step))
+
+
+def wlbm_step_tape(h: int, nsteps: int, d_tape, slot_bytes: int) -> None:
+    _check(lib().wlbm_step_tape(c_void_p(h), nsteps, _ptr(d_tape), slot_bytes))
+
+
+def wlbm_read_probes(h: int, n: int, d_cells, d_T) -> None:
+    _check(lib().wlbm_read_probes(c_void_p(h), n, _ptr(d_cells), _ptr(d_T)))
+
+
+def wlbm_adjoint_bytes(h: int) -> int:
+    n = c_size_t(0)
+    _check(lib().wlbm_adjoint_bytes(c_void_p(h), byref(n)))
+    return n.value
+
+
+def wlbm_adjoint_begin(h: int, d_ws, nbytes: int, step: int) -> None:
+    _check(lib().wlbm_adjoint_begin(c_void_p(h), _ptr(d_ws), nbytes, step))
+
+
+def wlbm_adjoint_seed(h: int, n: int, d_cells, d_dT) -> None:
+    _check(lib().wlbm_adjoint_seed(c_void_p(h), n, _ptr(d_cells), _ptr(d_dT)))
+
+
+def wlbm_adjoint_steps(h: int, n: int, d_states, slot_bytes: int) -> None:
+    _check(lib().wlbm_adjoint_steps(c_void_p(h), n, _ptr(d_states), slot_bytes))
+
+
+def wlbm_adjoint_read(h: int, d_g_mfp, d_g_T0):
+    """Returns the four wall gradients (x_lo, x_hi, y_lo, y_hi)."""
+    walls = (c_double * 4)()
+    _check(lib().wlbm_adjoint_read(c_void_p(h), _ptr(d_g_mfp), _ptr(d_g_T0), walls))
+    return tuple(walls)
+
+
+def wlbm_adjoint_step_index(h: int) -> int:
+    return lib().wlbm_adjoint_step_index(c_void_p(h))
 
 
 def make_params(nx: int, ny: int, q: int, mfp: float = float("inf"), dirs: str = "uniform",
