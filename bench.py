@@ -24,8 +24,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
-KERNEL_SRC = os.path.join(ROOT, "paper_1911_00180_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1911_00180_amd", "csrc")
+STEP_SOURCES = ("kernels.hip", "kernel_common.hpp", "device.hpp")
+ADJOINT_SOURCES = ("adjoint.hip", "kernel_common.hpp", "device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_1024x1024_q64_traffic.md")
+ADJOINT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_adjoint_1024x1024_q64.md")
 
 
 def bytes_per_update(q: int, per_cell_w: bool = False) -> float:
@@ -35,23 +38,27 @@ def bytes_per_update(q: int, per_cell_w: bool = False) -> float:
     return 8.0 + 8.0 / q + (4.0 / q if per_cell_w else 0.0)
 
 
-def kernel_hash() -> str:
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_hash(sources=STEP_SOURCES) -> str:
+    """Hash of the sources a kernel is built from (first 16 hex digits)."""
+    h = hashlib.sha256()
+    for name in sources:
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def recorded_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None if it is missing or was taken on a different kernel source."""
-    if not os.path.exists(TRAFFIC_FILE):
+def recorded_traffic(path=TRAFFIC_FILE, sources=STEP_SOURCES):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, or
+    None if it is missing or was taken on different kernel sources."""
+    if not os.path.exists(path):
         return None
     vals = {}
-    with open(TRAFFIC_FILE) as f:
+    with open(path) as f:
         for line in f:
             if ":" in line and line.strip().startswith("- "):
                 k, v = line.strip()[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_sha256_16") != kernel_hash():
+    if vals.get("kernel_sha256_16") != kernel_hash(sources):
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -87,6 +94,102 @@ def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911):
     del lat
     torch.cuda.empty_cache()
     return ms, wall, energy
+
+
+def adjoint_bytes_per_update(q: int, per_cell_w: bool = False) -> float:
+    """Algorithmic HBM bytes per cell-direction update of one reverse step:
+    adjoint populations read and written, forward state read (12 B); per cell
+    the eight move-class partial sums read and written (64 B), the forward E
+    read (4 B), the float64 gradient accumulator read and written (16 B), and
+    a per-cell weight field (4 B)."""
+    return 12.0 + (64.0 + 4.0 + 16.0 + (4.0 if per_cell_w else 0.0)) / q
+
+
+def run_adjoint_ratio(steps=1000, K=50, repeats=3):
+    """Forward (with checkpoints and probe reads) and backward (recompute +
+    reverse steps) of the 256 x 256, Q = 64 inverse problem; median times."""
+    import numpy as np
+    import torch
+
+    from paper_1911_00180_amd import inputs
+    from paper_1911_00180_amd.autodiff import ProbeSeries
+    from paper_1911_00180_amd.lattice import Lattice
+
+    n, mfp, tgt, T0, probes = inputs.inverse_problem_256()
+    lat = Lattice(n, n, 64, mfp=16.0, x_edge="blackbody", y_edge="periodic", device="cuda:0")
+    series = ProbeSeries(lat, probes, steps, 10, checkpoint_every=K)
+    dev = "cuda:0"
+    walls = torch.tensor([0.5, 0.0, 0.0, 0.0], device=dev)
+    T0d = torch.from_numpy(T0).to(dev)
+    with torch.no_grad():
+        target = series(torch.from_numpy(tgt).to(dev), T0d, walls)
+    stream = torch.cuda.current_stream()
+    fwd, bwd = [], []
+    for r in range(repeats + 1):
+        m = torch.from_numpy(mfp).to(dev).requires_grad_(True)
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        torch.cuda.synchronize()
+        e0.record(stream)
+        out = series(m, T0d, walls)
+        loss = ((out - target) ** 2).sum()
+        e1.record(stream)
+        loss.backward()
+        e2.record(stream)
+        torch.cuda.synchronize()
+        if r:
+            fwd.append(e0.elapsed_time(e1))
+            bwd.append(e1.elapsed_time(e2))
+    grad_ok = bool(torch.isfinite(m.grad).all())
+    lat.close()
+    f, b = float(np.median(fwd)), float(np.median(bwd))
+    return {"workload": "256x256, Q=64, lognormal MFP field (median 16, clipped 4..64), blackbody "
+                        "x walls 0.5/0, periodic y, 1000 steps, 32 probes, loss every 10 steps, "
+                        f"checkpoint every {K}",
+            "forward_ms": round(f, 3), "backward_ms": round(b, 3),
+            "ratio": round(b / f, 3), "grad_finite": grad_ok}
+
+
+def run_adjoint_kernel(nx=1024, ny=1024, q=64, steps=20):
+    """Reverse steps on the 1024 x 1024, Q = 64 periodic lattice (uniform
+    MFP 102.4): average time per step over a tape of `steps` states."""
+    import numpy as np
+    import torch
+
+    from paper_1911_00180_amd import inputs
+    from paper_1911_00180_amd import wormlbm as W
+    from paper_1911_00180_amd.lattice import Lattice
+
+    x0, y0 = inputs.seeded_center(1911, nx, ny)
+    T0 = inputs.gaussian_pulse(nx, ny, 16.0, x0, y0).astype(np.float32)
+    lat = Lattice(nx, ny, q, mfp=102.4, device="cuda:0")
+    lat.set_temperature(torch.from_numpy(T0))
+    tape = lat.new_states(steps)
+    lat.save_state(tape[0])
+    lat.step_tape(steps - 1, tape[1:])
+    ws = torch.empty(W.wlbm_adjoint_bytes(lat.handle), dtype=torch.uint8, device="cuda:0")
+    cells = torch.tensor([[x0, y0]], dtype=torch.int32, device="cuda:0")
+    seed = torch.ones(1, dtype=torch.float32, device="cuda:0")
+    stream = torch.cuda.current_stream()
+    times = []
+    for r in range(4):
+        lat._sync_stream()
+        W.wlbm_adjoint_begin(lat.handle, ws.data_ptr(), ws.numel(), steps)
+        W.wlbm_adjoint_seed(lat.handle, 1, cells.data_ptr(), seed.data_ptr())
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        W.wlbm_adjoint_steps(lat.handle, steps, tape[0].data_ptr(), tape.shape[1])
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if r:
+            times.append(e0.elapsed_time(e1) / steps)
+    lat.close()
+    ms = float(np.median(times))
+    bpu = adjoint_bytes_per_update(q)
+    achieved = bpu * nx * ny * q / (ms * 1e-3) / 1e9
+    return {"workload": f"{nx}x{ny} periodic, Q={q}, uniform MFP 102.4, {steps} reverse steps",
+            "ms_per_step": round(ms, 5), "bytes_per_update": round(bpu, 4),
+            "achieved_GBs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": recorded_traffic(ADJOINT_TRAFFIC_FILE, ADJOINT_SOURCES)}
 
 
 def cpu_baseline(budget_s: float = 15.0):
@@ -133,6 +236,7 @@ def main():
                     help="also time the 4096 x 4096, Q = 256 wall-bounded lattice")
     ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurements")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this size (counter calibration)")
@@ -215,6 +319,10 @@ def main():
             "ms_per_step": round(st, 4),
             "roofline_frac": round(bl / (st * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         }
+    if not args.no_adjoint:
+        adj = run_adjoint_ratio()
+        adj["kernel"] = run_adjoint_kernel()
+        out["adjoint"] = adj
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -209,35 +209,42 @@ hipError_t launch_adj_nw(const AdjArgs& a, bool wf, hipStream_t s) {
 }
 
 // Seeds dL/dT at probe cells: T = sum_i e_i, so every direction of the cell
-// receives the value.  Thread j < q owns direction plane j, threads q .. q+7
-// the partial-sum planes, thread q+8 the wall accumulator; each walks the
-// probe list in order, so repeated cells add up without races.
+// receives the value.  One thread per (probe, plane): planes j < q are the
+// directions, q .. q+7 the partial sums, q+8 the wall accumulator.  A cell
+// listed several times is handled by the threads of its first listing, which
+// add up the values of all its listings in order, so the result does not
+// depend on timing.
 __global__ __launch_bounds__(kBlock) void k_adj_seed(const AdjSeedArgs a) {
+  const int planes = a.q + 9;
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= (long long)a.n * planes) return;
+  const int p = int(t / planes);
+  const int j = int(t - (long long)p * planes);
+  const int x = a.cells[2 * p];
+  const int y = a.cells[2 * p + 1];
+  if (x < 0 || x >= a.nx || y < 0 || y >= a.ny) {
+    if (j == 0) *a.flag = 1;
+    return;
+  }
+  for (int r = 0; r < p; ++r)
+    if (a.cells[2 * r] == x && a.cells[2 * r + 1] == y) return;
+  float v = a.vals[p];
+  for (int r = p + 1; r < a.n; ++r)
+    if (a.cells[2 * r] == x && a.cells[2 * r + 1] == y) v += a.vals[r];
   const bool px = a.x_edge == kPeriodic, py = a.y_edge == kPeriodic;
-  for (int j = threadIdx.x; j < a.q + 9; j += kBlock) {
-    for (int p = 0; p < a.n; ++p) {
-      const int x = a.cells[2 * p];
-      const int y = a.cells[2 * p + 1];
-      if (x < 0 || x >= a.nx || y < 0 || y >= a.ny) {
-        if (j == 0) *a.flag = 1;
-        continue;
-      }
-      const float v = a.vals[p];
-      const bool wall = wall_cell(x, y, a.nx, a.ny, a.x_edge, a.y_edge);
-      const long long o = cell(x, y, a.pitch);
-      if (j < a.q) {
-        if (wall) continue;
-        float* pl = a.lam + (long long)j * a.plane;
-        store_ghosted(pl, x, y, pl[o] + v, a.nx, a.ny, a.pitch, px, py);
-      } else if (j < a.q + 8) {
-        if (wall) continue;
-        const int c = j - a.q;
-        float* pl = a.H + (long long)c * a.plane;
-        store_ghosted(pl, x, y, fmaf(v, a.wcls[c], pl[o]), a.nx, a.ny, a.pitch, px, py);
-      } else if (wall) {
-        a.gB[(long long)y * a.nx + x] += double(v) * a.wall_w;
-      }
-    }
+  const bool wall = wall_cell(x, y, a.nx, a.ny, a.x_edge, a.y_edge);
+  const long long o = cell(x, y, a.pitch);
+  if (j < a.q) {
+    if (wall) return;
+    float* pl = a.lam + (long long)j * a.plane;
+    store_ghosted(pl, x, y, pl[o] + v, a.nx, a.ny, a.pitch, px, py);
+  } else if (j < a.q + 8) {
+    if (wall) return;
+    const int c = j - a.q;
+    float* pl = a.H + (long long)c * a.plane;
+    store_ghosted(pl, x, y, fmaf(v, a.wcls[c], pl[o]), a.nx, a.ny, a.pitch, px, py);
+  } else if (wall) {
+    a.gB[(long long)y * a.nx + x] += double(v) * a.wall_w;
   }
 }
 
@@ -322,7 +329,10 @@ hipError_t launch_adjoint(const AdjArgs& a, int split, bool per_cell, hipStream_
 }
 
 hipError_t launch_adj_seed(const AdjSeedArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_seed, dim3(1), dim3(kBlock), 0, s, a);
+  const long long threads = (long long)a.n * (a.q + 9);
+  if (threads == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_adj_seed, dim3(unsigned((threads + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, a);
   return hipGetLastError();
 }
 

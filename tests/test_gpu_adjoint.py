@@ -187,25 +187,10 @@ def test_adjoint_rejects_diffuse_walls():
     lat.close()
 
 
-def c4_problem(seed_field=1, seed_target=2):
-    """The 256 x 256, Q = 64 inverse problem: lognormal MFP field (median 16,
-    ln-spread ln(4)/2, correlation 16 cells, clipped to [4, 64]), blackbody x
-    walls at 0.5 / 0, periodic y, centred Gaussian sigma0 = 16, 1000 steps,
-    32 interior probes, loss every 10 steps against the probe temperatures of
-    a run with the target field."""
-    n = 256
-    mfp = inputs.smooth_lognormal_field(n, n, seed_field, 16.0, 16.0, np.log(4.0) / 2, 4.0, 64.0)
-    tgt = inputs.smooth_lognormal_field(n, n, seed_target, 16.0, 16.0, np.log(4.0) / 2, 4.0,
-                                        64.0)
-    T0 = inputs.gaussian_pulse(n, n, 16.0, n // 2, n // 2)
-    probes = inputs.probe_cells(3, n, n, 32, margin=8)
-    return n, mfp.astype(np.float32), tgt.astype(np.float32), T0.astype(np.float32), probes
-
-
 def test_c4_full_size_directional_derivatives():
     """Full size: <grad, v> against central differences of the GPU forward
     along smooth directions of the MFP field and of T0, and for each wall."""
-    n, mfp, tgt, T0, probes = c4_problem()
+    n, mfp, tgt, T0, probes = inputs.inverse_problem_256()
     from paper_1911_00180_amd.autodiff import ProbeSeries
     from paper_1911_00180_amd.lattice import Lattice
     lat = Lattice(n, n, 64, mfp=16.0, x_edge="blackbody", y_edge="periodic")
