@@ -44,6 +44,7 @@ extern "C" {
 #endif
 
 typedef struct wlbm_lattice wlbm_lattice;
+typedef struct wlbm_batch wlbm_batch;
 
 typedef enum wlbm_status {
   WLBM_OK = 0,
@@ -162,6 +163,14 @@ wlbm_status wlbm_read_populations(wlbm_lattice* lat, float* d_e);
  * Output pointers may be NULL. */
 wlbm_status wlbm_read_totals(wlbm_lattice* lat, double* energy, double* qx_sum, double* qy_sum);
 
+/* Mean heat flux over the columns x0 <= x < x1 and all rows, summed in
+ * float64 in a fixed order: of the trailing flux window of the last
+ * wlbm_step call (averaged = 1; WLBM_ESTATE without a complete window) or of
+ * the current state (averaged = 0).  Sec. 3.4 takes the in-plane flux of a
+ * film from such averages.  Waits for the stream.  Outputs may be NULL. */
+wlbm_status wlbm_read_flux_mean(wlbm_lattice* lat, int32_t x0, int32_t x1, int32_t averaged,
+                                double* qx_mean, double* qy_mean);
+
 /* Host-side tables, valid without a GPU (they need only the parameters). */
 
 /* Unit vectors (sx, sy) and weights w of the q directions, host [q] arrays
@@ -268,6 +277,55 @@ wlbm_status wlbm_adjoint_read(wlbm_lattice* lat, float* d_g_mfp, float* d_g_T0, 
 
 /* Current adjoint step m, or -1 when no reverse pass was begun. */
 int64_t wlbm_adjoint_step_index(const wlbm_lattice* lat);
+
+/* ---- Launch configuration and autotuning ---------------------------------
+ * The step kernel splits the q directions of each cell over 1, 2 or 4
+ * waves.  Results of different splits agree to rounding (the per-cell sum E
+ * is added in a split-dependent order); a run with a fixed split is
+ * bit-reproducible. */
+
+/* Set the split (0: library default for q; else 1, 2 or 4 with q a multiple
+ * of 8 * split).  Takes effect from the next step. */
+wlbm_status wlbm_set_dir_split(wlbm_lattice* lat, int32_t split);
+
+/* Current split, or -1 for NULL. */
+int32_t wlbm_get_dir_split(const wlbm_lattice* lat);
+
+/* Time `steps` steps (1 .. 10000, after 2 warm-up steps) with each valid
+ * split on the current state and keep the fastest.  The state and step count
+ * are saved in d_state (wlbm_state_bytes bytes) and restored after each
+ * trial, so the lattice ends where it started; the flux-window sums are not
+ * touched.  ms_by_split (host [3], may be NULL) receives the time per step of
+ * splits 1, 2, 4 (-1 where not valid); *chosen (may be NULL) the split kept.
+ * Waits for the stream. */
+wlbm_status wlbm_autotune(wlbm_lattice* lat, void* d_state, size_t bytes, int32_t steps,
+                          float* ms_by_split, int32_t* chosen);
+
+/* ---- Batches ----------------------------------------------------------------
+ * Several lattices with the same q and direction set, at the same step, with
+ * the same split, per-cell field use, schedule chunk and flux window, are
+ * advanced together: one kernel launch per time step covers the tiles of all
+ * of them (the schedule row is shared: it depends only on the directions and
+ * the step).  Sizes, edges, wall temperatures and relaxation weights may
+ * differ.  Each step gives the same result as wlbm_step on each lattice. */
+
+/* Bytes of device workspace for a batch of these n lattices (1 .. 4096). */
+wlbm_status wlbm_batch_bytes(wlbm_lattice* const* lats, int32_t n, size_t* bytes);
+
+/* Create a batch over the n lattices (the handles stay owned by the caller
+ * and must outlive the batch) in the caller's workspace (256-byte aligned).
+ * Batch work is enqueued on `stream`; the caller orders it with the work of
+ * the lattices' own streams (e.g. by using one stream for both). */
+wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, size_t bytes,
+                              void* stream, wlbm_batch** out);
+
+/* Advance every lattice of the batch nsteps steps, as wlbm_step would (their
+ * step counts, buffers and flux windows are updated).  Wall temperatures and
+ * fields are read from the lattices at each call. */
+wlbm_status wlbm_batch_step(wlbm_batch* batch, int64_t nsteps);
+
+/* Release the batch after waiting for its stream.  NULL is accepted. */
+wlbm_status wlbm_batch_destroy(wlbm_batch* batch);
 
 /* Steps taken since creation (or -1 for NULL). */
 int64_t wlbm_step_count(const wlbm_lattice* lat);

@@ -219,6 +219,69 @@ void auto_tiling(wlbm_lattice* l) { l->split = l->p.dir_split ? l->p.dir_split :
 
 }  // namespace
 
+// A set of lattices advanced together, one launch per step.
+struct wlbm_batch {
+  std::vector<wlbm_lattice*> lats;
+  hipStream_t stream = nullptr;
+  char* ws = nullptr;
+  size_t off_args = 0, off_first = 0, off_sched = 0;
+  int chunk = 0;
+  uint8_t* pinned[2] = {nullptr, nullptr};
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  bool ev_pending[2] = {false, false};
+  int64_t chunk_counter = 0;
+  char* table = nullptr;        // pinned staging of the argument table
+  hipEvent_t table_ev = nullptr;
+  bool table_pending = false;
+};
+
+namespace {
+
+struct BatchCarve {
+  size_t args, first, sched, total;
+};
+
+BatchCarve batch_carve(int n, int q, int chunk) {
+  BatchCarve c{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  c.args = take(size_t(2) * n * sizeof(StepArgs));
+  c.first = take(size_t(n + 1) * sizeof(int));
+  c.sched = take(size_t(2) * chunk * q);
+  c.total = off;
+  return c;
+}
+
+wlbm_status check_members(wlbm_lattice* const* lats, int32_t n) {
+  if (!lats) return fail(WLBM_EINVAL, "lattice list is NULL");
+  if (n < 1 || n > 4096) return fail(WLBM_EINVAL, "a batch holds 1 .. 4096 lattices");
+  for (int j = 0; j < n; ++j) {
+    wlbm_status st = check_lat(lats[j]);
+    if (st) return st;
+    const wlbm_lattice* a = lats[0];
+    const wlbm_lattice* b = lats[j];
+    if (b->p.q != a->p.q || b->p.dirs != a->p.dirs)
+      return fail(WLBM_EINVAL, "lattice %d: all lattices of a batch share q and the direction set",
+                  j);
+    if (b->tas.n != a->tas.n)
+      return fail(WLBM_EINVAL, "lattice %d: all lattices of a batch must be at the same step", j);
+    if (b->split != a->split || b->per_cell != a->per_cell || b->chunk != a->chunk)
+      return fail(WLBM_EINVAL,
+                  "lattice %d: direction split, per-cell field use and schedule chunk must agree", j);
+    if (b->flux_window != a->flux_window)
+      return fail(WLBM_EINVAL, "lattice %d: flux windows must agree", j);
+    for (int k = 0; k < j; ++k)
+      if (lats[k] == b) return fail(WLBM_EINVAL, "lattice %d appears twice in the batch", j);
+  }
+  return WLBM_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void wlbm_default_params(wlbm_params* p) {
@@ -936,6 +999,307 @@ wlbm_status wlbm_adjoint_read(wlbm_lattice* l, float* d_g_mfp, float* d_g_T0, do
 }
 
 int64_t wlbm_adjoint_step_index(const wlbm_lattice* l) { return l ? l->am : -1; }
+
+wlbm_status wlbm_set_dir_split(wlbm_lattice* l, int32_t split) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (split == 0) {
+    l->split = auto_split(l->p.q);
+    return WLBM_OK;
+  }
+  if (split != 1 && split != 2 && split != 4)
+    return fail(WLBM_EINVAL, "dir_split must be 0, 1, 2 or 4");
+  if (l->p.q % (kMaxGroupPlanes * split) != 0)
+    return fail(WLBM_EINVAL, "q = %d cannot be split over %d waves", l->p.q, split);
+  l->split = split;
+  return WLBM_OK;
+}
+
+int32_t wlbm_get_dir_split(const wlbm_lattice* l) { return l ? l->split : -1; }
+
+wlbm_status wlbm_batch_bytes(wlbm_lattice* const* lats, int32_t n, size_t* bytes) {
+  wlbm_status st = check_members(lats, n);
+  if (st) return st;
+  if (!bytes) return fail(WLBM_EINVAL, "bytes is NULL");
+  *bytes = batch_carve(n, lats[0]->p.q, lats[0]->chunk).total;
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, size_t bytes,
+                              void* stream, wlbm_batch** out) {
+  if (!out) return fail(WLBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  wlbm_status st = check_members(lats, n);
+  if (st) return st;
+  const BatchCarve bc = batch_carve(n, lats[0]->p.q, lats[0]->chunk);
+  if (!d_ws) return fail(WLBM_EINVAL, "batch workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
+    return fail(WLBM_EINVAL, "batch workspace must be 256-byte aligned");
+  if (bytes < bc.total)
+    return fail(WLBM_ENOMEM, "batch workspace too small: %zu bytes given, %zu needed", bytes,
+                bc.total);
+  wlbm_batch* b = new (std::nothrow) wlbm_batch();
+  if (!b) return fail(WLBM_ENOMEM, "host allocation failed");
+  b->lats.assign(lats, lats + n);
+  b->stream = static_cast<hipStream_t>(stream);
+  b->ws = static_cast<char*>(d_ws);
+  b->off_args = bc.args;
+  b->off_first = bc.first;
+  b->off_sched = bc.sched;
+  b->chunk = lats[0]->chunk;
+  const size_t stage = size_t(b->chunk) * lats[0]->p.q;
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->pinned[k]), stage, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming);
+  }
+  if (e == hipSuccess)
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->table), bc.first + size_t(n + 1) * sizeof(int),
+                      hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->table_ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)wlbm_batch_destroy(b);
+    return fail(WLBM_ENOMEM, "batch set-up failed: %s", hipGetErrorString(e));
+  }
+  *out = b;
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
+  if (!b) return fail(WLBM_EINVAL, "batch is NULL");
+  const int n = int(b->lats.size());
+  wlbm_status st = check_members(b->lats.data(), n);
+  if (st) return st;
+  wlbm_lattice* l0 = b->lats[0];
+  st = check_steps(l0, nsteps);
+  if (st) return st;
+  if (nsteps == 0) return WLBM_OK;
+  const int q = l0->p.q;
+  // argument table: lattice j, buffer parity p (p = 1 after an odd number of
+  // steps of this call); wall temperatures and fields as they are now.  The
+  // pinned staging copy of the previous call must have been consumed.
+  if (b->table_pending) {
+    hipError_t e = hipEventSynchronize(b->table_ev);
+    if (e != hipSuccess) return fail(WLBM_EHIP, "hipEventSynchronize failed: %s",
+                                     hipGetErrorString(e));
+    b->table_pending = false;
+  }
+  StepArgs* table = reinterpret_cast<StepArgs*>(b->table);
+  int* first = reinterpret_cast<int*>(b->table + b->off_first);
+  first[0] = 0;
+  for (int j = 0; j < n; ++j) {
+    wlbm_lattice* l = b->lats[j];
+    for (int par = 0; par < 2; ++par) {
+      StepArgs& a = table[size_t(2) * j + par];
+      const int in = l->cur ^ par;
+      a.e_in = l->ptr(l->c.e[in]);
+      a.e_out = l->ptr(l->c.e[1 - in]);
+      a.E_in = l->ptr(l->c.E[in]);
+      a.E_out = l->ptr(l->c.E[1 - in]);
+      a.Wf = l->ptr(l->c.Wf);
+      a.qsx = l->ptr(l->c.qsx);
+      a.qsy = l->ptr(l->c.qsy);
+      a.wtab = l->ptr(l->c.wtab);
+      a.sxtab = l->ptr(l->c.sxtab);
+      a.sytab = l->ptr(l->c.sytab);
+      a.W = l->W;
+      a.t_x_lo = l->walls.x_lo;
+      a.t_x_hi = l->walls.x_hi;
+      a.t_y_lo = l->walls.y_lo;
+      a.t_y_hi = l->walls.y_hi;
+      a.nx = l->g.nx;
+      a.ny = l->g.ny;
+      a.q = q;
+      a.pitch = l->g.pitch;
+      a.plane = l->g.plane;
+      a.x_edge = l->g.x_edge;
+      a.y_edge = l->g.y_edge;
+      a.tiles_x = tiles_x_for(l->g.nx);
+      a.ntiles = a.tiles_x * tiles_y_for(l->g.ny, l->split);
+    }
+    first[size_t(j) + 1] = first[size_t(j)] + table[size_t(2) * j].ntiles;
+  }
+  // the table and first[] sit at the same offsets in the staging buffer and
+  // in the workspace, so one copy moves both
+  HIP_TRY(hipMemcpyAsync(b->ws, b->table, b->off_first + size_t(n + 1) * sizeof(int),
+                         hipMemcpyHostToDevice, b->stream));
+  HIP_TRY(hipEventRecord(b->table_ev, b->stream));
+  b->table_pending = true;
+  BatchStepArgs ba{};
+  ba.lats = reinterpret_cast<const StepArgs*>(b->ws + b->off_args);
+  ba.first = reinterpret_cast<const int*>(b->ws + b->off_first);
+  ba.n = n;
+  ba.nblocks = first[size_t(n)];
+  const int64_t flux_from = l0->flux_window > 0 ? nsteps - l0->flux_window : nsteps;
+  TasState tas = l0->tas;
+  std::vector<int8_t> dx(q), dy(q);
+  std::vector<uint8_t> hop(q);
+  std::vector<float> insums;
+  int64_t done = 0;
+  while (done < nsteps) {
+    const int cnt = int(std::min<int64_t>(b->chunk, nsteps - done));
+    const int slot = int(b->chunk_counter & 1);
+    if (b->ev_pending[slot]) {
+      hipError_t e = hipEventSynchronize(b->ev[slot]);
+      if (e != hipSuccess) return fail(WLBM_EHIP, "hipEventSynchronize failed: %s",
+                                       hipGetErrorString(e));
+      b->ev_pending[slot] = false;
+    }
+    uint8_t* rows = b->pinned[slot];
+    insums.assign(size_t(cnt) * 4, 0.f);
+    for (int j = 0; j < cnt; ++j) {
+      tas_advance(l0->dirs, tas, dx.data(), dy.data(), hop.data());
+      for (wlbm_lattice* l : b->lats) l->book.note(tas);
+      double lo_h = 0, lo_a = 0, hi_h = 0, hi_a = 0;
+      for (int i = 0; i < q; ++i) {
+        rows[size_t(j) * q + i] = pack_code(dx[i], dy[i], hop[i]);
+        if (dy[i] == 1) {
+          lo_a += l0->dirs.w[i];
+          if (hop[i]) lo_h += l0->dirs.w[i];
+        } else if (dy[i] == -1) {
+          hi_a += l0->dirs.w[i];
+          if (hop[i]) hi_h += l0->dirs.w[i];
+        }
+      }
+      insums[4 * j] = float(lo_h);
+      insums[4 * j + 1] = float(lo_a);
+      insums[4 * j + 2] = float(hi_h);
+      insums[4 * j + 3] = float(hi_a);
+    }
+    uint8_t* dev_rows = reinterpret_cast<uint8_t*>(b->ws + b->off_sched) + size_t(slot) * b->chunk * q;
+    hipError_t e = hipMemcpyAsync(dev_rows, rows, size_t(cnt) * q, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipEventRecord(b->ev[slot], b->stream);
+    if (e != hipSuccess) return fail(WLBM_EHIP, "schedule upload failed: %s", hipGetErrorString(e));
+    b->ev_pending[slot] = true;
+    ++b->chunk_counter;
+    for (int j = 0; j < cnt; ++j) {
+      const int64_t k = done + j;
+      const bool flux = k >= flux_from;
+      ba.codes = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j) * q);
+      ba.in_lo_hop = insums[4 * j];
+      ba.in_lo_all = insums[4 * j + 1];
+      ba.in_hi_hop = insums[4 * j + 2];
+      ba.in_hi_all = insums[4 * j + 3];
+      ba.parity = int(k & 1);
+      ba.q_first = (flux && k == flux_from) ? 1 : 0;
+      e = launch_step_batch(ba, l0->split, l0->per_cell, flux, b->stream);
+      if (e != hipSuccess) {
+        for (wlbm_lattice* l : b->lats) l->broken = true;
+        return fail(WLBM_EHIP, "batch step launch failed: %s", hipGetErrorString(e));
+      }
+    }
+    done += cnt;
+  }
+  for (wlbm_lattice* l : b->lats) {
+    l->tas = tas;
+    l->cur ^= int(nsteps & 1);
+    l->flux_valid = l->flux_window > 0 && nsteps >= l->flux_window;
+  }
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_batch_destroy(wlbm_batch* b) {
+  if (!b) return WLBM_OK;
+  hipError_t e = hipStreamSynchronize(b->stream);
+  for (int k = 0; k < 2; ++k) {
+    if (b->pinned[k]) (void)hipHostFree(b->pinned[k]);
+    if (b->ev[k]) (void)hipEventDestroy(b->ev[k]);
+  }
+  if (b->table) (void)hipHostFree(b->table);
+  if (b->table_ev) (void)hipEventDestroy(b->table_ev);
+  delete b;
+  if (e != hipSuccess) return fail(WLBM_EHIP, "stream sync at destroy: %s", hipGetErrorString(e));
+  return WLBM_OK;
+}
+
+
+wlbm_status wlbm_autotune(wlbm_lattice* l, void* d_state, size_t bytes, int32_t steps,
+                          float* ms_by_split, int32_t* chosen) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (steps < 1 || steps > 10000) return fail(WLBM_EINVAL, "steps must be in 1 .. 10000");
+  if (l->tas.n + steps + 2 > kMaxSteps) return fail(WLBM_EINVAL, "step count would overflow");
+  const int64_t step0 = l->tas.n;
+  const bool flux_valid = l->flux_valid;
+  const int flux_window = l->flux_window;
+  const int keep_split = l->split;
+  st = wlbm_save_state(l, d_state, bytes);
+  if (st) return st;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(WLBM_EHIP, "hipEventCreate failed: %s", hipGetErrorString(he));
+  }
+  const int cand[3] = {1, 2, 4};
+  float best = 0.f;
+  int best_split = keep_split;
+  bool have = false;
+  l->flux_window = 0;  // the tuning steps leave the flux-window sums alone
+  for (int k = 0; k < 3 && st == WLBM_OK; ++k) {
+    float ms = -1.f;
+    if (l->p.q % (kMaxGroupPlanes * cand[k]) == 0) {
+      l->split = cand[k];
+      st = run_steps(l, 2, nullptr, 0);  // warm-up
+      if (!st && (he = hipEventRecord(e0, l->stream)) != hipSuccess)
+        st = fail(WLBM_EHIP, "hipEventRecord failed: %s", hipGetErrorString(he));
+      if (!st) st = run_steps(l, steps, nullptr, 0);
+      if (!st && (he = hipEventRecord(e1, l->stream)) != hipSuccess)
+        st = fail(WLBM_EHIP, "hipEventRecord failed: %s", hipGetErrorString(he));
+      if (!st && (he = hipEventSynchronize(e1)) != hipSuccess)
+        st = fail(WLBM_EHIP, "hipEventSynchronize failed: %s", hipGetErrorString(he));
+      if (!st && (he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+        st = fail(WLBM_EHIP, "hipEventElapsedTime failed: %s", hipGetErrorString(he));
+      if (!st) {
+        ms /= float(steps);
+        if (!have || ms < best) {
+          best = ms;
+          best_split = cand[k];
+          have = true;
+        }
+      }
+      if (!st) st = wlbm_load_state(l, d_state, bytes, step0);
+    }
+    if (ms_by_split) ms_by_split[k] = ms;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  l->flux_window = flux_window;
+  if (st) {
+    l->split = keep_split;
+    return st;
+  }
+  l->split = best_split;
+  l->flux_valid = flux_valid;
+  if (chosen) *chosen = best_split;
+  return WLBM_OK;
+}
+
+
+wlbm_status wlbm_read_flux_mean(wlbm_lattice* l, int32_t x0, int32_t x1, int32_t averaged,
+                                double* qx_mean, double* qy_mean) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (x0 < 0 || x1 > l->g.nx || x0 >= x1)
+    return fail(WLBM_EINVAL, "columns must satisfy 0 <= x0 < x1 <= nx");
+  if (averaged && !l->flux_valid)
+    return fail(WLBM_ESTATE, "no complete flux window: set one and step at least that far");
+  double* dev = reinterpret_cast<double*>(l->ws + l->c.totals);
+  HIP_TRY(launch_flux_sum(l->g, l->ptr(l->c.e[l->cur]), l->ptr(l->c.sxtab), l->ptr(l->c.sytab),
+                          l->ptr(l->c.qsx), l->ptr(l->c.qsy), averaged ? 1 : 0, x0, x1,
+                          reinterpret_cast<double*>(l->ws + l->c.partials), kReduceBlocks, dev,
+                          l->stream));
+  double h[3];
+  HIP_TRY(hipMemcpyAsync(h, dev, sizeof(h), hipMemcpyDeviceToHost, l->stream));
+  HIP_TRY(hipStreamSynchronize(l->stream));
+  const double scale = 1.0 / (double(x1 - x0) * l->g.ny * (averaged ? l->flux_window : 1));
+  if (qx_mean) *qx_mean = h[0] * scale;
+  if (qy_mean) *qy_mean = h[1] * scale;
+  if (!std::isfinite(h[0]) || !std::isfinite(h[1]))
+    return fail(WLBM_ENONFINITE, "non-finite flux sums");
+  return WLBM_OK;
+}
 
 int64_t wlbm_step_count(const wlbm_lattice* l) { return l ? l->tas.n : -1; }
 

@@ -77,6 +77,21 @@ hipError_t launch_step(const StepArgs& a, int split, bool per_cell, bool flux, h
 int tiles_x_for(int nx);
 int tiles_y_for(int ny, int split);
 
+// One time step of n lattices in one launch (same q, direction set and
+// schedule row).  lats holds, for each lattice j, its arguments for buffer
+// parity 0 and 1 ([2n], on the device); first[j] is the first block of
+// lattice j, first[n] = nblocks.  The per-step fields of StepArgs (codes,
+// wall sums, q_first) come from here.
+struct BatchStepArgs {
+  const StepArgs* lats;
+  const int* first;
+  const uint32_t* codes;
+  float in_lo_hop, in_lo_all, in_hi_hop, in_hi_all;
+  int n, nblocks, parity, q_first;
+};
+hipError_t launch_step_batch(const BatchStepArgs& b, int split, bool per_cell, bool flux,
+                             hipStream_t s);
+
 // e_i = w_i T0 (T0 unpadded [ny][nx]), blackbody walls, E, ghosts.
 hipError_t launch_init_temperature(const Geometry& g, const float* T0, float* e, float* E,
                                    const float* wtab, Walls walls, hipStream_t s);
@@ -93,6 +108,12 @@ hipError_t launch_scale_pair(int n, const float* ax, const float* ay, float scal
 hipError_t launch_totals(const Geometry& g, const float* e, const float* E, const float* sxtab,
                          const float* sytab, double* partials, int max_blocks, double* out,
                          hipStream_t s);
+// Float64 sums of q_x, q_y over columns x0 <= x < x1, all rows: out[0], out[1]
+// (out[2] = 0).  window != 0: from the flux-window sums qsx/qsy; else from e.
+hipError_t launch_flux_sum(const Geometry& g, const float* e, const float* sxtab,
+                           const float* sytab, const float* qsx, const float* qsy, int window,
+                           int x0, int x1, double* partials, int max_blocks, double* out,
+                           hipStream_t s);
 // Per-cell corrected weight from an MFP field: check pass (sets *flag on a
 // non-positive MFP or an unstable/non-finite weight), then write pass.
 hipError_t launch_check_mfp(const Geometry& g, const float* mfp, double lam, double f, int corr,

@@ -233,17 +233,27 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
   }
 }
 
+// LDS of one block of the step kernel.
 template <int NW, bool WF, bool FLUX>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_step(
-    const StepArgs a) {
+struct StepShared {
   using T = TileShape<NW>;
-  __shared__ float sE[T::LH * T::LP];
-  __shared__ float sW[WF ? T::LH * T::LP : 1];
-  __shared__ float sTg[2 * T::LP];
-  __shared__ float sWTg[2 * T::LP];
-  __shared__ float sRed[NW > 1 ? (FLUX ? 3 : 1) * kBlock : 1];
+  float sE[T::LH * T::LP];
+  float sW[WF ? T::LH * T::LP : 1];
+  float sTg[2 * T::LP];
+  float sWTg[2 * T::LP];
+  float sRed[NW > 1 ? (FLUX ? 3 : 1) * kBlock : 1];
+};
 
-  const int t = xcd_tile(blockIdx.x, gridDim.x);
+// One block's tile t of one time step of lattice a.
+template <int NW, bool WF, bool FLUX>
+__device__ __forceinline__ void step_tile(const StepArgs& a, int t,
+                                          StepShared<NW, WF, FLUX>& sh) {
+  using T = TileShape<NW>;
+  float* sE = sh.sE;
+  float* sW = sh.sW;
+  float* sTg = sh.sTg;
+  float* sWTg = sh.sWTg;
+  float* sRed = sh.sRed;
   const int tx = t % a.tiles_x;
   const int ty = t / a.tiles_x;
   const int x0 = tx * T::TX;
@@ -298,6 +308,36 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     sweep<NW, WF, FLUX, true>(a, sE, sW, sTg, sWTg, sRed, x0, y0, boff, v0);
   else
     sweep<NW, WF, FLUX, false>(a, sE, sW, sTg, sWTg, sRed, x0, y0, boff, v0);
+}
+
+template <int NW, bool WF, bool FLUX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_step(
+    const StepArgs a) {
+  __shared__ StepShared<NW, WF, FLUX> sh;
+  step_tile<NW, WF, FLUX>(a, xcd_tile(blockIdx.x, gridDim.x), sh);
+}
+
+// One time step of several lattices in one launch.  The tiles of lattice j
+// are blocks first[j] .. first[j+1]-1 of the (XCD-remapped) grid; each block
+// reads its lattice's arguments for the current buffer parity from the table
+// through the scalar cache and runs the same tile code as k_step.
+template <int NW, bool WF, bool FLUX>
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_step_batch(
+    const BatchStepArgs b) {
+  __shared__ StepShared<NW, WF, FLUX> sh;
+  const int g = xcd_tile(blockIdx.x, gridDim.x);
+  const WLBM_CONST int* first = scalar_ptr(b.first);
+  int j = 0;
+  while (j + 1 < b.n && g >= first[j + 1]) ++j;
+  j = __builtin_amdgcn_readfirstlane(j);
+  StepArgs a = b.lats[2 * j + b.parity];
+  a.codes = b.codes;
+  a.in_lo_hop = b.in_lo_hop;
+  a.in_lo_all = b.in_lo_all;
+  a.in_hi_hop = b.in_hi_hop;
+  a.in_hi_all = b.in_hi_all;
+  a.q_first = b.q_first;
+  step_tile<NW, WF, FLUX>(a, g - first[j], sh);
 }
 
 template <int NW, bool WF, bool FLUX>
@@ -452,6 +492,41 @@ __global__ __launch_bounds__(kBlock) void k_totals_final(const double* partials,
   block_sum3(sh, a, b, c, out);
 }
 
+// Sums of the heat flux over the columns x0 <= x < x1 (all rows), in
+// float64: from the flux-window sums (window mode) or from the populations.
+__global__ __launch_bounds__(kBlock) void k_flux_sum_partial(const Geometry g, const float* e,
+                                                            const float* sxtab,
+                                                            const float* sytab,
+                                                            const float* qsx, const float* qsy,
+                                                            int window, int x0, int x1,
+                                                            double* partials) {
+  __shared__ double sh[3 * kBlock];
+  const int w = x1 - x0;
+  const long long n = (long long)w * g.ny;
+  double sx = 0.0, sy = 0.0;
+  for (long long c = (long long)blockIdx.x * kBlock + threadIdx.x; c < n;
+       c += (long long)gridDim.x * kBlock) {
+    const int x = x0 + int(c % w);
+    const int y = int(c / w);
+    if (window) {
+      const long long o = (long long)y * g.nx + x;
+      sx += double(qsx[o]);
+      sy += double(qsy[o]);
+    } else {
+      const long long o = cell(x, y, g.pitch);
+      double ax = 0.0, ay = 0.0;
+      for (int i = 0; i < g.q; ++i) {
+        const double v = e[(long long)i * g.plane + o];
+        ax += v * double(sxtab[i]);
+        ay += v * double(sytab[i]);
+      }
+      sx += ax;
+      sy += ay;
+    }
+  }
+  block_sum3(sh, sx, sy, 0.0, partials + 3 * blockIdx.x);
+}
+
 __device__ __forceinline__ double corrected(double mfp, double lam, double f, int corr) {
   const double W = isinf(mfp) ? 0.0 : 1.0 / mfp;
   if (!corr) return W;
@@ -496,11 +571,34 @@ int tiles_y_for(int ny, int split) {
   return (ny + ty - 1) / ty;
 }
 
+template <int NW, bool WF, bool FLUX>
+hipError_t launch_batch_tmpl(const BatchStepArgs& b, hipStream_t s) {
+  hipLaunchKernelGGL((k_step_batch<NW, WF, FLUX>), dim3(b.nblocks), dim3(kBlock), 0, s, b);
+  return hipGetLastError();
+}
+
+template <int NW>
+hipError_t launch_batch_nw(const BatchStepArgs& b, bool wf, bool fl, hipStream_t s) {
+  if (wf)
+    return fl ? launch_batch_tmpl<NW, true, true>(b, s) : launch_batch_tmpl<NW, true, false>(b, s);
+  return fl ? launch_batch_tmpl<NW, false, true>(b, s) : launch_batch_tmpl<NW, false, false>(b, s);
+}
+
 hipError_t launch_step(const StepArgs& a, int split, bool per_cell, bool flux, hipStream_t s) {
   switch (split) {
     case 1: return launch_nw<1>(a, per_cell, flux, s);
     case 2: return launch_nw<2>(a, per_cell, flux, s);
     case 4: return launch_nw<4>(a, per_cell, flux, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_step_batch(const BatchStepArgs& b, int split, bool per_cell, bool flux,
+                             hipStream_t s) {
+  switch (split) {
+    case 1: return launch_batch_nw<1>(b, per_cell, flux, s);
+    case 2: return launch_batch_nw<2>(b, per_cell, flux, s);
+    case 4: return launch_batch_nw<4>(b, per_cell, flux, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -551,6 +649,20 @@ hipError_t launch_totals(const Geometry& g, const float* e, const float* E, cons
   const int nb = int(need < max_blocks ? need : max_blocks);
   hipLaunchKernelGGL(k_totals_partial, dim3(nb), dim3(kBlock), 0, s, g, e, E, sxtab, sytab,
                      partials);
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return err;
+  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(kBlock), 0, s, partials, nb, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_sum(const Geometry& g, const float* e, const float* sxtab,
+                           const float* sytab, const float* qsx, const float* qsy, int window,
+                           int x0, int x1, double* partials, int max_blocks, double* out,
+                           hipStream_t s) {
+  const long long need = ((long long)(x1 - x0) * g.ny + kBlock - 1) / kBlock;
+  const int nb = int(need < max_blocks ? need : max_blocks);
+  hipLaunchKernelGGL(k_flux_sum_partial, dim3(nb), dim3(kBlock), 0, s, g, e, sxtab, sytab, qsx,
+                     qsy, window, x0, x1, partials);
   hipError_t err = hipGetLastError();
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(kBlock), 0, s, partials, nb, out);

@@ -1,0 +1,152 @@
+"""In-plane conductivity of thin films versus Knudsen number (Sec. 3.4).
+
+A film of thickness Ny cells with adiabatic diffuse walls (y) is held
+between blackbody columns x = 0 (T = 1) and x = Nx - 1 (T = 0), starting
+from T0 = 0.  The effective conductivity follows from the heat flux averaged
+over the last ten steps (Sec. 3.4), over the interior columns:
+kappa_eff = <q_x> (Nx - 1) / (T_h - T_c), against the bulk kappa = Lambda / 2
+of the 2D gray model (unit heat capacity and group velocity).
+
+The sweep: 24 films, Nx = 512, Q = 128 evenly spaced directions,
+Kn_j = 10^(-2 + 4j/23) per film thickness (MFP = Kn Ny cells), Ny_j drawn by
+default_rng(180) from the thicknesses in {32, 64, 128, 256} for which the
+MFP is at least one cell (W <= 1).  All films advance together through a
+Batch (one kernel launch per step for all 24); `step_each` advances them one
+after another for comparison.
+
+    python -m paper_1911_00180_amd.films [--steps N] [--steady]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+import torch
+
+from .lattice import Batch, Lattice
+
+THICKNESSES = (32, 64, 128, 256)
+
+
+def film_set(n: int = 24, seed: int = 180):
+    """[(Kn, Ny, MFP in cells)] of the sweep."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for j in range(n):
+        kn = 10.0 ** (-2.0 + 4.0 * j / (n - 1))
+        ok = [t for t in THICKNESSES if kn * t >= 1.0]
+        ny = int(rng.choice(ok))
+        out.append((kn, ny, kn * ny))
+    return out
+
+
+class FilmSweep:
+    def __init__(self, films, nx: int = 512, q: int = 128, window: int = 10,
+                 device="cuda", t_hot: float = 1.0, t_cold: float = 0.0, dir_split: int = 0):
+        self.films = list(films)
+        self.nx, self.q, self.window = nx, q, window
+        self.t_hot, self.t_cold = t_hot, t_cold
+        self.lattices = []
+        for kn, ny, mfp in self.films:
+            lat = Lattice(nx, ny, q, mfp=mfp, device=device, x_edge="blackbody",
+                          y_edge="diffuse", t_x_lo=t_hot, t_x_hi=t_cold, dir_split=dir_split)
+            lat.set_temperature(torch.zeros((ny, nx)))
+            lat.set_flux_window(window)
+            self.lattices.append(lat)
+        self.batch = Batch(self.lattices)
+
+    @property
+    def updates_per_step(self) -> int:
+        return sum(self.nx * ny * self.q for _, ny, _ in self.films)
+
+    def step_batched(self, n: int) -> None:
+        self.batch.step(n)
+
+    def step_each(self, n: int) -> None:
+        for lat in self.lattices:
+            lat.step(n)
+
+    def kappa_ratios(self):
+        """kappa_eff / kappa of every film from the last flux window."""
+        out = []
+        for (kn, ny, mfp), lat in zip(self.films, self.lattices):
+            qx, _ = lat.flux_mean(1, self.nx - 1, averaged=True)
+            out.append(qx * (self.nx - 1) / (self.t_hot - self.t_cold) / (mfp / 2.0))
+        return out
+
+    def run_to_steady(self, check_every: int = 1000, rtol: float = 1e-6,
+                      max_steps: int = 2_000_000):
+        """Step (batched) until kappa changes by less than rtol between checks
+        for every film; films that have converged leave the batch."""
+        active = list(range(len(self.films)))
+        last = [None] * len(self.films)
+        steps = [0] * len(self.films)
+        done_k = [None] * len(self.films)
+        batch = self.batch
+        total = 0
+        while active and total < max_steps:
+            batch.step(check_every)
+            total += check_every
+            ks = self.kappa_ratios()
+            still = []
+            for j in active:
+                steps[j] = total
+                if last[j] is not None and abs(ks[j] - last[j]) <= rtol * abs(ks[j]):
+                    done_k[j] = ks[j]
+                else:
+                    still.append(j)
+                last[j] = ks[j]
+            if still != active and still:
+                batch.close()
+                batch = Batch([self.lattices[j] for j in still])
+            active = still
+        if batch is not self.batch:
+            batch.close()
+        for j in active:
+            done_k[j] = last[j]
+        return done_k, steps, not active
+
+    def close(self) -> None:
+        self.batch.close()
+        for lat in self.lattices:
+            lat.close()
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--steps", type=int, default=10000, help="fixed steps for the timing")
+    ap.add_argument("--steady", action="store_true", help="also run every film to steady state")
+    args = ap.parse_args()
+    films = film_set()
+    sweep = FilmSweep(films)
+    sweep.step_batched(10)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    sweep.step_batched(args.steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    other = FilmSweep(films)
+    other.step_each(10)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    other.step_each(args.steps)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t
+    res = {"films": [{"kn": kn, "ny": ny, "mfp": mfp} for kn, ny, mfp in films],
+           "steps": args.steps, "batched_s": tb, "one_by_one_s": te,
+           "batched_gups": sweep.updates_per_step * args.steps / tb / 1e9,
+           "one_by_one_gups": sweep.updates_per_step * args.steps / te / 1e9}
+    other.close()
+    if args.steady:
+        k, steps, ok = sweep.run_to_steady()
+        res["kappa_ratio"] = k
+        res["steady_steps"] = steps
+        res["all_converged"] = ok
+    sweep.close()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -128,9 +128,60 @@ class Lattice:
         W.wlbm_read_probes(self.handle, cells.shape[0], cells.data_ptr(), out.data_ptr())
         return out
 
+    # -- launch configuration -------------------------------------------------
+    @property
+    def dir_split(self) -> int:
+        return W.wlbm_get_dir_split(self.handle)
+
+    def set_dir_split(self, split: int) -> None:
+        W.wlbm_set_dir_split(self.handle, split)
+
+    def autotune(self, steps: int = 20):
+        """Keep the fastest direction split; returns (ms per step for splits
+        1, 2, 4, chosen split).  The state is restored afterwards."""
+        self._sync_stream()
+        buf = torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
+        return W.wlbm_autotune(self.handle, buf.data_ptr(), buf.numel(), steps)
+
+    def flux_mean(self, x0: int = 0, x1: int | None = None, averaged: bool = True):
+        """Mean (q_x, q_y) over columns x0 <= x < x1, float64."""
+        self._sync_stream()
+        return W.wlbm_read_flux_mean(self.handle, x0, self.nx if x1 is None else x1,
+                                     int(averaged))
+
     def close(self) -> None:
         if getattr(self, "handle", None):
             W.wlbm_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Lattices advanced together, one kernel launch per step (same q,
+    direction set, step count, split and flux window)."""
+
+    def __init__(self, lattices):
+        self.lattices = list(lattices)
+        self.device = self.lattices[0].device
+        handles = [lat.handle for lat in self.lattices]
+        nbytes = W.wlbm_batch_bytes(handles)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.handle = W.wlbm_batch_create(handles, self.workspace.data_ptr(), nbytes,
+                                          torch.cuda.current_stream(self.device).cuda_stream)
+
+    def step(self, n: int = 1) -> None:
+        for lat in self.lattices:
+            lat._sync_stream()
+        W.wlbm_batch_step(self.handle, n)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            W.wlbm_batch_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -41,6 +41,8 @@ EXPORTS = (
     "wlbm_state_bytes", "wlbm_save_state", "wlbm_load_state", "wlbm_step_tape",
     "wlbm_read_probes", "wlbm_adjoint_bytes", "wlbm_adjoint_begin", "wlbm_adjoint_seed",
     "wlbm_adjoint_steps", "wlbm_adjoint_read", "wlbm_adjoint_step_index",
+    "wlbm_set_dir_split", "wlbm_get_dir_split", "wlbm_autotune", "wlbm_batch_bytes",
+    "wlbm_batch_create", "wlbm_batch_step", "wlbm_batch_destroy", "wlbm_read_flux_mean",
 )
 
 
@@ -111,6 +113,17 @@ def lib() -> ctypes.CDLL:
         "wlbm_adjoint_steps": (c_int, [c_void_p, c_int64, c_void_p, c_size_t]),
         "wlbm_adjoint_read": (c_int, [c_void_p, c_void_p, c_void_p, POINTER(c_double)]),
         "wlbm_adjoint_step_index": (c_int64, [c_void_p]),
+        "wlbm_set_dir_split": (c_int, [c_void_p, c_int32]),
+        "wlbm_get_dir_split": (c_int32, [c_void_p]),
+        "wlbm_autotune": (c_int, [c_void_p, c_void_p, c_size_t, c_int32, POINTER(ctypes.c_float),
+                                  POINTER(c_int32)]),
+        "wlbm_batch_bytes": (c_int, [POINTER(c_void_p), c_int32, POINTER(c_size_t)]),
+        "wlbm_batch_create": (c_int, [POINTER(c_void_p), c_int32, c_void_p, c_size_t, c_void_p,
+                                      POINTER(c_void_p)]),
+        "wlbm_batch_step": (c_int, [c_void_p, c_int64]),
+        "wlbm_batch_destroy": (c_int, [c_void_p]),
+        "wlbm_read_flux_mean": (c_int, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double),
+                                        POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -289,6 +302,54 @@ def wlbm_adjoint_read(h: int, d_g_mfp, d_g_T0):
 
 def wlbm_adjoint_step_index(h: int) -> int:
     return lib().wlbm_adjoint_step_index(c_void_p(h))
+
+
+def wlbm_set_dir_split(h: int, split: int) -> None:
+    _check(lib().wlbm_set_dir_split(c_void_p(h), split))
+
+
+def wlbm_get_dir_split(h: int) -> int:
+    return lib().wlbm_get_dir_split(c_void_p(h))
+
+
+def wlbm_autotune(h: int, d_state, nbytes: int, steps: int):
+    """(ms per step for splits 1, 2, 4 (-1 if invalid), chosen split)."""
+    ms = (ctypes.c_float * 3)()
+    chosen = c_int32(0)
+    _check(lib().wlbm_autotune(c_void_p(h), _ptr(d_state), nbytes, steps, ms, byref(chosen)))
+    return tuple(ms), chosen.value
+
+
+def _handles(hs):
+    arr = (c_void_p * len(hs))(*[c_void_p(h) for h in hs])
+    return arr
+
+
+def wlbm_batch_bytes(handles) -> int:
+    n = c_size_t(0)
+    _check(lib().wlbm_batch_bytes(_handles(handles), len(handles), byref(n)))
+    return n.value
+
+
+def wlbm_batch_create(handles, d_ws, nbytes: int, stream) -> int:
+    b = c_void_p()
+    _check(lib().wlbm_batch_create(_handles(handles), len(handles), _ptr(d_ws), nbytes,
+                                   c_void_p(stream or 0), byref(b)))
+    return b.value
+
+
+def wlbm_batch_step(b: int, nsteps: int) -> None:
+    _check(lib().wlbm_batch_step(c_void_p(b), nsteps))
+
+
+def wlbm_batch_destroy(b: int) -> None:
+    _check(lib().wlbm_batch_destroy(c_void_p(b)))
+
+
+def wlbm_read_flux_mean(h: int, x0: int, x1: int, averaged: int = 1):
+    qx, qy = c_double(), c_double()
+    _check(lib().wlbm_read_flux_mean(c_void_p(h), x0, x1, averaged, byref(qx), byref(qy)))
+    return qx.value, qy.value
 
 
 def make_params(nx: int, ny: int, q: int, mfp: float = float("inf"), dirs: str = "uniform",

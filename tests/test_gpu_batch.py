@@ -1,0 +1,136 @@
+"""Batched stepping, the split autotuner and the film readout on the GPU.
+
+A batch step runs the same tile code as a single-lattice step, so batched
+and one-by-one runs must agree bit for bit.  The film conductivity is
+checked against the FP64 oracle (oracle/film.py): the window-averaged
+column flux within 1e-5 of the wall temperature difference (the flux is a
+sum of terms of either sign, so its error is measured against the
+temperature scale, as for every flux check).
+"""
+import numpy as np
+import pytest
+
+from oracle import film as ofilm
+from oracle import worm_lbm as o
+from paper_1911_00180_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_00180_amd import wormlbm
+    wormlbm.lib()
+
+
+MIXED = [
+    dict(nx=70, ny=45, mfp=6.0, x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0),
+    dict(nx=64, ny=64, mfp=20.0),
+    dict(nx=131, ny=9, mfp=3.0, x_edge="periodic", y_edge="blackbody", t_y_lo=0.5),
+    dict(nx=33, ny=100, mfp=1e4, x_edge="blackbody", y_edge="periodic", t_x_hi=2.0),
+    dict(nx=200, ny=17, mfp=2.5, x_edge="blackbody", y_edge="blackbody", t_x_lo=1.0,
+         t_y_hi=0.25),
+]
+
+
+def _make(q, cfg, seed, **kw):
+    from paper_1911_00180_amd.lattice import Lattice
+    lat = Lattice(cfg["nx"], cfg["ny"], q, **{k: v for k, v in cfg.items() if k not in
+                                               ("nx", "ny")}, **kw)
+    lat.set_populations(torch.from_numpy(inputs.random_populations(seed, q, cfg["ny"],
+                                                                   cfg["nx"])))
+    return lat
+
+
+@pytest.mark.parametrize("q,split", [(16, 0), (32, 4), (24, 1)])
+def test_batch_equals_one_by_one(q, split):
+    from paper_1911_00180_amd.lattice import Batch
+    kw = dict(dir_split=split, sched_chunk=16)
+    a = [_make(q, c, 10 + k, **kw) for k, c in enumerate(MIXED)]
+    b = [_make(q, c, 10 + k, **kw) for k, c in enumerate(MIXED)]
+    for lat in a + b:
+        lat.set_flux_window(5)
+    batch = Batch(a)
+    batch.step(37)          # crosses two schedule chunks, ends on odd parity
+    batch.step(6)
+    for lat in b:
+        lat.step(37)
+        lat.step(6)
+    for x, y in zip(a, b):
+        assert x.step_count == y.step_count == 43
+        assert torch.equal(x.populations(), y.populations())
+        assert torch.equal(x.temperature(), y.temperature())
+        for u, v in zip(x.heat_flux(averaged=True), y.heat_flux(averaged=True)):
+            assert torch.equal(u, v)
+        assert x.flux_mean(averaged=True) == y.flux_mean(averaged=True)
+    batch.close()
+    for lat in a + b:
+        lat.close()
+
+
+def test_batch_rejects_mismatched_lattices():
+    from paper_1911_00180_amd import wormlbm as W
+    from paper_1911_00180_amd.lattice import Batch
+    a = _make(16, MIXED[0], 1)
+    b = _make(32, MIXED[1], 2)
+    with pytest.raises(W.WormLBMError):
+        Batch([a, b])
+    c = _make(16, MIXED[1], 3)
+    c.step(1)
+    with pytest.raises(W.WormLBMError):
+        Batch([a, c])
+    with pytest.raises(W.WormLBMError):
+        Batch([a, a])
+    for lat in (a, b, c):
+        lat.close()
+
+
+def test_autotune_restores_state_and_keeps_a_valid_split():
+    lat = _make(64, dict(nx=300, ny=200, mfp=12.0, x_edge="blackbody", y_edge="diffuse",
+                         t_x_lo=1.0), 4)
+    lat.step(7)
+    before = lat.populations()
+    ms, chosen = lat.autotune(steps=5)
+    assert chosen in (1, 2, 4) and lat.dir_split == chosen
+    assert all(m > 0 for m in ms)
+    assert lat.step_count == 7
+    assert torch.equal(lat.populations(), before)
+    lat.close()
+
+
+@pytest.mark.parametrize("kn,ny", [(0.3, 8), (2.0, 12), (20.0, 16)])
+def test_film_flux_matches_oracle(kn, ny):
+    from paper_1911_00180_amd.films import FilmSweep
+    nx, q, n = 48, 16, 1500
+    sweep = FilmSweep([(kn, ny, kn * ny)], nx=nx, q=q)
+    sweep.step_batched(n)
+    qx, _ = sweep.lattices[0].flux_mean(1, nx - 1, averaged=True)
+    cfg = o.Config(nx=nx, ny=ny, q=q, mfp=kn * ny, x_edge="blackbody", y_edge="diffuse",
+                   t_x_lo=1.0, t_x_hi=0.0)
+    _, oqx, _ = ofilm.film_run(cfg, n, window=10)
+    assert abs(qx - float(np.mean(oqx[:, 1:nx - 1]))) <= 1e-5
+    k = sweep.kappa_ratios()[0]
+    assert k == pytest.approx(ofilm.kappa_ratio(cfg, oqx), abs=1e-5 * (nx - 1) / (kn * ny / 2))
+    sweep.close()
+
+
+def test_film_sweep_full_size_batched_equals_one_by_one():
+    """The 24-film sweep at full size (Nx = 512, Q = 128) in the launch
+    configuration the bench times: batched and one-by-one agree bit for bit."""
+    from paper_1911_00180_amd.films import FilmSweep, film_set
+    films = film_set()
+    a = FilmSweep(films)
+    b = FilmSweep(films)
+    a.step_batched(60)
+    b.step_each(60)
+    for x, y in zip(a.lattices, b.lattices):
+        assert torch.equal(x.temperature(), y.temperature())
+    ka, kb = a.kappa_ratios(), b.kappa_ratios()
+    assert ka == kb
+    assert all(np.isfinite(ka))
+    a.close()
+    b.close()
