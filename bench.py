@@ -192,6 +192,35 @@ def run_adjoint_kernel(nx=1024, ny=1024, q=64, steps=20):
             "traffic": recorded_traffic(ADJOINT_TRAFFIC_FILE, ADJOINT_SOURCES)}
 
 
+def run_films(steps=10000):
+    """The 24-film sweep (Nx = 512, Q = 128, Ny 32..256, blackbody x, diffuse
+    y): fixed steps batched (one launch per step) against one-by-one."""
+    import torch
+
+    from paper_1911_00180_amd.films import FilmSweep, film_set
+
+    films = film_set()
+    out = {"workload": "24 films, Nx=512, Q=128, Ny from {32,64,128,256}, Kn 0.01..100, "
+                       f"blackbody x 1/0, diffuse y, {steps} steps"}
+    stream = torch.cuda.current_stream()
+    for mode in ("batched", "one_by_one"):
+        sw = FilmSweep(films)
+        go = sw.step_batched if mode == "batched" else sw.step_each
+        go(20)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        go(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        out[mode + "_ms_per_step"] = round(ms / steps, 5)
+        out[mode + "_gups"] = round(sw.updates_per_step * steps / (ms * 1e-3) / 1e9, 2)
+        sw.close()
+    out["speedup"] = round(out["one_by_one_ms_per_step"] / out["batched_ms_per_step"], 3)
+    return out
+
+
 def cpu_baseline(budget_s: float = 15.0):
     """The FP64 oracle on a bounded sample of the same workload: a 256 x 256
     periodic crop with the same Q and MFP, timed on the host."""
@@ -237,6 +266,8 @@ def main():
     ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurements")
+    ap.add_argument("--no-films", action="store_true", help="skip the batched film sweep")
+    ap.add_argument("--film-steps", type=int, default=10000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this size (counter calibration)")
@@ -323,6 +354,8 @@ def main():
         adj = run_adjoint_ratio()
         adj["kernel"] = run_adjoint_kernel()
         out["adjoint"] = adj
+    if not args.no_films:
+        out["films"] = run_films(args.film_steps)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(out), flush=True)
