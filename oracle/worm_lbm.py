@@ -291,6 +291,13 @@ class Config:
     t_x_hi: float = 0.0
     t_y_lo: float = 0.0
     t_y_hi: float = 0.0
+    # fraction of what crosses a DIFFUSE y wall that is reflected specularly
+    # (Eq. adiabatic-specular); the rest is scattered diffusely
+    y_specularity: float = 0.0
+    # internal sources (Eq. isotropic, Eq. anisotropic): cells [S, 2] (x, y)
+    # whose DDEDs are overwritten every step by values [S, q]
+    source_cells: np.ndarray | None = None
+    source_values: np.ndarray | None = None
 
 
 @dataclass
@@ -323,9 +330,19 @@ class Lattice:
             Wc = W                   # the uncorrected scheme compared in Fig. 3
         if np.any(Wc > 1.0):                                    # App. A: W <= 1
             raise ValueError("unstable: corrected relaxation weight exceeds 1")
+        if not 0.0 <= c.y_specularity <= 1.0:
+            raise ValueError("y_specularity must lie in [0, 1]")
+        # mirror image of each direction in a y wall: (sx, sy) -> (sx, -sy)
+        self.mirror_y = np.array([self._find(d.sx, -d.sy) for d in self.dirs])
         self.Wc = float(Wc) if Wc.ndim == 0 else Wc
         self.e = np.zeros((c.q, c.ny, c.nx))
         self._sched = None
+
+    def _find(self, sx: float, sy: float) -> int:
+        for j, d in enumerate(self.dirs):
+            if abs(d.sx - sx) < 1e-12 and abs(d.sy - sy) < 1e-12:
+                return j
+        raise ValueError("direction set is not symmetric under a y mirror")
 
     # -- state ------------------------------------------------------------
     def set_temperature(self, T0: np.ndarray) -> None:
@@ -333,6 +350,7 @@ class Lattice:
         Linear gray model e_eq = T (reading; see temperature())."""
         self.e = self.w[:, None, None] * np.asarray(T0, dtype=np.float64)[None]
         self._apply_blackbody(self.e)
+        self._apply_sources(self.e)
 
     def set_populations(self, e: np.ndarray) -> None:
         self.e = np.array(e, dtype=np.float64)
@@ -385,6 +403,17 @@ class Lattice:
             e[:, :, 0] = w * c.t_x_lo
             e[:, :, c.nx - 1] = w * c.t_x_hi
 
+    def _apply_sources(self, e: np.ndarray) -> None:
+        """Internal sources (Sec. 2.6, Eq. isotropic and Eq. anisotropic): the
+        DDEDs of each source cell are overwritten by the imposed distribution
+        at every step.  Reading: after the blackbody walls, so a source on a
+        wall cell wins."""
+        c = self.cfg
+        if c.source_cells is None:
+            return
+        for (x, y), vals in zip(np.asarray(c.source_cells), np.asarray(c.source_values)):
+            e[:, int(y), int(x)] = vals
+
     def step(self) -> None:
         """Advance one time step n -> n+1 (push form).
 
@@ -413,6 +442,7 @@ class Lattice:
         new = np.zeros_like(self.e)
         r_lo = np.zeros(c.nx)
         r_hi = np.zeros(c.nx)
+        p = c.y_specularity
         for i in range(c.q):
             sx, sy = D2Q8[int(mv[i])]
             acc = np.zeros((c.ny + 2, c.nx + 2))
@@ -424,13 +454,22 @@ class Lattice:
                 self._deposit(acc, dded, 0, 0)
             self._deposit(acc, eed, sx, sy)
             inside, lo, hi = self._fold(acc)
-            new[i] = inside
+            new[i] += inside
             if lo is not None:
-                r_lo += lo
-                r_hi += hi
+                r_lo += (1.0 - p) * lo
+                r_hi += (1.0 - p) * hi
+                if p > 0.0:
+                    # Reading (Eq. adiabatic-specular): a packet that crosses
+                    # the wall at y = -1/2 (ny - 1/2) is reflected there and
+                    # ends the step in the wall-row cell it crossed under, in
+                    # the mirrored direction.
+                    j = self.mirror_y[i]
+                    new[j, 0, :] += p * lo
+                    new[j, c.ny - 1, :] += p * hi
         if c.y_edge == DIFFUSE:
             self._diffuse(new, r_lo, r_hi, mv, hp)
         self._apply_blackbody(new)
+        self._apply_sources(new)
         self.e = new
         self.n = n
 
@@ -453,6 +492,10 @@ class Lattice:
         Reading (corners): the boundary node below or above a blackbody column
         belongs to the blackbody wall and emits at its temperature, as the
         blackbody overwrite wins at the corner cells themselves.
+        Reading (specular-diffuse walls): r_lo / r_hi hold only the diffuse
+        share (1 - p) of what crossed; the corner nodes emit that share of
+        the wall temperature, so a fully specular wall (p = 1) emits nothing
+        of its own and equals the mirror image of the domain.
         """
         c = self.cfg
         nx, ny = c.nx, c.ny
@@ -469,8 +512,8 @@ class Lattice:
                     crossing.append((i, sx, a))
             Tg = r / C
             if c.x_edge == BLACKBODY:
-                Tg[0] = c.t_x_lo
-                Tg[nx - 1] = c.t_x_hi
+                Tg[0] = (1.0 - c.y_specularity) * c.t_x_lo
+                Tg[nx - 1] = (1.0 - c.y_specularity) * c.t_x_hi
             for i, sx, a in crossing:
                 acc = np.zeros(nx + 2)
                 acc[1 + sx:1 + sx + nx] += a * Tg
@@ -530,6 +573,18 @@ def ballistic_temperature(T0: np.ndarray, w: np.ndarray, pos: np.ndarray) -> np.
     for i in range(len(w)):
         out += w[i] * np.roll(T0, shift=(int(pos[i, 1]), int(pos[i, 0])), axis=(0, 1))
     return out
+
+
+def flux_distribution(dirs: list[Direction], w: np.ndarray, T: float, q) -> np.ndarray:
+    """DDEDs of a flux boundary or source (Sec. 2.6, Eq. lbm-heat-flux): the
+    paper asks for the DDEDs to be prescribed uniquely; reading: the
+    distribution linear in the direction, e_i = w_i (T + s_i . a), whose
+    energy is T and whose flux sum_i e_i s_i is q, i.e. a = M^{-1} q with
+    M = sum_i w_i s_i s_i^T (symmetric direction sets have sum_i w_i s_i = 0)."""
+    S = np.array([[d.sx, d.sy] for d in dirs])
+    M = (S * np.asarray(w)[:, None]).T @ S
+    a = np.linalg.solve(M, np.asarray(q, dtype=np.float64))
+    return np.asarray(w) * (T + S @ a)
 
 
 def growth_factor(W: float, k: float, paused: bool) -> complex:

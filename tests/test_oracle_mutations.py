@@ -73,6 +73,24 @@ MUTATIONS = {
         "        if c.x_edge == BLACKBODY:\n            e[:, :, 0] = w * c.t_x_lo\n"
         "            e[:, :, c.nx - 1] = w * c.t_x_hi\n        if c.y_edge == BLACKBODY:\n"
         "            e[:, 0, :] = w * c.t_y_lo\n            e[:, c.ny - 1, :] = w * c.t_y_hi"),
+    "specular_mirrors_wrong_axis": (
+        "[self._find(d.sx, -d.sy) for d in self.dirs]",
+        "[self._find(-d.sx, d.sy) for d in self.dirs]"),
+    "specular_lands_one_row_in": (
+        "new[j, 0, :] += p * lo",
+        "new[j, 1, :] += p * lo"),
+    "specular_share_also_diffused": (
+        "r_lo += (1.0 - p) * lo",
+        "r_lo += lo"),
+    "corner_node_ignores_specularity": (
+        "Tg[0] = (1.0 - c.y_specularity) * c.t_x_lo",
+        "Tg[0] = c.t_x_lo"),
+    "sources_before_blackbody": (
+        "        self._apply_blackbody(new)\n        self._apply_sources(new)",
+        "        self._apply_sources(new)\n        self._apply_blackbody(new)"),
+    "sources_not_imposed_at_start": (
+        "        self._apply_blackbody(self.e)\n        self._apply_sources(self.e)",
+        "        self._apply_blackbody(self.e)"),
 }
 
 
@@ -107,13 +125,27 @@ def _consistency_checks(o):
         checks.o = saved
 
 
+def _wall_source_checks(o):
+    """The specular-wall and source pins of test_oracle_walls_sources."""
+    import test_oracle_walls_sources as wchecks
+    saved = wchecks.o
+    wchecks.o = o
+    try:
+        wchecks.test_specular_film_equals_mirrored_periodic_film(16, "uniform", "blackbody")
+        wchecks.test_specular_diffuse_conserves_energy_and_keeps_equilibrium(0.35)
+        wchecks.test_source_wins_over_blackbody_wall_and_is_imposed_at_start()
+        wchecks.test_source_lays_values_along_worm_paths(16, "uniform")
+    finally:
+        wchecks.o = saved
+
+
 @pytest.mark.parametrize("name", sorted(MUTATIONS))
 def test_mutation_is_caught(name):
     old, new = MUTATIONS[name]
     mod = _load_mutant(name, old, new)
     try:
         caught = []
-        for pin in pins.ALL_PINS + [_consistency_checks]:
+        for pin in pins.ALL_PINS + [_consistency_checks, _wall_source_checks]:
             try:
                 pin(mod)
             except Exception as exc:   # AssertionError or a crash of the mutant
