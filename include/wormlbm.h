@@ -88,11 +88,16 @@ typedef struct wlbm_params {
   int32_t dir_split;         /* waves sharing one cell's directions: 0 (auto),   */
                              /* 1, 2 or 4; q must be a multiple of 8*dir_split   */
   int32_t sched_chunk;       /* steps per schedule upload: 0 (auto) or 16..65536 */
-  int32_t reserved[6];       /* must be zero                                     */
+  double y_specularity;      /* diffuse y walls: fraction p in [0, 1] of what    */
+                             /* crosses them that is reflected specularly        */
+                             /* (Eq. adiabatic-specular); 1 - p is scattered     */
+                             /* diffusely (Eq. adiabatic-diffuse)                */
+  int32_t reserved[4];       /* must be zero                                     */
 } wlbm_params;
 
 /* Fill *p with defaults: 64 x 64, q = 16, uniform directions, MFP 16, f = 1,
- * correction on, all edges periodic, wall temperatures 0, automatic tiling. */
+ * correction on, all edges periodic, wall temperatures 0, automatic tiling,
+ * fully diffuse walls (y_specularity 0). */
 void wlbm_default_params(wlbm_params* p);
 
 /* Bytes of device workspace needed for the lattice described by *p.  Host
@@ -126,6 +131,18 @@ wlbm_status wlbm_set_populations(wlbm_lattice* lat, const float* d_e);
  * previous field) if any corrected weight exceeds 1 or is not finite, or if
  * an MFP is not positive. */
 wlbm_status wlbm_set_mfp_field(wlbm_lattice* lat, const float* d_mfp);
+
+/* Internal sources (Sec. 2.6, Eq. isotropic and Eq. anisotropic): the DDEDs
+ * of n distinct cells d_cells (device [n][2] int32, (x, y)) are overwritten
+ * by d_values (device [n][q] float) after every step, after the blackbody
+ * walls (a source on a wall cell wins), and now and at every later
+ * initialisation.  An isotropic blackbody source at T has values w_i T; a
+ * flux source the values of wlbm_flux_distribution.  The arrays stay the
+ * caller's and must remain valid and unchanged while set; n = 0 removes the
+ * sources.  Waits for the stream (the cells are checked on the host:
+ * WLBM_EINVAL for a cell outside the lattice or listed twice). */
+wlbm_status wlbm_set_sources(wlbm_lattice* lat, int32_t n, const int32_t* d_cells,
+                             const float* d_values);
 
 /* Change the blackbody wall temperatures (Sec. 2.6 allows time-dependent
  * boundary values).  Takes effect from the next step. */
@@ -181,6 +198,15 @@ wlbm_status wlbm_get_directions(const wlbm_params* p, double* sx, double* sy, do
  * gereralized), W = 1/MFP and the corrected weight (Eq. W-correction). */
 wlbm_status wlbm_get_constants(const wlbm_params* p, double* lambda_corr, double* w,
                                double* w_corr);
+
+/* DDEDs of a flux boundary or source (Sec. 2.6, Eq. lbm-heat-flux) into a host
+ * [q] array: the paper asks for the DDEDs to be prescribed uniquely; this is
+ * the distribution linear in the direction, e_i = w_i (T + s_i . a), whose
+ * energy sum_i e_i is T and whose flux sum_i e_i s_i is (qx, qy)
+ * (a = M^-1 q, M = sum_i w_i s_i s_i^T; for evenly spaced directions
+ * e_i = w_i (T + 2 q . s_i)).  Host only. */
+wlbm_status wlbm_flux_distribution(const wlbm_params* p, double T, double qx, double qy,
+                                   double* e);
 
 /* Worm/TAS schedule of steps step0+1 .. step0+n into a host [n][q] int8 array:
  * the D2Q8 move 1..8 (E, N, W, S, NE, NW, SW, SE) pending for each direction,

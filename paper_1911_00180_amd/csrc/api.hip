@@ -52,7 +52,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Byte offsets of the workspace regions.
 struct Carve {
-  size_t e[2], E[2], Wf, Wraw, qsx, qsy, partials, totals, flag, sched, wtab, sxtab, sytab, total;
+  size_t e[2], E[2], Wf, Wraw, qsx, qsy, partials, totals, flag, sched, wtab, sxtab, sytab, mtab,
+      total;
 };
 
 int chunk_steps(const wlbm_params& p) { return p.sched_chunk ? p.sched_chunk : kDefaultChunk; }
@@ -82,6 +83,7 @@ Carve carve(const wlbm_params& p) {
   c.wtab = take(size_t(p.q) * sizeof(float));
   c.sxtab = take(size_t(p.q) * sizeof(float));
   c.sytab = take(size_t(p.q) * sizeof(float));
+  c.mtab = take(size_t(p.q) * sizeof(int));
   c.total = off;
   return c;
 }
@@ -111,8 +113,10 @@ wlbm_status validate(const wlbm_params* p) {
                 p->q, p->dir_split, kMaxGroupPlanes * p->dir_split);
   if (p->sched_chunk != 0 && (p->sched_chunk < 16 || p->sched_chunk > 65536))
     return fail(WLBM_EINVAL, "sched_chunk must be 0 or 16..65536");
-  for (int k = 0; k < 6; ++k)
+  for (int k = 0; k < 4; ++k)
     if (p->reserved[k] != 0) return fail(WLBM_EINVAL, "reserved fields must be zero");
+  if (!(p->y_specularity >= 0.0 && p->y_specularity <= 1.0))
+    return fail(WLBM_EINVAL, "y_specularity must lie in [0, 1]");
   if (!std::isfinite(p->t_x_lo) || !std::isfinite(p->t_x_hi) || !std::isfinite(p->t_y_lo) ||
       !std::isfinite(p->t_y_hi))
     return fail(WLBM_EINVAL, "wall temperatures must be finite");
@@ -189,6 +193,10 @@ struct wlbm_lattice {
   Walls walls{};
   ScheduleBook book;        // schedule rows of any step, for restarts and the adjoint
   // adjoint (reverse pass) state
+  // internal sources (caller's device arrays, kept valid by the caller)
+  int nsrc = 0;
+  const int32_t* src_cells = nullptr;
+  const float* src_vals = nullptr;
   char* aws = nullptr;      // caller's adjoint workspace
   AdjCarve ac{};
   int acur = 0;             // lam / H buffer holding lam^am
@@ -421,7 +429,7 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
     delete l;
     return s;
   };
-  const size_t stage = std::max<size_t>(size_t(l->chunk) * p->q, 3 * size_t(p->q) * sizeof(float));
+  const size_t stage = std::max<size_t>(size_t(l->chunk) * p->q, 4 * size_t(p->q) * sizeof(float));
   for (int k = 0; k < 2; ++k) {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&l->pinned[k]), stage, hipHostMallocDefault);
     if (e != hipSuccess) {
@@ -452,6 +460,11 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
   if (e == hipSuccess)
     e = hipMemcpyAsync(l->ws + l->c.sytab, tabs + 2 * p->q, p->q * sizeof(float),
                        hipMemcpyHostToDevice, l->stream);
+  int* mir = reinterpret_cast<int*>(tabs + 3 * p->q);
+  for (int i = 0; i < p->q; ++i) mir[i] = l->dirs.mirror_y[i];
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(l->ws + l->c.mtab, mir, p->q * sizeof(int), hipMemcpyHostToDevice,
+                       l->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(l->stream);
   if (e != hipSuccess) {
     wlbm_status s = fail(WLBM_EHIP, "workspace set-up failed: %s", hipGetErrorString(e));
@@ -473,6 +486,8 @@ wlbm_status wlbm_set_temperature(wlbm_lattice* l, const float* d_T0) {
   if (!d_T0) return fail(WLBM_EINVAL, "T0 is NULL");
   HIP_TRY(launch_init_temperature(l->g, d_T0, l->ptr(l->c.e[l->cur]), l->ptr(l->c.E[l->cur]),
                                   l->ptr(l->c.wtab), l->walls, l->stream));
+  HIP_TRY(launch_apply_sources(l->g, l->ptr(l->c.e[l->cur]), l->ptr(l->c.E[l->cur]), l->src_cells,
+                               l->src_vals, l->nsrc, l->stream));
   l->flux_valid = false;
   return WLBM_OK;
 }
@@ -483,6 +498,8 @@ wlbm_status wlbm_set_populations(wlbm_lattice* l, const float* d_e) {
   if (!d_e) return fail(WLBM_EINVAL, "populations pointer is NULL");
   HIP_TRY(launch_init_populations(l->g, d_e, l->ptr(l->c.e[l->cur]), l->ptr(l->c.E[l->cur]),
                                   l->ptr(l->c.wtab), l->walls, l->stream));
+  HIP_TRY(launch_apply_sources(l->g, l->ptr(l->c.e[l->cur]), l->ptr(l->c.E[l->cur]), l->src_cells,
+                               l->src_vals, l->nsrc, l->stream));
   l->flux_valid = false;
   return WLBM_OK;
 }
@@ -509,6 +526,63 @@ wlbm_status wlbm_set_mfp_field(wlbm_lattice* l, const float* d_mfp) {
   HIP_TRY(launch_write_wfield(l->g, d_mfp, l->dirs.lambda_corr, f, l->p.mfp_correction,
                               l->ptr(l->c.Wf), l->ptr(l->c.Wraw), l->stream));
   l->per_cell = true;
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_set_sources(wlbm_lattice* l, int32_t n, const int32_t* d_cells,
+                             const float* d_values) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (n < 0) return fail(WLBM_EINVAL, "source count must be >= 0");
+  if (n == 0) {
+    l->nsrc = 0;
+    l->src_cells = nullptr;
+    l->src_vals = nullptr;
+    return WLBM_OK;
+  }
+  if (!d_cells || !d_values) return fail(WLBM_EINVAL, "source arrays must not be NULL");
+  std::vector<int32_t> cells(size_t(n) * 2);
+  HIP_TRY(hipMemcpyAsync(cells.data(), d_cells, cells.size() * sizeof(int32_t),
+                         hipMemcpyDeviceToHost, l->stream));
+  HIP_TRY(hipStreamSynchronize(l->stream));
+  std::vector<uint8_t> seen(size_t(l->g.nx) * l->g.ny, 0);
+  for (int s = 0; s < n; ++s) {
+    const int x = cells[2 * size_t(s)], y = cells[2 * size_t(s) + 1];
+    if (x < 0 || x >= l->g.nx || y < 0 || y >= l->g.ny)
+      return fail(WLBM_EINVAL, "source %d at (%d, %d) lies outside the lattice", s, x, y);
+    uint8_t& f = seen[size_t(y) * l->g.nx + x];
+    if (f) return fail(WLBM_EINVAL, "source %d repeats cell (%d, %d)", s, x, y);
+    f = 1;
+  }
+  l->nsrc = n;
+  l->src_cells = d_cells;
+  l->src_vals = d_values;
+  HIP_TRY(launch_apply_sources(l->g, l->ptr(l->c.e[l->cur]), l->ptr(l->c.E[l->cur]), d_cells,
+                               d_values, n, l->stream));
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_flux_distribution(const wlbm_params* p, double T, double qx, double qy,
+                                   double* e) {
+  wlbm_status st = validate(p);
+  if (st) return st;
+  if (!e) return fail(WLBM_EINVAL, "output is NULL");
+  try {
+    DirSet d = build_dirs(p->q, p->dirs);
+    // M = sum_i w_i s_i s_i^T; e_i = w_i (T + s_i . M^-1 q)
+    double mxx = 0, mxy = 0, myy = 0;
+    for (int i = 0; i < p->q; ++i) {
+      mxx += d.w[i] * d.sx[i] * d.sx[i];
+      mxy += d.w[i] * d.sx[i] * d.sy[i];
+      myy += d.w[i] * d.sy[i] * d.sy[i];
+    }
+    const double det = mxx * myy - mxy * mxy;
+    const double ax = (myy * qx - mxy * qy) / det;
+    const double ay = (mxx * qy - mxy * qx) / det;
+    for (int i = 0; i < p->q; ++i) e[i] = d.w[i] * (T + d.sx[i] * ax + d.sy[i] * ay);
+  } catch (const std::exception& ex) {
+    return fail(WLBM_EINVAL, "%s", ex.what());
+  }
   return WLBM_OK;
 }
 
@@ -553,7 +627,9 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
   a.wtab = l->ptr(l->c.wtab);
   a.sxtab = l->ptr(l->c.sxtab);
   a.sytab = l->ptr(l->c.sytab);
+  a.mtab = reinterpret_cast<const int*>(l->ws + l->c.mtab);
   a.W = l->W;
+  a.spec = float(l->p.y_specularity);
   a.t_x_lo = l->walls.x_lo;
   a.t_x_hi = l->walls.x_hi;
   a.t_y_lo = l->walls.y_lo;
@@ -635,6 +711,9 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
       }
       a.q_first = (flux && k == flux_from) ? 1 : 0;
       e = launch_step(a, l->split, l->per_cell, flux, l->stream);
+      if (e == hipSuccess)
+        e = launch_apply_sources(l->g, a.e_out, a.E_out, l->src_cells, l->src_vals, l->nsrc,
+                                 l->stream);
       if (e != hipSuccess) {
         l->broken = true;
         return fail(WLBM_EHIP, "step kernel launch failed: %s", hipGetErrorString(e));
@@ -810,6 +889,7 @@ wlbm_status wlbm_adjoint_begin(wlbm_lattice* l, void* d_ws, size_t bytes, int64_
   if (st) return st;
   if (l->p.y_edge == WLBM_EDGE_DIFFUSE)
     return fail(WLBM_EINVAL, "the adjoint covers periodic and blackbody edges only");
+  if (l->nsrc) return fail(WLBM_EINVAL, "the adjoint does not cover internal sources");
   if (step < 0 || step > kMaxSteps) return fail(WLBM_EINVAL, "step must be in 0 .. 2^31 - 1");
   if (!d_ws) return fail(WLBM_EINVAL, "adjoint workspace is NULL");
   if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
@@ -1102,7 +1182,9 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
       a.wtab = l->ptr(l->c.wtab);
       a.sxtab = l->ptr(l->c.sxtab);
       a.sytab = l->ptr(l->c.sytab);
+      a.mtab = reinterpret_cast<const int*>(l->ws + l->c.mtab);
       a.W = l->W;
+      a.spec = float(l->p.y_specularity);
       a.t_x_lo = l->walls.x_lo;
       a.t_x_hi = l->walls.x_hi;
       a.t_y_lo = l->walls.y_lo;
@@ -1183,6 +1265,13 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
       ba.parity = int(k & 1);
       ba.q_first = (flux && k == flux_from) ? 1 : 0;
       e = launch_step_batch(ba, l0->split, l0->per_cell, flux, b->stream);
+      for (int jl = 0; jl < n && e == hipSuccess; ++jl) {
+        wlbm_lattice* l = b->lats[jl];
+        if (!l->nsrc) continue;
+        const int out = 1 - (l->cur ^ int(k & 1));
+        e = launch_apply_sources(l->g, l->ptr(l->c.e[out]), l->ptr(l->c.E[out]), l->src_cells,
+                                 l->src_vals, l->nsrc, b->stream);
+      }
       if (e != hipSuccess) {
         for (wlbm_lattice* l : b->lats) l->broken = true;
         return fail(WLBM_EHIP, "batch step launch failed: %s", hipGetErrorString(e));

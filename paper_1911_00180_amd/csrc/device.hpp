@@ -42,7 +42,9 @@ struct StepArgs {
   const float* wtab;      // [q] weights
   const float* sxtab;     // [q] unit vectors
   const float* sytab;
+  const int* mtab;        // [q] index of each direction's mirror image in a y wall
   float W;                // uniform corrected weight
+  float spec;             // diffuse y walls: specular fraction p
   // Diffuse walls: sums of w_i over the directions whose pending move points
   // into the domain through the lo (dy = +1) / hi (dy = -1) wall on this
   // step, over the hopping ones and over all of them.
@@ -99,6 +101,10 @@ hipError_t launch_init_temperature(const Geometry& g, const float* T0, float* e,
 hipError_t launch_init_populations(const Geometry& g, const float* src, float* e, float* E,
                                    const float* wtab, Walls walls, hipStream_t s);
 hipError_t launch_read_populations(const Geometry& g, const float* e, float* dst, hipStream_t s);
+// Overwrite the n source cells (x, y) = cells[2s], cells[2s+1] with the
+// imposed DDEDs vals[s][q], and E with their sum.
+hipError_t launch_apply_sources(const Geometry& g, float* e, float* E, const int32_t* cells,
+                                const float* vals, int n, hipStream_t s);
 hipError_t launch_read_field(const Geometry& g, const float* f, float* dst, hipStream_t s);
 hipError_t launch_read_flux(const Geometry& g, const float* e, const float* sxtab,
                             const float* sytab, float* qx, float* qy, hipStream_t s);

@@ -25,8 +25,8 @@ namespace {
 
 // Boundary node of a diffuse wall (Sec. 2.6, Eq. adiabatic-diffuse): the node
 // at column X behind the lo (wall 0, row -1) or hi (wall 1, row ny) wall
-// absorbs what streams into it on this step and re-emits it isotropically,
-// as inward DDEDs w_i T_g.  A direction with an inward pending move delivers
+// absorbs the diffuse share 1 - p of what streams into it on this step and
+// re-emits it isotropically, as inward DDEDs w_i T_g.  A direction with an inward pending move delivers
 // w_i T_g on a hop and w_i W_g T_g (its EED part) on a pause; T_g is chosen so
 // that the node emits exactly what it absorbed.  Returns T_g and W_g T_g.
 // The node below/above a blackbody column belongs to the blackbody wall.
@@ -41,7 +41,7 @@ __device__ void boundary_node(const StepArgs& a, int wall, int X, float& tg, flo
     }
     if (X == 0 || X == a.nx - 1) {
       const float Wg = WF ? a.Wf[cell(X, yrow, a.pitch)] : a.W;
-      tg = (X == a.nx - 1) ? a.t_x_hi : a.t_x_lo;
+      tg = (1.f - a.spec) * ((X == a.nx - 1) ? a.t_x_hi : a.t_x_lo);
       wtg = Wg * tg;
       return;
     }
@@ -67,7 +67,7 @@ __device__ void boundary_node(const StepArgs& a, int wall, int X, float& tg, flo
   const float hs = wall == 0 ? a.in_lo_hop : a.in_hi_hop;
   const float as = wall == 0 ? a.in_lo_all : a.in_hi_all;
   const float C = fmaf(Wg, as - hs, hs);
-  tg = R / C;
+  tg = (1.f - a.spec) * R / C;
   wtg = Wg * tg;
 }
 
@@ -165,6 +165,18 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
           if (y == 0 && dy == 1) out = fmaf(wi, (hop ? sTg : sWTg)[lane + 1 - dx], out);
           if (y == a.ny - 1 && dy == -1)
             out = fmaf(wi, (hop ? sTg : sWTg)[T::LP + lane + 1 - dx], out);
+          // specular share (Eq. adiabatic-specular): the packet that the
+          // mirror direction m sends from (x - dx, y) across the wall is
+          // reflected there and ends the step here, in direction i
+          if (a.spec > 0.f && ((y == 0 && dy == 1) || (y == a.ny - 1 && dy == -1))) {
+            const int m = scalar_ptr(a.mtab)[i];
+            const float em = a.e_in[(long long)m * plane + cell(x - dx, y, pitch)];
+            const int lsrc = lc - dx;
+            const float Ws = WF ? sW[lsrc] : a.W;
+            const float WEs = WF ? sE[lsrc] : a.W * sE[lsrc];
+            const float pk = fmaf(wi, WEs, hop ? fmaf(-Ws, em, em) : 0.f);
+            out = fmaf(a.spec, pk, out);
+          }
         }
         out = blackbody(out, wi, x, y, a.nx, a.ny, a.x_edge, a.y_edge, a.t_x_lo, a.t_x_hi,
                         a.t_y_lo, a.t_y_hi);
@@ -394,6 +406,26 @@ __global__ __launch_bounds__(kBlock) void k_init_populations(const Geometry g, c
   store_ghosted(E, x, y, sum, g.nx, g.ny, g.pitch, px, py);
 }
 
+// Internal sources (Sec. 2.6, Eq. isotropic and Eq. anisotropic): the DDEDs
+// of source cell s are overwritten by vals[s][0..q-1], E by their sum (in
+// direction order), with the ghost copies of periodic edges.  Cells are
+// distinct and inside the lattice (checked by the host).
+__global__ __launch_bounds__(kBlock) void k_apply_sources(const Geometry g, float* e, float* E,
+                                                         const int32_t* cells,
+                                                         const float* vals, int n) {
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= n) return;
+  const int x = cells[2 * s], y = cells[2 * s + 1];
+  const bool px = g.x_edge == kPeriodic, py = g.y_edge == kPeriodic;
+  float sum = 0.f;
+  for (int i = 0; i < g.q; ++i) {
+    const float v = vals[(long long)s * g.q + i];
+    store_ghosted(e + (long long)i * g.plane, x, y, v, g.nx, g.ny, g.pitch, px, py);
+    sum += v;
+  }
+  store_ghosted(E, x, y, sum, g.nx, g.ny, g.pitch, px, py);
+}
+
 __global__ __launch_bounds__(kBlock) void k_read_populations(const Geometry g, const float* e,
                                                             float* dst) {
   const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
@@ -614,6 +646,14 @@ hipError_t launch_init_populations(const Geometry& g, const float* src, float* e
                                    const float* wtab, Walls walls, hipStream_t s) {
   hipLaunchKernelGGL(k_init_populations, dim3(cell_blocks(g)), dim3(kBlock), 0, s, g, src, e, E,
                      wtab, walls);
+  return hipGetLastError();
+}
+
+hipError_t launch_apply_sources(const Geometry& g, float* e, float* E, const int32_t* cells,
+                                const float* vals, int n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_apply_sources, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, g, e,
+                     E, cells, vals, n);
   return hipGetLastError();
 }
 

@@ -123,6 +123,15 @@ DirSet build_dirs(int q, int kind) {
     throw std::invalid_argument("unknown direction set");
   }
   d.lambda_corr = q / compensated_sum(d.speed);
+  // mirror image in a y wall (Eq. adiabatic-specular): both sets are
+  // symmetric under (sx, sy) -> (sx, -sy)
+  d.mirror_y.assign(q, -1);
+  for (int i = 0; i < q; ++i)
+    for (int j = 0; j < q; ++j)
+      if (std::fabs(d.sx[j] - d.sx[i]) < 1e-12 && std::fabs(d.sy[j] + d.sy[i]) < 1e-12)
+        d.mirror_y[i] = j;
+  for (int i = 0; i < q; ++i)
+    if (d.mirror_y[i] < 0) throw std::invalid_argument("direction set without y mirror pairs");
   return d;
 }
 

@@ -27,6 +27,7 @@ struct DirSet {
   int m = 0;
   std::vector<double> sx, sy, w, speed, slope;
   std::vector<int> major, sgn_major, sgn_minor;
+  std::vector<int> mirror_y;  // index of the direction (sx, -sy)
   std::vector<int64_t> ring_j;
   double lambda_corr = 0.0;  // Q / sum_i speed_i (Eq. W-correction-factor-gereralized)
 };

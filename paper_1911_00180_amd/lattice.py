@@ -58,6 +58,21 @@ class Lattice:
         W.wlbm_set_mfp_field(self.handle, t.data_ptr())
         self._mfp_field = t
 
+    def set_sources(self, cells, values) -> None:
+        """Internal sources: cells [S, 2] (x, y), imposed DDEDs values [S, q];
+        None (or S = 0) removes them.  The tensors are kept alive here."""
+        self._sync_stream()
+        if cells is None or len(cells) == 0:
+            W.wlbm_set_sources(self.handle, 0, None, None)
+            self._sources = None
+            return
+        c = torch.as_tensor(cells, dtype=torch.int32, device=self.device).contiguous()
+        v = torch.as_tensor(values, dtype=torch.float32, device=self.device).contiguous()
+        if c.dim() != 2 or c.shape[1] != 2 or tuple(v.shape) != (c.shape[0], self.q):
+            raise ValueError("cells must be [S, 2] and values [S, q]")
+        W.wlbm_set_sources(self.handle, c.shape[0], c.data_ptr(), v.data_ptr())
+        self._sources = (c, v)
+
     def set_wall_temperatures(self, t_x_lo=0.0, t_x_hi=0.0, t_y_lo=0.0, t_y_hi=0.0) -> None:
         W.wlbm_set_wall_temperatures(self.handle, t_x_lo, t_x_hi, t_y_lo, t_y_hi)
 

@@ -43,6 +43,7 @@ EXPORTS = (
     "wlbm_adjoint_steps", "wlbm_adjoint_read", "wlbm_adjoint_step_index",
     "wlbm_set_dir_split", "wlbm_get_dir_split", "wlbm_autotune", "wlbm_batch_bytes",
     "wlbm_batch_create", "wlbm_batch_step", "wlbm_batch_destroy", "wlbm_read_flux_mean",
+    "wlbm_set_sources", "wlbm_flux_distribution",
 )
 
 
@@ -55,7 +56,8 @@ class WlbmParams(ctypes.Structure):
         ("x_edge", c_int32), ("y_edge", c_int32),
         ("t_x_lo", c_double), ("t_x_hi", c_double), ("t_y_lo", c_double), ("t_y_hi", c_double),
         ("dir_split", c_int32), ("sched_chunk", c_int32),
-        ("reserved", c_int32 * 6),
+        ("y_specularity", c_double),
+        ("reserved", c_int32 * 4),
     ]
 
 
@@ -124,6 +126,8 @@ def lib() -> ctypes.CDLL:
         "wlbm_batch_destroy": (c_int, [c_void_p]),
         "wlbm_read_flux_mean": (c_int, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double),
                                         POINTER(c_double)]),
+        "wlbm_set_sources": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
+        "wlbm_flux_distribution": (c_int, [P, c_double, c_double, c_double, POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -352,12 +356,23 @@ def wlbm_read_flux_mean(h: int, x0: int, x1: int, averaged: int = 1):
     return qx.value, qy.value
 
 
+def wlbm_set_sources(h: int, n: int, d_cells, d_values) -> None:
+    _check(lib().wlbm_set_sources(c_void_p(h), n, _ptr(d_cells), _ptr(d_values)))
+
+
+def wlbm_flux_distribution(p: WlbmParams, T: float, qx: float, qy: float):
+    import numpy as np
+    e = np.zeros(p.q)
+    _check(lib().wlbm_flux_distribution(byref(p), T, qx, qy, e.ctypes.data_as(POINTER(c_double))))
+    return e
+
+
 def make_params(nx: int, ny: int, q: int, mfp: float = float("inf"), dirs: str = "uniform",
                 emulate_3d: bool = False, mfp_correction: bool = True,
                 x_edge: str = "periodic", y_edge: str = "periodic",
                 t_x_lo: float = 0.0, t_x_hi: float = 0.0, t_y_lo: float = 0.0,
                 t_y_hi: float = 0.0, dir_split: int = 0,
-                sched_chunk: int = 0) -> WlbmParams:
+                sched_chunk: int = 0, y_specularity: float = 0.0) -> WlbmParams:
     """Parameters from keyword arguments (edge and direction names as strings)."""
     edges = {"periodic": EDGE_PERIODIC, "blackbody": EDGE_BLACKBODY, "diffuse": EDGE_DIFFUSE}
     p = wlbm_default_params()
@@ -370,4 +385,5 @@ def make_params(nx: int, ny: int, q: int, mfp: float = float("inf"), dirs: str =
     p.y_edge = edges[y_edge]
     p.t_x_lo, p.t_x_hi, p.t_y_lo, p.t_y_hi = t_x_lo, t_x_hi, t_y_lo, t_y_hi
     p.dir_split, p.sched_chunk = dir_split, sched_chunk
+    p.y_specularity = y_specularity
     return p

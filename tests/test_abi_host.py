@@ -135,3 +135,24 @@ def test_direction_split_needs_divisible_q():
     with pytest.raises(W.WormLBMError) as ei:
         W.wlbm_workspace_bytes(W.make_params(64, 64, 24, mfp=8.0, dir_split=2))
     assert ei.value.status == W.WLBM_EINVAL
+
+
+def test_flux_distribution_matches_oracle():
+    import numpy as np
+
+    from oracle import worm_lbm as o
+    for q, kind in ((16, "uniform"), (64, "uniform"), (24, "ring"), (40, "ring")):
+        p = W.make_params(16, 16, q, mfp=8.0, dirs=kind)
+        e = W.wlbm_flux_distribution(p, 0.6, 0.03, -0.07)
+        lat = o.Lattice(o.Config(nx=4, ny=4, q=q, dirs=kind))
+        want = o.flux_distribution(lat.dirs, lat.w, 0.6, np.array([0.03, -0.07]))
+        assert np.max(np.abs(e - want)) < 1e-15
+
+
+def test_specularity_validated():
+    p = W.make_params(16, 16, 16, mfp=8.0, y_edge="diffuse", y_specularity=1.5)
+    with pytest.raises(W.WormLBMError) as ei:
+        W.wlbm_workspace_bytes(p)
+    assert ei.value.status == W.WLBM_EINVAL
+    p = W.make_params(16, 16, 16, mfp=8.0, y_edge="diffuse", y_specularity=0.25)
+    assert W.wlbm_workspace_bytes(p) > 0
