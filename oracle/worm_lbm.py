@@ -233,7 +233,8 @@ class Schedule:
     pos: np.ndarray       # int64 [nsteps, Q, 2], worm position after step n
 
 
-def tas_schedule(dirs: list[Direction], nsteps: int, step0: int = 0) -> Schedule:
+def tas_schedule(dirs: list[Direction], nsteps: int, step0: int = 0,
+                 speeds=None) -> Schedule:
     """Worm-LBM schedule for steps step0+1 .. step0+nsteps.
 
     Reading of Eq. algorithm (x_cum, x_ax, Delta x): at step n the DDED of
@@ -245,6 +246,12 @@ def tas_schedule(dirs: list[Direction], nsteps: int, step0: int = 0) -> Schedule
     Reading: the worm index advances only when the move is executed; a paused
     direction retries the same move at the next step.  This reproduces the
     D2Q8 diagonal example of Fig. 2 (hops at n = 1, 2, 4, 5, pause at n = 3).
+
+    Angle-dependent grid speed (Sec. 2.3: the TAS can impose any
+    direction-dependent velocity): with speeds v_i in (0, 1] cells per step
+    (default 1) the axial distance after step n is v_i n, so
+        hop  iff  |P + s|^2 <= (v_i n + 1)^2 ,
+    evaluated in float64 when v_i != 1 (the integer rule when v_i = 1).
     """
     q = len(dirs)
     total = step0 + nsteps
@@ -259,7 +266,11 @@ def tas_schedule(dirs: list[Direction], nsteps: int, step0: int = 0) -> Schedule
             m = paths[i][k[i]]
             cx = P[i][0] + D2Q8[m][0]
             cy = P[i][1] + D2Q8[m][1]
-            h = cx * cx + cy * cy <= (n + 1) * (n + 1)
+            if speeds is None or speeds[i] == 1.0:
+                h = cx * cx + cy * cy <= (n + 1) * (n + 1)
+            else:
+                r = speeds[i] * n + 1.0
+                h = float(cx * cx + cy * cy) <= r * r
             if h:
                 P[i] = [cx, cy]
                 k[i] += 1
@@ -298,6 +309,8 @@ class Config:
     # whose DDEDs are overwritten every step by values [S, q]
     source_cells: np.ndarray | None = None
     source_values: np.ndarray | None = None
+    # grid speed of each direction in cells per step (Sec. 2.3), None = 1
+    speeds: np.ndarray | None = None
 
 
 @dataclass
@@ -332,6 +345,10 @@ class Lattice:
             raise ValueError("unstable: corrected relaxation weight exceeds 1")
         if not 0.0 <= c.y_specularity <= 1.0:
             raise ValueError("y_specularity must lie in [0, 1]")
+        if c.speeds is not None:
+            v = np.asarray(c.speeds, dtype=np.float64)
+            if v.shape != (c.q,) or np.any(~(v > 0.0)) or np.any(v > 1.0):
+                raise ValueError("speeds must be q values in (0, 1]")
         # mirror image of each direction in a y wall: (sx, sy) -> (sx, -sy)
         self.mirror_y = np.array([self._find(d.sx, -d.sy) for d in self.dirs])
         self.Wc = float(Wc) if Wc.ndim == 0 else Wc
@@ -359,7 +376,8 @@ class Lattice:
         """Schedule rows for steps 1..nsteps (cached, extended on demand)."""
         have = 0 if self._sched is None else self._sched.move.shape[0]
         if have < nsteps:
-            self._sched = tas_schedule(self.dirs, max(nsteps, 2 * have, 16))
+            self._sched = tas_schedule(self.dirs, max(nsteps, 2 * have, 16),
+                                       speeds=self.cfg.speeds)
         return self._sched
 
     # -- one step ---------------------------------------------------------

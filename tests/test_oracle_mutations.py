@@ -88,6 +88,9 @@ MUTATIONS = {
     "sources_before_blackbody": (
         "        self._apply_blackbody(new)\n        self._apply_sources(new)",
         "        self._apply_sources(new)\n        self._apply_blackbody(new)"),
+    "speed_without_lead": (
+        "r = speeds[i] * n + 1.0",
+        "r = speeds[i] * (n + 1.0)"),
     "sources_not_imposed_at_start": (
         "        self._apply_blackbody(self.e)\n        self._apply_sources(self.e)",
         "        self._apply_blackbody(self.e)"),
@@ -135,6 +138,8 @@ def _wall_source_checks(o):
         wchecks.test_specular_diffuse_conserves_energy_and_keeps_equilibrium(0.35)
         wchecks.test_source_wins_over_blackbody_wall_and_is_imposed_at_start()
         wchecks.test_source_lays_values_along_worm_paths(16, "uniform")
+        wchecks.test_axial_hop_count_closed_form(0.5)
+        wchecks.test_slowed_axis_travels_at_its_speed()
     finally:
         wchecks.o = saved
 

@@ -118,3 +118,52 @@ def test_flux_distribution_uniform_closed_form():
     e = o.flux_distribution(lat.dirs, lat.w, 0.3, np.array([0.02, -0.05]))
     assert abs(e.sum() - 0.3) < 1e-15
     assert np.allclose(lat.s.T @ e, [0.02, -0.05], atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# Angle-dependent grid speed (Sec. 2.3)
+# ---------------------------------------------------------------------------
+def test_unit_speeds_give_the_isotropic_schedule():
+    for q, kind in ((16, "uniform"), (24, "ring")):
+        dirs = o.make_directions(q, kind)
+        a = o.tas_schedule(dirs, 300)
+        b = o.tas_schedule(dirs, 300, speeds=np.ones(q))
+        assert np.array_equal(a.move, b.move) and np.array_equal(a.hop, b.hop)
+
+
+@pytest.mark.parametrize("v", [0.5, 0.3, 0.75, 0.999])
+def test_axial_hop_count_closed_form(v):
+    """An axial direction at speed v has made min(n, floor(v n + 1)) hops
+    after n steps (one hop per step at most; the worm may lead by one
+    cell)."""
+    dirs = o.make_directions(16, "uniform")
+    sch = o.tas_schedule(dirs, 400, speeds=np.full(16, v))
+    for n in range(1, 401):
+        k = int(np.abs(sch.pos[n - 1, 0]).sum())       # direction 0 is +x
+        assert k == min(n, int(np.floor(v * n + 1.0))), n
+
+
+def test_worm_keeps_to_its_speed():
+    """Every worm stays within radius v_i n + 1 and, once started, at most
+    one diagonal hop (sqrt 2) plus the lead of one cell behind it."""
+    rng = np.random.default_rng(5)
+    for q, kind in ((16, "uniform"), (32, "ring")):
+        dirs = o.make_directions(q, kind)
+        v = rng.uniform(0.2, 1.0, size=q)
+        sch = o.tas_schedule(dirs, 500, speeds=v)
+        r = np.hypot(sch.pos[..., 0], sch.pos[..., 1])
+        n = np.arange(1, 501)[:, None]
+        assert np.all(r <= v[None, :] * n + 1.0 + 1e-12)
+        assert np.all(r >= v[None, :] * n + 1.0 - np.sqrt(2.0) - 1.0)
+
+
+def test_slowed_axis_travels_at_its_speed():
+    """Directions nearer the x axis slowed to half speed: after n steps the
+    +x worm is at v n + 1 and the +y worm at n."""
+    q = 32
+    lat0 = o.Lattice(o.Config(nx=4, ny=4, q=q))
+    v = np.where(np.abs(lat0.s[:, 0]) > np.abs(lat0.s[:, 1]), 0.5, 1.0)
+    n = 60
+    sch = o.tas_schedule(lat0.dirs, n, speeds=v)
+    assert tuple(sch.pos[n - 1, 0]) == (31, 0)        # direction 0: +x
+    assert tuple(sch.pos[n - 1, q // 4]) == (0, 60)   # direction q/4: +y
