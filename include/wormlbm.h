@@ -43,6 +43,12 @@
 extern "C" {
 #endif
 
+/* The library is built with hidden visibility; these declarations are its
+ * exported interface. */
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility push(default)
+#endif
+
 typedef struct wlbm_lattice wlbm_lattice;
 typedef struct wlbm_batch wlbm_batch;
 
@@ -144,6 +150,14 @@ wlbm_status wlbm_set_mfp_field(wlbm_lattice* lat, const float* d_mfp);
 wlbm_status wlbm_set_sources(wlbm_lattice* lat, int32_t n, const int32_t* d_cells,
                              const float* d_values);
 
+/* Angle-dependent grid speed (Sec. 2.3: the TAS can impose any
+ * direction-dependent velocity): host [q] speeds v_i in (0, 1] cells per step
+ * (NULL: 1 for all, the isotropic TAS).  Direction i then hops iff
+ * |P_i + s_i|^2 <= (v_i n + 1)^2 at step n (float64; the integer rule for
+ * v_i = 1).  The relaxation weight is unchanged.  Only at step 0
+ * (WLBM_ESTATE otherwise). */
+wlbm_status wlbm_set_speeds(wlbm_lattice* lat, const double* speeds);
+
 /* Change the blackbody wall temperatures (Sec. 2.6 allows time-dependent
  * boundary values).  Takes effect from the next step. */
 wlbm_status wlbm_set_wall_temperatures(wlbm_lattice* lat, double t_x_lo, double t_x_hi,
@@ -164,6 +178,10 @@ wlbm_status wlbm_step(wlbm_lattice* lat, int64_t nsteps);
 /* Pseudo-temperature T = sum_i e_i (Eq. pseudo-T, linear gray model) into a
  * device [ny][nx] array. */
 wlbm_status wlbm_read_temperature(wlbm_lattice* lat, float* d_T);
+
+/* d_T += scale * T (device [ny][nx]): superposition of uncoupled gray runs
+ * (the multigray approach of Sec. 2.2), one call per band. */
+wlbm_status wlbm_accumulate_temperature(wlbm_lattice* lat, double scale, float* d_T);
 
 /* Heat flux q = sum_i e_i s_i (Eq. q_corr, v_g = 1) into device [ny][nx]
  * arrays.  averaged = 0: the current state.  averaged = 1: the mean over the
@@ -208,13 +226,14 @@ wlbm_status wlbm_get_constants(const wlbm_params* p, double* lambda_corr, double
 wlbm_status wlbm_flux_distribution(const wlbm_params* p, double T, double qx, double qy,
                                    double* e);
 
-/* Worm/TAS schedule of steps step0+1 .. step0+n into a host [n][q] int8 array:
+/* Worm/TAS schedule of steps step0+1 .. step0+n into a host [n][q] int8 array
+ * (speeds: host [q] grid speeds as for wlbm_set_speeds, or NULL for 1):
  * the D2Q8 move 1..8 (E, N, W, S, NE, NW, SW, SE) pending for each direction,
  * positive if the DDED hops on that step, negative if it pauses (Sec. 2.3
  * Eq. algorithm, Sec. 2.5 Eq. worm-paths).  If pos is not NULL it receives
  * the host [n][q][2] int64 worm positions after each step. */
-wlbm_status wlbm_get_schedule(const wlbm_params* p, int64_t step0, int64_t n, int8_t* moves,
-                              int64_t* pos);
+wlbm_status wlbm_get_schedule(const wlbm_params* p, const double* speeds, int64_t step0,
+                              int64_t n, int8_t* moves, int64_t* pos);
 
 /* ---- Saved states (checkpoints) ------------------------------------------
  * A state is the lattice's padded population planes followed by its padded
@@ -362,6 +381,10 @@ const char* wlbm_last_error(void);
 /* Release the handle and its pinned host memory after waiting for its stream.
  * The workspace may be reused afterwards.  NULL is accepted. */
 wlbm_status wlbm_destroy(wlbm_lattice* lat);
+
+#if defined(__GNUC__) || defined(__clang__)
+#pragma GCC visibility pop
+#endif
 
 #ifdef __cplusplus
 }

@@ -277,6 +277,8 @@ wlbm_status check_members(wlbm_lattice* const* lats, int32_t n) {
                   j);
     if (b->tas.n != a->tas.n)
       return fail(WLBM_EINVAL, "lattice %d: all lattices of a batch must be at the same step", j);
+    if (b->dirs.vgrid != a->dirs.vgrid)
+      return fail(WLBM_EINVAL, "lattice %d: grid speeds must agree (the schedule is shared)", j);
     if (b->split != a->split || b->per_cell != a->per_cell || b->chunk != a->chunk)
       return fail(WLBM_EINVAL,
                   "lattice %d: direction split, per-cell field use and schedule chunk must agree", j);
@@ -355,15 +357,25 @@ wlbm_status wlbm_get_constants(const wlbm_params* p, double* lambda_corr, double
   return WLBM_OK;
 }
 
-wlbm_status wlbm_get_schedule(const wlbm_params* p, int64_t step0, int64_t n, int8_t* moves,
-                              int64_t* pos) {
+static wlbm_status check_speeds(int q, const double* v) {
+  if (!v) return WLBM_OK;
+  for (int i = 0; i < q; ++i)
+    if (!(v[i] > 0.0 && v[i] <= 1.0))
+      return fail(WLBM_EINVAL, "speed of direction %d is %g; speeds lie in (0, 1]", i, v[i]);
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_get_schedule(const wlbm_params* p, const double* speeds, int64_t step0,
+                              int64_t n, int8_t* moves, int64_t* pos) {
   wlbm_status st = validate(p);
+  if (!st) st = check_speeds(p->q, speeds);
   if (st) return st;
   if (step0 < 0 || n < 0 || step0 + n > kMaxSteps)
     return fail(WLBM_EINVAL, "steps must satisfy 0 <= step0, 0 <= n, step0 + n < 2^31");
   if (n > 0 && !moves) return fail(WLBM_EINVAL, "moves is NULL");
   try {
     DirSet d = build_dirs(p->q, p->dirs);
+    if (speeds) d.vgrid.assign(speeds, speeds + p->q);
     TasState s;
     s.reset(p->q);
     std::vector<int8_t> dx(p->q), dy(p->q);
@@ -586,6 +598,19 @@ wlbm_status wlbm_flux_distribution(const wlbm_params* p, double T, double qx, do
   return WLBM_OK;
 }
 
+wlbm_status wlbm_set_speeds(wlbm_lattice* l, const double* speeds) {
+  wlbm_status st = check_lat(l);
+  if (!st) st = check_speeds(l->p.q, speeds);
+  if (st) return st;
+  if (l->tas.n != 0) return fail(WLBM_ESTATE, "grid speeds can only be set at step 0");
+  if (speeds)
+    l->dirs.vgrid.assign(speeds, speeds + l->p.q);
+  else
+    l->dirs.vgrid.assign(l->p.q, 1.0);
+  l->book.reset(&l->dirs);
+  return WLBM_OK;
+}
+
 wlbm_status wlbm_set_wall_temperatures(wlbm_lattice* l, double txl, double txh, double tyl,
                                        double tyh) {
   wlbm_status st = check_lat(l);
@@ -783,6 +808,15 @@ wlbm_status wlbm_read_temperature(wlbm_lattice* l, float* d_T) {
   if (st) return st;
   if (!d_T) return fail(WLBM_EINVAL, "T is NULL");
   HIP_TRY(launch_read_field(l->g, l->ptr(l->c.E[l->cur]), d_T, l->stream));
+  return WLBM_OK;
+}
+
+wlbm_status wlbm_accumulate_temperature(wlbm_lattice* l, double scale, float* d_T) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (!d_T) return fail(WLBM_EINVAL, "T is NULL");
+  if (!std::isfinite(scale)) return fail(WLBM_EINVAL, "scale must be finite");
+  HIP_TRY(launch_axpy_field(l->g, float(scale), l->ptr(l->c.E[l->cur]), d_T, l->stream));
   return WLBM_OK;
 }
 

@@ -106,6 +106,9 @@ hipError_t launch_read_populations(const Geometry& g, const float* e, float* dst
 hipError_t launch_apply_sources(const Geometry& g, float* e, float* E, const int32_t* cells,
                                 const float* vals, int n, hipStream_t s);
 hipError_t launch_read_field(const Geometry& g, const float* f, float* dst, hipStream_t s);
+// dst[y][x] += a * f(x, y) (f padded, dst unpadded).
+hipError_t launch_axpy_field(const Geometry& g, float a, const float* f, float* dst,
+                             hipStream_t s);
 hipError_t launch_read_flux(const Geometry& g, const float* e, const float* sxtab,
                             const float* sytab, float* qx, float* qy, hipStream_t s);
 hipError_t launch_scale_pair(int n, const float* ax, const float* ay, float scale, float* bx,

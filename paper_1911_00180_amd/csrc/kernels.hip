@@ -166,16 +166,22 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
           if (y == a.ny - 1 && dy == -1)
             out = fmaf(wi, (hop ? sTg : sWTg)[T::LP + lane + 1 - dx], out);
           // specular share (Eq. adiabatic-specular): the packet that the
-          // mirror direction m sends from (x - dx, y) across the wall is
+          // mirror direction m sends across the wall from (x - dx_m, y),
+          // when its own pending move points out through that wall, is
           // reflected there and ends the step here, in direction i
-          if (a.spec > 0.f && ((y == 0 && dy == 1) || (y == a.ny - 1 && dy == -1))) {
+          if (a.spec > 0.f && (y == 0 || y == a.ny - 1)) {
             const int m = scalar_ptr(a.mtab)[i];
-            const float em = a.e_in[(long long)m * plane + cell(x - dx, y, pitch)];
-            const int lsrc = lc - dx;
-            const float Ws = WF ? sW[lsrc] : a.W;
-            const float WEs = WF ? sE[lsrc] : a.W * sE[lsrc];
-            const float pk = fmaf(wi, WEs, hop ? fmaf(-Ws, em, em) : 0.f);
-            out = fmaf(a.spec, pk, out);
+            int mdx, mdy;
+            bool mhop;
+            decode((codes[m >> 2] >> (8 * (m & 3))) & 0xffu, mdx, mdy, mhop);
+            if ((y == 0 && mdy == -1) || (y == a.ny - 1 && mdy == 1)) {
+              const float em = a.e_in[(long long)m * plane + cell(x - mdx, y, pitch)];
+              const int lsrc = lc - mdx;
+              const float Ws = WF ? sW[lsrc] : a.W;
+              const float WEs = WF ? sE[lsrc] : a.W * sE[lsrc];
+              const float pk = fmaf(wtab[m], WEs, mhop ? fmaf(-Ws, em, em) : 0.f);
+              out = fmaf(a.spec, pk, out);
+            }
           }
         }
         out = blackbody(out, wi, x, y, a.nx, a.ny, a.x_edge, a.y_edge, a.t_x_lo, a.t_x_hi,
@@ -444,6 +450,13 @@ __global__ __launch_bounds__(kBlock) void k_read_field(const Geometry g, const f
   dst[c] = f[cell(int(c % g.nx), int(c / g.nx), g.pitch)];
 }
 
+__global__ __launch_bounds__(kBlock) void k_axpy_field(const Geometry g, float a, const float* f,
+                                                      float* dst) {
+  const long long c = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (c >= (long long)g.nx * g.ny) return;
+  dst[c] = fmaf(a, f[cell(int(c % g.nx), int(c / g.nx), g.pitch)], dst[c]);
+}
+
 __global__ __launch_bounds__(kBlock) void k_read_flux(const Geometry g, const float* e,
                                                      const float* sxtab, const float* sytab,
                                                      float* qx, float* qy) {
@@ -665,6 +678,12 @@ hipError_t launch_read_populations(const Geometry& g, const float* e, float* dst
 
 hipError_t launch_read_field(const Geometry& g, const float* f, float* dst, hipStream_t s) {
   hipLaunchKernelGGL(k_read_field, dim3(cell_blocks(g)), dim3(kBlock), 0, s, g, f, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_field(const Geometry& g, float a, const float* f, float* dst,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy_field, dim3(cell_blocks(g)), dim3(kBlock), 0, s, g, a, f, dst);
   return hipGetLastError();
 }
 

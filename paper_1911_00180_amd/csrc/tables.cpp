@@ -123,6 +123,7 @@ DirSet build_dirs(int q, int kind) {
     throw std::invalid_argument("unknown direction set");
   }
   d.lambda_corr = q / compensated_sum(d.speed);
+  d.vgrid.assign(q, 1.0);
   // mirror image in a y wall (Eq. adiabatic-specular): both sets are
   // symmetric under (sx, sy) -> (sx, -sy)
   d.mirror_y.assign(q, -1);
@@ -189,7 +190,13 @@ void tas_advance(const DirSet& d, TasState& st, int8_t* dx, int8_t* dy, uint8_t*
     worm_move(d, i, st.k[i] + 1, &mx, &my);
     const int64_t cx = st.px[i] + mx;
     const int64_t cy = st.py[i] + my;
-    const bool h = cx * cx + cy * cy <= r * r;
+    bool h;
+    if (d.vgrid[i] == 1.0) {
+      h = cx * cx + cy * cy <= r * r;
+    } else {
+      const double rv = d.vgrid[i] * double(n) + 1.0;
+      h = double(cx * cx + cy * cy) <= rv * rv;
+    }
     if (h) {
       st.px[i] = cx;
       st.py[i] = cy;

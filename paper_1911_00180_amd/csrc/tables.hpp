@@ -28,6 +28,7 @@ struct DirSet {
   std::vector<double> sx, sy, w, speed, slope;
   std::vector<int> major, sgn_major, sgn_minor;
   std::vector<int> mirror_y;  // index of the direction (sx, -sy)
+  std::vector<double> vgrid;  // grid speed in cells per step, (0, 1] (Sec. 2.3)
   std::vector<int64_t> ring_j;
   double lambda_corr = 0.0;  // Q / sum_i speed_i (Eq. W-correction-factor-gereralized)
 };
@@ -62,6 +63,8 @@ struct TasState {
 // One step of the schedule (step n = st.n + 1): for each direction the
 // pending move s_i and whether the DDED hops, hop iff |P_i + s_i|^2 <= (n+1)^2
 // in exact integers; on a hop P_i and k_i advance.  Outputs are [q] arrays.
+// A direction with grid speed v_i != 1 hops iff |P_i + s_i|^2 <= (v_i n + 1)^2,
+// evaluated in float64 (the axial distance after step n is v_i n).
 void tas_advance(const DirSet& d, TasState& st, int8_t* dx, int8_t* dy, uint8_t* hop);
 
 // The state after n steps from the hop counts k_i alone: after k hops the

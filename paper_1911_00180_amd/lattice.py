@@ -73,6 +73,15 @@ class Lattice:
         W.wlbm_set_sources(self.handle, c.shape[0], c.data_ptr(), v.data_ptr())
         self._sources = (c, v)
 
+    def set_speeds(self, speeds) -> None:
+        """Grid speed of each direction ([q] in (0, 1]; None = 1), at step 0."""
+        W.wlbm_set_speeds(self.handle, self.q, speeds)
+
+    def accumulate_temperature(self, scale: float, T: torch.Tensor) -> None:
+        """T += scale * (this lattice's temperature), on the device."""
+        self._sync_stream()
+        W.wlbm_accumulate_temperature(self.handle, scale, T.data_ptr())
+
     def set_wall_temperatures(self, t_x_lo=0.0, t_x_hi=0.0, t_y_lo=0.0, t_y_hi=0.0) -> None:
         W.wlbm_set_wall_temperatures(self.handle, t_x_lo, t_x_hi, t_y_lo, t_y_hi)
 

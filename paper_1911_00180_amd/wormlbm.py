@@ -43,7 +43,8 @@ EXPORTS = (
     "wlbm_adjoint_steps", "wlbm_adjoint_read", "wlbm_adjoint_step_index",
     "wlbm_set_dir_split", "wlbm_get_dir_split", "wlbm_autotune", "wlbm_batch_bytes",
     "wlbm_batch_create", "wlbm_batch_step", "wlbm_batch_destroy", "wlbm_read_flux_mean",
-    "wlbm_set_sources", "wlbm_flux_distribution",
+    "wlbm_set_sources", "wlbm_flux_distribution", "wlbm_set_speeds",
+    "wlbm_accumulate_temperature",
 )
 
 
@@ -100,7 +101,8 @@ def lib() -> ctypes.CDLL:
                                         POINTER(c_double)]),
         "wlbm_get_constants": (c_int, [P, POINTER(c_double), POINTER(c_double),
                                        POINTER(c_double)]),
-        "wlbm_get_schedule": (c_int, [P, c_int64, c_int64, POINTER(c_int8), POINTER(c_int64)]),
+        "wlbm_get_schedule": (c_int, [P, POINTER(c_double), c_int64, c_int64, POINTER(c_int8),
+                                      POINTER(c_int64)]),
         "wlbm_step_count": (c_int64, [c_void_p]),
         "wlbm_last_error": (c_char_p, []),
         "wlbm_destroy": (c_int, [c_void_p]),
@@ -128,6 +130,8 @@ def lib() -> ctypes.CDLL:
                                         POINTER(c_double)]),
         "wlbm_set_sources": (c_int, [c_void_p, c_int32, c_void_p, c_void_p]),
         "wlbm_flux_distribution": (c_int, [P, c_double, c_double, c_double, POINTER(c_double)]),
+        "wlbm_set_speeds": (c_int, [c_void_p, POINTER(c_double)]),
+        "wlbm_accumulate_temperature": (c_int, [c_void_p, c_double, c_void_p]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -234,15 +238,36 @@ def wlbm_get_constants(p: WlbmParams):
     return lam.value, w.value, wc.value
 
 
-def wlbm_get_schedule(p: WlbmParams, step0: int, n: int, positions: bool = False):
+def _host_doubles(v, n):
+    import numpy as np
+    if v is None:
+        return None, None
+    a = np.ascontiguousarray(v, dtype=np.float64)
+    if a.shape != (n,):
+        raise ValueError(f"expected {n} values")
+    return a, a.ctypes.data_as(POINTER(c_double))
+
+
+def wlbm_get_schedule(p: WlbmParams, step0: int, n: int, positions: bool = False,
+                      speeds=None):
     """(moves [n, q] int8, positions [n, q, 2] int64 or None)."""
     import numpy as np
     moves = np.zeros((n, p.q), dtype=np.int8)
     pos = np.zeros((n, p.q, 2), dtype=np.int64) if positions else None
+    keep, sp = _host_doubles(speeds, p.q)
     _check(lib().wlbm_get_schedule(
-        byref(p), step0, n, moves.ctypes.data_as(POINTER(c_int8)),
+        byref(p), sp, step0, n, moves.ctypes.data_as(POINTER(c_int8)),
         pos.ctypes.data_as(POINTER(c_int64)) if positions else None))
     return moves, pos
+
+
+def wlbm_set_speeds(h: int, q: int, speeds) -> None:
+    keep, sp = _host_doubles(speeds, q)
+    _check(lib().wlbm_set_speeds(c_void_p(h), sp))
+
+
+def wlbm_accumulate_temperature(h: int, scale: float, d_T) -> None:
+    _check(lib().wlbm_accumulate_temperature(c_void_p(h), scale, _ptr(d_T)))
 
 
 def wlbm_step_count(h: int) -> int:

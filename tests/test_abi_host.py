@@ -16,11 +16,39 @@ HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))
 
 def test_exports_every_declared_symbol():
     src = open(HEADER).read()
-    declared = set(re.findall(r"\b(wlbm_[a-z_]+)\s*\(", src))
+    declared = set(re.findall(r"\b(wlbm_[a-z_0-9]+)\s*\(", src))
     assert declared == set(W.EXPORTS)
     L = W.lib()
     for name in declared:
         assert hasattr(L, name), name
+
+
+def test_exports_nothing_else():
+    """The library is built with hidden visibility: its dynamic symbol table
+    holds the declared entry points and nothing more of its own."""
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", W.LIB_PATH], capture_output=True,
+                         text=True)
+    if out.returncode != 0:
+        pytest.skip("nm not available")
+    text_syms = {ln.split()[-1] for ln in out.stdout.splitlines()
+                 if len(ln.split()) == 3 and ln.split()[1] == "T"}
+    assert text_syms == set(W.EXPORTS)
+
+
+@pytest.mark.parametrize("q,kind", [(16, "uniform"), (64, "uniform"), (24, "ring")])
+def test_schedule_with_speeds_bit_exact_against_oracle(q, kind):
+    rng = np.random.default_rng(q)
+    v = rng.uniform(0.2, 1.0, size=q)
+    v[::5] = 1.0
+    p = W.make_params(32, 32, q, mfp=10.0, dirs=kind)
+    moves, pos = W.wlbm_get_schedule(p, 0, 1500, positions=True, speeds=v)
+    sch = o.tas_schedule(o.make_directions(q, kind), 1500, speeds=v)
+    want = np.where(sch.hop, sch.move, -sch.move).astype(np.int8)
+    assert np.array_equal(moves, want)
+    assert np.array_equal(pos, sch.pos)
+    with pytest.raises(W.WormLBMError):
+        W.wlbm_get_schedule(p, 0, 10, speeds=np.full(q, 1.5))
 
 
 @pytest.mark.parametrize("q,kind", [(8, "uniform"), (16, "uniform"), (64, "uniform"),
