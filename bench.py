@@ -66,7 +66,7 @@ def recorded_traffic(path=TRAFFIC_FILE, sources=STEP_SOURCES):
         return None
 
 
-def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911):
+def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=True):
     import numpy as np
     import torch
 
@@ -75,7 +75,8 @@ def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911):
 
     x0, y0 = inputs.seeded_center(seed, nx, ny)
     T0 = inputs.gaussian_pulse(nx, ny, 16.0, x0, y0).astype(np.float32)
-    lat = Lattice(nx, ny, q, mfp=mfp, device="cuda:0", dir_split=split, **edges)
+    lat = Lattice(nx, ny, q, mfp=mfp, device="cuda:0", dir_split=split, step_fusion=fusion,
+                  **edges)
     lat.set_temperature(torch.from_numpy(T0))
     lat.step(warmup)
     torch.cuda.synchronize()
@@ -267,6 +268,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurements")
     ap.add_argument("--no-films", action="store_true", help="skip the batched film sweep")
+    ap.add_argument("--single-step", action="store_true",
+                    help="one time step per kernel launch (no two-step fusion)")
     ap.add_argument("--film-steps", type=int, default=10000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -297,7 +300,8 @@ def main():
     nx = ny = 1024
     q = 64
     mfp = args.kn * nx
-    ms, wall, energy = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.split)
+    ms, wall, energy = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.split,
+                               fusion=not args.single_step)
     updates = nx * ny * q * args.steps
     gups = updates / (ms * 1e-3) / 1e9
     ms_step = ms / args.steps

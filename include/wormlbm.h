@@ -98,12 +98,16 @@ typedef struct wlbm_params {
                              /* crosses them that is reflected specularly        */
                              /* (Eq. adiabatic-specular); 1 - p is scattered     */
                              /* diffusely (Eq. adiabatic-diffuse)                */
-  int32_t reserved[4];       /* must be zero                                     */
+  int32_t step_fusion;       /* 1: advance two steps per kernel launch where     */
+                             /* possible (periodic edges, no sources, q <= 64,   */
+                             /* outside flux windows and tapes), with results    */
+                             /* identical to single steps; 0: one step per launch */
+  int32_t reserved[3];       /* must be zero                                     */
 } wlbm_params;
 
 /* Fill *p with defaults: 64 x 64, q = 16, uniform directions, MFP 16, f = 1,
  * correction on, all edges periodic, wall temperatures 0, automatic tiling,
- * fully diffuse walls (y_specularity 0). */
+ * fully diffuse walls (y_specularity 0), step fusion on. */
 void wlbm_default_params(wlbm_params* p);
 
 /* Bytes of device workspace needed for the lattice described by *p.  Host

@@ -12,7 +12,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libwormlbm.so")
-SOURCES = ["tables.cpp", "kernels.hip", "adjoint.hip", "api.hip"]
+SOURCES = ["tables.cpp", "kernels.hip", "fused.hip", "adjoint.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -76,8 +76,7 @@ __device__ __forceinline__ void adj_sweep(const AdjArgs& a, float* sRed, int x0,
   const uint32_t boff = uint32_t(cell(ok ? x : 0, ok ? y : 0, pitch) * 4);
   const bool px = a.x_edge == kPeriodic;
   const bool py = a.y_edge == kPeriodic;
-  const bool ghost = EDGE && ok && ((px && (x == 0 || x == a.nx - 1)) ||
-                                    (py && (y == 0 || y == a.ny - 1)));
+  const bool ghost = EDGE && ok && has_ghost(x, y, a.nx, a.ny, px, py);
   const bool wall = EDGE && ok && wall_cell(x, y, a.nx, a.ny, a.x_edge, a.y_edge);
 
   // G(z) from the eight move-class partial sums, in a fixed order

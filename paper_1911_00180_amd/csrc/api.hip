@@ -113,8 +113,10 @@ wlbm_status validate(const wlbm_params* p) {
                 p->q, p->dir_split, kMaxGroupPlanes * p->dir_split);
   if (p->sched_chunk != 0 && (p->sched_chunk < 16 || p->sched_chunk > 65536))
     return fail(WLBM_EINVAL, "sched_chunk must be 0 or 16..65536");
-  for (int k = 0; k < 4; ++k)
+  for (int k = 0; k < 3; ++k)
     if (p->reserved[k] != 0) return fail(WLBM_EINVAL, "reserved fields must be zero");
+  if (p->step_fusion != 0 && p->step_fusion != 1)
+    return fail(WLBM_EINVAL, "step_fusion is 0 or 1");
   if (!(p->y_specularity >= 0.0 && p->y_specularity <= 1.0))
     return fail(WLBM_EINVAL, "y_specularity must lie in [0, 1]");
   if (!std::isfinite(p->t_x_lo) || !std::isfinite(p->t_x_hi) || !std::isfinite(p->t_y_lo) ||
@@ -306,6 +308,7 @@ void wlbm_default_params(wlbm_params* p) {
   p->mfp_correction = 1;
   p->x_edge = WLBM_EDGE_PERIODIC;
   p->y_edge = WLBM_EDGE_PERIODIC;
+  p->step_fusion = 1;
 }
 
 wlbm_status wlbm_workspace_bytes(const wlbm_params* p, size_t* bytes) {
@@ -668,6 +671,16 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
   a.y_edge = l->g.y_edge;
   a.tiles_x = tiles_x_for(l->g.nx);
   a.ntiles = a.tiles_x * tiles_y_for(l->g.ny, l->split);
+  // two steps per launch: periodic edges only, no sources, not into a tape,
+  // and a direction share per wave the fused kernel is built for
+  const bool fuse = l->p.step_fusion && !tape && l->nsrc == 0 &&
+                    l->g.x_edge == kPeriodic && l->g.y_edge == kPeriodic &&
+                    step2_supported(q, l->split);
+
+  // the two-step kernel reads the second ghost column; other producers
+  // write the first one only, so the frame is refreshed before the first
+  // two-step launch and after any single step in between
+  bool refresh_ghosts = true;
 
   int64_t done = 0;
   while (done < nsteps) {
@@ -716,6 +729,43 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
     for (int j = 0; j < cnt; ++j) {
       const int64_t k = done + j;
       const bool flux = k >= flux_from;
+      if (fuse && j + 1 < cnt && k + 1 < flux_from) {
+        // steps k and k+1 in one launch
+        Step2Args a2{};
+        a2.e_in = l->ptr(l->c.e[l->cur]);
+        a2.e_out = l->ptr(l->c.e[1 - l->cur]);
+        a2.E_in = l->ptr(l->c.E[l->cur]);
+        a2.E_out = l->ptr(l->c.E[1 - l->cur]);
+        a2.Wf = a.Wf;
+        a2.codes1 = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j) * q);
+        a2.codes2 = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j + 1) * q);
+        a2.wtab = a.wtab;
+        a2.W = a.W;
+        a2.nx = a.nx;
+        a2.ny = a.ny;
+        a2.q = q;
+        a2.pitch = a.pitch;
+        a2.plane = a.plane;
+        a2.strips_x = step2_strips_x(a.nx);
+        a2.strips_y = step2_strips_y(a.ny);
+        e = hipSuccess;
+        if (refresh_ghosts) {
+          e = fill_ghosts(l->ptr(l->c.e[l->cur]), a.plane, q, a.nx, a.ny, a.pitch, l->stream);
+          if (e == hipSuccess)
+            e = fill_ghosts(l->ptr(l->c.E[l->cur]), a.plane, 1, a.nx, a.ny, a.pitch, l->stream);
+          if (e == hipSuccess && l->per_cell)
+            e = fill_ghosts(l->ptr(l->c.Wf), a.plane, 1, a.nx, a.ny, a.pitch, l->stream);
+          refresh_ghosts = false;
+        }
+        if (e == hipSuccess) e = launch_step2(a2, l->split, l->per_cell, l->stream);
+        if (e != hipSuccess) {
+          l->broken = true;
+          return fail(WLBM_EHIP, "fused step kernel launch failed: %s", hipGetErrorString(e));
+        }
+        l->cur = 1 - l->cur;
+        ++j;
+        continue;
+      }
       a.codes = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j) * q);
       a.in_lo_hop = insums[4 * j];
       a.in_lo_all = insums[4 * j + 1];
@@ -744,6 +794,7 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
         return fail(WLBM_EHIP, "step kernel launch failed: %s", hipGetErrorString(e));
       }
       if (!tape) l->cur = 1 - l->cur;
+      refresh_ghosts = true;
     }
     done += cnt;
   }

@@ -9,19 +9,22 @@
 namespace wlbm {
 
 // Padded HBM layout of every per-cell field (populations, E, W field).
-// A field plane holds rows y = -1 .. ny and columns x = -1 .. nx, where the
-// rows/columns -1 and nx (ny) are ghosts: for a periodic edge they hold a
-// copy of the opposite edge written by the producer of that cell, otherwise
-// they stay zero.  Cell (x, y) sits at (y + 1) * pitch + kXOff + x, so that
-// x = 0 starts a 128-byte line and a wave's 64 consecutive cells are two
-// whole lines.  Populations are [q] such planes (structure of arrays).
+// A field plane holds rows y = -1 .. ny and columns x = -2 .. nx + 1, where
+// rows -1 and ny and columns -2, -1, nx, nx + 1 are ghosts: for a periodic
+// edge they hold copies of the opposite edge, otherwise they stay zero.  The
+// producer of a cell writes the first ghost column / row (-1, nx, ny); the
+// second ghost column (-2, nx + 1), read only by the two-step kernel, is
+// refreshed by fill_ghosts.  Cell (x, y) sits at (y + 1) * pitch + kXOff + x,
+// so that x = 0 starts a 128-byte line and a wave's 64 consecutive cells are
+// two whole lines; each row has at least three cells of padding after
+// x = nx - 1.  Populations are [q] such planes (structure of arrays).
 constexpr int kXOff = 32;
 constexpr int kBlock = 256;
 constexpr int kMaxQ = 1024;
 
 enum Edge { kPeriodic = 0, kBlackbody = 1, kDiffuse = 2 };
 
-inline int padded_pitch(int nx) { return ((nx + kXOff + 1 + 31) / 32) * 32; }
+inline int padded_pitch(int nx) { return ((nx + kXOff + 3 + 31) / 32) * 32; }
 inline int64_t padded_plane(int nx, int ny) { return int64_t(ny + 2) * padded_pitch(nx); }
 
 // Schedule code of one direction on one step: bits 0-1 dx+1, bits 2-3 dy+1,
@@ -78,6 +81,34 @@ constexpr int kMaxGroupPlanes = 8;
 hipError_t launch_step(const StepArgs& a, int split, bool per_cell, bool flux, hipStream_t s);
 int tiles_x_for(int nx);
 int tiles_y_for(int ny, int split);
+
+// Two time steps (n+1, n+2) of a lattice with periodic x and y edges in one
+// launch; codes1 / codes2 are the schedule rows of the two steps.  Same
+// results as two launch_step calls with the same split.
+struct Step2Args {
+  const float* e_in;
+  float* e_out;
+  const float* E_in;
+  float* E_out;
+  const float* Wf;
+  const uint32_t* codes1;
+  const uint32_t* codes2;
+  const float* wtab;
+  float W;
+  int nx, ny, q, pitch;
+  long long plane;
+  int strips_x, strips_y;
+};
+hipError_t launch_step2(const Step2Args& a, int split, bool per_cell, hipStream_t s);
+// Ghost frame (both ghost columns each side, ghost rows) of nplanes periodic
+// planes from the cells they wrap to.
+hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny, int pitch,
+                       hipStream_t s);
+int step2_strips_x(int nx);
+int step2_strips_y(int ny);
+// Whether the fused kernel is built for this q and direction split (q / split
+// directions per wave: 8 or 16).
+bool step2_supported(int q, int split);
 
 // One time step of n lattices in one launch (same q, direction set and
 // schedule row).  lats holds, for each lattice j, its arguments for buffer

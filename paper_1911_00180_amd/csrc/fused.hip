@@ -1,0 +1,335 @@
+// Two time steps of the worm-LBM per launch (temporal blocking) for gfx950.
+//
+// One launch of k_step2 advances a periodic lattice by steps n+1 and n+2
+// (Sec. 2.3 Eq. algorithm, pull form as in k_step): each population is read
+// from HBM once and written once per two steps, instead of once per step.
+//
+// A block owns a strip of 60 columns and kRows2 rows of the output.  Its NW
+// waves cover the same 64 columns x0-2 .. x0+61, one per lane, and split the
+// directions as k_step does (Q/NW = SH each).  Rows are pipelined: for
+// intermediate row r = y0-1 .. y0+kRows2 the waves compute step n+1 from the
+// step-n populations in HBM and keep it in registers, a ring of three rows;
+// as soon as rows r-2 .. r are there they compute step n+2 of row r-1.  The
+// one-cell shifts in x of the pull are lane shifts of a whole wave (DPP
+// wave_shr / wave_shl), so step n+1 is valid on lanes 1..62 and step n+2 on
+// lanes 2..61.  Rows wrap by index arithmetic; columns read the two-deep
+// ghost frame of periodic x edges, which must be valid on entry (the caller
+// refreshes it after other producers) and which k_fill_ghosts refreshes
+// after the launch (the kernel itself writes the cells only).  E of the intermediate rows is summed over
+// the waves in LDS in k_step's fixed order, and every update uses k_step's
+// arithmetic, so one k_step2 launch gives the same bits as two k_step
+// launches with the same direction split.
+#include "device.hpp"
+#include "kernel_common.hpp"
+
+namespace wlbm {
+namespace {
+
+constexpr int kStrip = 60;   // output columns per block (lanes 2 .. 61)
+constexpr int kRows2 = 16;   // output rows per block (kRows2 + 2 divisible by 3)
+static_assert((kRows2 + 2) % 3 == 0, "the row loop is unrolled by three");
+
+// Value held by lane l - 1 (the cell at x - 1), lane l + 1 (x + 1).
+__device__ __forceinline__ float from_lower_lane(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x138, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float from_upper_lane(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
+                                                               0x130, 0xF, 0xF, false));
+}
+// The value at column x - dx; dx is the same in every lane.  Both shifts are
+// computed and one is selected, so that no branch surrounds the (convergent)
+// lane shifts.
+__device__ __forceinline__ float at_minus(float v, int dx) {
+  const float lo = from_lower_lane(v), up = from_upper_lane(v);
+  return dx > 0 ? lo : (dx < 0 ? up : v);
+}
+template <class T>
+__device__ __forceinline__ T pick3(T a, T b, T c, int k) {
+  return k == 0 ? a : (k == 1 ? b : c);
+}
+
+template <int SH>
+struct Ring {
+  float X[3][SH];   // step n+1 populations of this wave's directions, rows by slot
+  float E1[3];      // step n+1 E (per-cell mode: W E) at this lane's column
+  float W1[3];      // W at this lane's column (per-cell mode)
+  float En[3];      // step n E (per-cell mode: W E), rows by slot
+  float Wn[3];      // step n W (per-cell mode)
+  float V[SH];      // step n populations pulled into the next intermediate row
+};
+
+// Issue the loads of intermediate row r: the step-n populations each of this
+// wave's directions pulls (row r - hy, column x - hx) into g.V, and step-n E
+// (and W) of row r + 1 into ring slot SN.  Nothing waits for them here.
+template <int SH, bool WF, int SN>
+__device__ __forceinline__ void issue_row(const Step2Args& a, Ring<SH>& g, int r, int i_begin,
+                                          uint32_t lcol) {
+  const WLBM_CONST uint32_t* codes1 = scalar_ptr(a.codes1);
+  const long long plane = a.plane;
+  const uint32_t plane_bytes = uint32_t(plane * 4);
+  auto row_bytes = [&](int rr) { return uint32_t((wrap_index(rr, a.ny) + 1) * a.pitch * 4); };
+  const uint32_t rb_m = row_bytes(r + 1), rb_0 = row_bytes(r), rb_p = row_bytes(r - 1);
+  {
+    const float Ev = buf_load(make_rsrc(a.E_in, plane_bytes), lcol, rb_m);
+    if constexpr (WF) {
+      const float Wv = buf_load(make_rsrc(a.Wf, plane_bytes), lcol, rb_m);
+      g.Wn[SN] = Wv;
+      g.En[SN] = Ev * Wv;
+    } else {
+      g.En[SN] = Ev;
+    }
+  }
+#pragma unroll
+  for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
+    const int i0 = i_begin + b0;
+    uint32_t words[kMaxGroupPlanes / 4];
+#pragma unroll
+    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes1[(i0 >> 2) + k];
+    // one float before the batch, so that the column shift 4 (1 - hx) >= 0
+    const rsrc_t rs = make_rsrc(a.e_in + (long long)i0 * plane - 1,
+                                uint32_t((kMaxGroupPlanes * plane + 2) * 4));
+#pragma unroll
+    for (int d = 0; d < kMaxGroupPlanes; ++d) {
+      int dx, dy;
+      bool hop;
+      decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
+      const int hx = hop ? dx : 0, hy = hop ? dy : 0;
+      g.V[b0 + d] = buf_load(rs, lcol,
+                             uint32_t(d * plane_bytes) + pick3(rb_m, rb_0, rb_p, hy + 1) +
+                                 uint32_t(4 * (1 - hx)));
+    }
+  }
+}
+
+// Intermediate row t (r = y0 - 1 + t, ring slot S = t mod 3), then output row
+// r - 1 once t >= 2.  Slots: step-n rows r-1, r, r+1 are S, S+1, S+2 (mod 3);
+// step-(n+1) rows r-2, r-1, r are S+1, S+2, S.  The loads of row t were
+// issued by the previous call; this one issues those of row t + 1 before its
+// second step, so that they are in flight meanwhile.
+template <int NW, int SH, bool WF, int S>
+__device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float* sP, int t,
+                                         int x0, int y0, int lane, int part, uint32_t lcol,
+                                         bool out_lane) {
+  constexpr int S1 = (S + 1) % 3, S2 = (S + 2) % 3;
+  // Keep the compiler from hoisting the schedule decoding of every direction
+  // out of the row loop (it would hold all of it in scalar registers and
+  // spill); the codes are re-read from the scalar cache for each row.
+  __asm__ volatile("" ::: "memory");
+  const WLBM_CONST uint32_t* codes1 = scalar_ptr(a.codes1);
+  const WLBM_CONST uint32_t* codes2 = scalar_ptr(a.codes2);
+  const WLBM_CONST float* wtab = scalar_ptr(a.wtab);
+  const int ny = a.ny, pitch = a.pitch;
+  const long long plane = a.plane;
+  const uint32_t plane_bytes = uint32_t(plane * 4);
+  const int r = y0 - 1 + t;
+  const int i_begin = part * SH;
+
+  // ---- step n+1, row r ----
+  float Eacc = 0.f;
+#pragma unroll
+  for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
+    const int i0 = i_begin + b0;
+    uint32_t words[kMaxGroupPlanes / 4];
+#pragma unroll
+    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes1[(i0 >> 2) + k];
+#pragma unroll
+    for (int d = 0; d < kMaxGroupPlanes; ++d) {
+      const int i = i0 + d;
+      int dx, dy;
+      bool hop;
+      decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
+      const float wi = wtab[i];
+      const float e = g.V[b0 + d];
+      // source rows r - dy: dy = -1 -> slot S2, 0 -> S1, 1 -> S
+      const float Es = at_minus(pick3(g.En[S2], g.En[S1], g.En[S], dy + 1), dx);
+      float out;
+      if constexpr (!WF) {
+        out = fmaf(a.W, fmaf(wi, Es, -e), e);
+      } else {
+        const float Wh = hop ? at_minus(pick3(g.Wn[S2], g.Wn[S1], g.Wn[S], dy + 1), dx)
+                             : g.Wn[S1];
+        out = e + fmaf(wi, Es, -(Wh * e));
+      }
+      g.X[S][b0 + d] = out;
+      Eacc += out;
+    }
+  }
+  // W of this row for the second step, before slot S is refilled
+  if constexpr (WF) g.W1[S] = g.Wn[S1];
+  const float Wrow = WF ? g.Wn[S1] : 1.f;
+  // loads of the next intermediate row (its step-n row r + 2 goes to slot S)
+  if (t + 1 < kRows2 + 2) issue_row<SH, WF, S>(a, g, r + 1, i_begin, lcol);
+  // E of row r over all waves, in k_step's order
+  float* p1 = sP + (t & 1) * NW * 64;
+  p1[part * 64 + lane] = Eacc;
+  lds_barrier();
+  float E1 = p1[lane];
+#pragma unroll
+  for (int k = 1; k < NW; ++k) E1 += p1[k * 64 + lane];
+  if constexpr (WF)
+    g.E1[S] = E1 * Wrow;
+  else
+    g.E1[S] = E1;
+  if (t < 2) return;
+
+  // ---- step n+2, row ro = r - 1 ----
+  const int ro = r - 1;
+  const bool store = out_lane && ro < ny;
+  (void)pitch;
+  const int xo = x0 - 2 + lane;
+  const uint32_t ob = uint32_t(cell(store ? xo : 0, store ? ro : 0, pitch) * 4);
+  float E2acc = 0.f;
+#pragma unroll
+  for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
+    const int i0 = i_begin + b0;
+    uint32_t words[kMaxGroupPlanes / 4];
+#pragma unroll
+    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes2[(i0 >> 2) + k];
+    const rsrc_t ro_rs = make_rsrc(a.e_out + (long long)i0 * plane,
+                                   uint32_t(kMaxGroupPlanes * plane * 4));
+#pragma unroll
+    for (int d = 0; d < kMaxGroupPlanes; ++d) {
+      const int i = i0 + d;
+      int dx, dy;
+      bool hop;
+      decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
+      const int hx = hop ? dx : 0, hy = hop ? dy : 0;
+      const float wi = wtab[i];
+      // source rows ro - dy: dy = -1 -> r (slot S), 0 -> r - 1 (S2), 1 -> r - 2 (S1)
+      const float e = at_minus(pick3(g.X[S][b0 + d], g.X[S2][b0 + d], g.X[S1][b0 + d], hy + 1),
+                               hx);
+      const float Es = at_minus(pick3(g.E1[S], g.E1[S2], g.E1[S1], dy + 1), dx);
+      float out;
+      if constexpr (!WF) {
+        out = fmaf(a.W, fmaf(wi, Es, -e), e);
+      } else {
+        const float Wh = at_minus(pick3(g.W1[S], g.W1[S2], g.W1[S1], hy + 1), hx);
+        out = e + fmaf(wi, Es, -(Wh * e));
+      }
+      E2acc += out;
+      if (store) buf_store_stream(out, ro_rs, ob, uint32_t(d * plane_bytes));
+    }
+  }
+  float* p2 = sP + (2 + (t & 1)) * NW * 64;
+  p2[part * 64 + lane] = E2acc;
+  lds_barrier();
+  if (part == 0 && store) {
+    float E2 = p2[lane];
+#pragma unroll
+    for (int k = 1; k < NW; ++k) E2 += p2[k * 64 + lane];
+    buf_store(E2, make_rsrc(a.E_out, plane_bytes), ob);
+  }
+}
+
+// Ghost frame of a periodic lattice after k_step2 (which writes the cells
+// only): every ghost cell (columns -2, -1, nx, nx + 1 of rows 0 .. ny - 1, and
+// rows -1, ny of columns -2 .. nx + 1) of planes 0 .. nplanes - 1 copies the
+// cell it wraps to.
+__global__ __launch_bounds__(kBlock) void k_fill_ghosts(float* base, long long plane, int nplanes,
+                                                       int nx, int ny, int pitch) {
+  const long long nper = 4LL * ny + 2LL * (nx + 4);
+  const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nper * nplanes) return;
+  const int p = int(t / nper);
+  const long long g = t - (long long)p * nper;
+  int gx, gy;
+  if (g < 4LL * ny) {
+    const int k = int(g / ny);
+    gy = int(g - (long long)k * ny);
+    gx = k < 2 ? k - 2 : nx + k - 2;
+  } else {
+    const long long h = g - 4LL * ny;
+    const int k = int(h / (nx + 4));
+    gx = int(h - (long long)k * (nx + 4)) - 2;
+    gy = k == 0 ? -1 : ny;
+  }
+  float* pl = base + (long long)p * plane;
+  pl[cell(gx, gy, pitch)] = pl[cell(wrap_index(gx, nx), wrap_index(gy, ny), pitch)];
+}
+
+template <int NW, int SH, bool WF>
+__global__ __launch_bounds__(64 * NW) void k_step2(const Step2Args a) {
+  __shared__ float sP[4 * NW * 64];   // E partial sums: [intermediate | output][parity][wave]
+  const int lane = threadIdx.x & 63;
+  const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (b % a.strips_x) * kStrip;
+  const int y0 = (b / a.strips_x) * kRows2;
+  // this lane's column; lanes past nx + 1 read column nx + 1 (their values are
+  // never used), so that every read stays inside the row and its padding
+  const int x = x0 - 2 + lane;
+  const int xl = x < a.nx + 1 ? x : a.nx + 1;
+  const uint32_t lcol = uint32_t((kXOff + xl) * 4);
+  const bool out_lane = lane >= 2 && lane < 2 + kStrip && x < a.nx;
+
+  Ring<SH> g;
+  // step-n rows y0 - 2 and y0 - 1 into slots 0 and 1; the loads of the first
+  // intermediate row (r = y0 - 1) bring row y0 into slot 2
+  const uint32_t plane_bytes = uint32_t(a.plane * 4);
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const uint32_t rb = uint32_t((wrap_index(y0 - 2 + k, a.ny) + 1) * a.pitch * 4);
+    const float Ev = buf_load(make_rsrc(a.E_in, plane_bytes), lcol, rb);
+    if constexpr (WF) {
+      const float Wv = buf_load(make_rsrc(a.Wf, plane_bytes), lcol, rb);
+      g.Wn[k] = Wv;
+      g.En[k] = Ev * Wv;
+    } else {
+      g.En[k] = Ev;
+    }
+  }
+  issue_row<SH, WF, 2>(a, g, y0 - 1, part * SH, lcol);
+  for (int t = 0; t < kRows2 + 2; t += 3) {
+    row_pair<NW, SH, WF, 0>(a, g, sP, t, x0, y0, lane, part, lcol, out_lane);
+    row_pair<NW, SH, WF, 1>(a, g, sP, t + 1, x0, y0, lane, part, lcol, out_lane);
+    row_pair<NW, SH, WF, 2>(a, g, sP, t + 2, x0, y0, lane, part, lcol, out_lane);
+  }
+}
+
+template <int NW, int SH>
+hipError_t launch2(const Step2Args& a, bool wf, hipStream_t s) {
+  const dim3 grid(a.strips_x * a.strips_y), block(64 * NW);
+  if (wf)
+    hipLaunchKernelGGL((k_step2<NW, SH, true>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_step2<NW, SH, false>), grid, block, 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) e = fill_ghosts(a.e_out, a.plane, a.q, a.nx, a.ny, a.pitch, s);
+  if (e == hipSuccess) e = fill_ghosts(a.E_out, a.plane, 1, a.nx, a.ny, a.pitch, s);
+  return e;
+}
+
+}  // namespace
+
+hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny, int pitch,
+                       hipStream_t s) {
+  const long long n = (4LL * ny + 2LL * (nx + 4)) * nplanes;
+  hipLaunchKernelGGL(k_fill_ghosts, dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     base, plane, nplanes, nx, ny, pitch);
+  return hipGetLastError();
+}
+
+int step2_strips_x(int nx) { return (nx + kStrip - 1) / kStrip; }
+int step2_strips_y(int ny) { return (ny + kRows2 - 1) / kRows2; }
+bool step2_supported(int q, int split) {
+  if (split != 1 && split != 2 && split != 4) return false;
+  const int sh = q / split;
+  return sh == 8 || sh == 16;
+}
+
+hipError_t launch_step2(const Step2Args& a, int split, bool per_cell, hipStream_t s) {
+  const int sh = a.q / split;
+  switch (split * 100 + sh) {
+    case 108: return launch2<1, 8>(a, per_cell, s);
+    case 116: return launch2<1, 16>(a, per_cell, s);
+    case 208: return launch2<2, 8>(a, per_cell, s);
+    case 216: return launch2<2, 16>(a, per_cell, s);
+    case 408: return launch2<4, 8>(a, per_cell, s);
+    case 416: return launch2<4, 16>(a, per_cell, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace wlbm

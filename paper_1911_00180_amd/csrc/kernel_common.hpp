@@ -50,6 +50,15 @@ __device__ __forceinline__ void buf_store_stream(float v, rsrc_t r, uint32_t vof
                                         kStreamStore);
 }
 
+// Barrier for data exchanged through LDS only: waits for this wave's LDS
+// accesses, not for its global loads and stores (a full __syncthreads()
+// would also wait for every store in flight).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Tables that every lane reads at the same index (schedule codes, weights,
 // unit vectors) are read through the scalar cache.
 #define WLBM_CONST __attribute__((address_space(4)))
@@ -58,7 +67,21 @@ __device__ __forceinline__ const WLBM_CONST T* scalar_ptr(const T* p) {
   return (const WLBM_CONST T*)p;
 }
 
-// Store a cell value and, for periodic edges, its ghost copies.
+// Whether cell (x, y) has ghost copies (periodic edges: one ghost column and
+// one ghost row each side).
+__device__ __forceinline__ bool has_ghost(int x, int y, int nx, int ny, bool px, bool py) {
+  return (px && (x == 0 || x == nx - 1)) || (py && (y == 0 || y == ny - 1));
+}
+
+__device__ __forceinline__ int wrap_index(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// Store a cell value and, for periodic edges, its ghost copies: column nx
+// holds column 0, column -1 holds column nx - 1, likewise for rows, corners
+// both.  (The second ghost column each side, which the two-step kernel
+// reads, is refreshed by k_fill_ghosts.)
 __device__ __forceinline__ void store_ghosted(float* __restrict__ plane, int x, int y, float v,
                                               int nx, int ny, int pitch, bool px, bool py) {
   plane[cell(x, y, pitch)] = v;

@@ -129,8 +129,7 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
 
   const bool ok = !EDGE || (x < a.nx && y < a.ny);
   const int lc = (row + 1) * T::LP + lane + 1;
-  const bool ghost = EDGE && ok && ((px && (x == 0 || x == a.nx - 1)) ||
-                                    (py && (y == 0 || y == a.ny - 1)));
+  const bool ghost = EDGE && ok && has_ghost(x, y, a.nx, a.ny, px, py);
 
   float Eacc = 0.f, qx = 0.f, qy = 0.f;
   const int share = a.q / NW;
@@ -217,7 +216,7 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
       sRed[NW * n + slot] = qx;
       sRed[2 * NW * n + slot] = qy;
     }
-    __syncthreads();
+    lds_barrier();
     if (part != 0) return;
     const int base = row * 64 + lane;
     Eacc = sRed[base];

@@ -58,7 +58,8 @@ class WlbmParams(ctypes.Structure):
         ("t_x_lo", c_double), ("t_x_hi", c_double), ("t_y_lo", c_double), ("t_y_hi", c_double),
         ("dir_split", c_int32), ("sched_chunk", c_int32),
         ("y_specularity", c_double),
-        ("reserved", c_int32 * 4),
+        ("step_fusion", c_int32),
+        ("reserved", c_int32 * 3),
     ]
 
 
@@ -397,7 +398,8 @@ def make_params(nx: int, ny: int, q: int, mfp: float = float("inf"), dirs: str =
                 x_edge: str = "periodic", y_edge: str = "periodic",
                 t_x_lo: float = 0.0, t_x_hi: float = 0.0, t_y_lo: float = 0.0,
                 t_y_hi: float = 0.0, dir_split: int = 0,
-                sched_chunk: int = 0, y_specularity: float = 0.0) -> WlbmParams:
+                sched_chunk: int = 0, y_specularity: float = 0.0,
+                step_fusion: bool = True) -> WlbmParams:
     """Parameters from keyword arguments (edge and direction names as strings)."""
     edges = {"periodic": EDGE_PERIODIC, "blackbody": EDGE_BLACKBODY, "diffuse": EDGE_DIFFUSE}
     p = wlbm_default_params()
@@ -411,4 +413,5 @@ def make_params(nx: int, ny: int, q: int, mfp: float = float("inf"), dirs: str =
     p.t_x_lo, p.t_x_hi, p.t_y_lo, p.t_y_hi = t_x_lo, t_x_hi, t_y_lo, t_y_hi
     p.dir_split, p.sched_chunk = dir_split, sched_chunk
     p.y_specularity = y_specularity
+    p.step_fusion = int(step_fusion)
     return p

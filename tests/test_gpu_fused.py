@@ -1,0 +1,96 @@
+"""Two steps per launch (k_step2) against one step per launch (k_step).
+
+The fused kernel uses the same arithmetic and the same summation order as the
+single-step kernel, so with the same direction split the populations must
+agree bit for bit, on ragged and tiny lattices, for odd step counts (the last
+step runs alone), across schedule chunks and around flux windows (whose steps
+run alone).  Oracle parity of the fused path is covered by every periodic
+parity test, which now runs it by default.
+"""
+import numpy as np
+import pytest
+
+from paper_1911_00180_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1911_00180_amd import wormlbm
+    wormlbm.lib()
+
+
+def _pair(nx, ny, q, **kw):
+    from paper_1911_00180_amd.lattice import Lattice
+    a = Lattice(nx, ny, q, step_fusion=True, **kw)
+    b = Lattice(nx, ny, q, step_fusion=False, **kw)
+    return a, b
+
+
+@pytest.mark.parametrize("nx,ny,q,split,mfp,kind", [
+    (1024, 64, 64, 0, 102.4, "uniform"),
+    (131, 37, 64, 4, 6.0, "uniform"),
+    (70, 45, 16, 2, 3.0, "uniform"),
+    (20, 10, 32, 1, 9.0, "ring"),
+    (5, 3, 8, 1, 2.0, "uniform"),
+    (200, 17, 24, 1, 1e9, "ring"),
+])
+def test_fused_equals_single_steps(nx, ny, q, split, mfp, kind):
+    a, b = _pair(nx, ny, q, mfp=mfp, dirs=kind, dir_split=split, sched_chunk=16)
+    e0 = torch.from_numpy(inputs.random_populations(3, q, ny, nx))
+    for lat in (a, b):
+        lat.set_populations(e0)
+    for n in (1, 2, 7, 16, 33):
+        a.step(n)
+        b.step(n)
+        assert torch.equal(a.populations(), b.populations()), n
+        assert torch.equal(a.temperature(), b.temperature()), n
+    a.close()
+    b.close()
+
+
+def test_fused_with_mfp_field_and_flux_window():
+    nx, ny, q = 150, 40, 32
+    a, b = _pair(nx, ny, q, mfp=5.0, sched_chunk=16)
+    mfp = torch.from_numpy(inputs.smooth_lognormal_field(nx, ny, 4, 5.0, 6.0, 0.6, 2.0, 30.0)
+                           .astype(np.float32))
+    T0 = torch.from_numpy(inputs.random_temperature(6, ny, nx))
+    for lat in (a, b):
+        lat.set_mfp_field(mfp)
+        lat.set_temperature(T0)
+        lat.set_flux_window(5)
+    for n in (40, 13, 6):
+        a.step(n)
+        b.step(n)
+        assert torch.equal(a.populations(), b.populations()), n
+        for u, v in zip(a.heat_flux(averaged=True), b.heat_flux(averaged=True)):
+            assert torch.equal(u, v)
+    a.close()
+    b.close()
+
+
+def test_fused_then_adjoint_tape_and_restart():
+    """Tapes and restarts still run single steps; a fused run continued from a
+    saved state matches an unfused one."""
+    nx, ny, q = 90, 50, 16
+    a, b = _pair(nx, ny, q, mfp=7.0)
+    T0 = torch.from_numpy(inputs.random_temperature(8, ny, nx))
+    for lat in (a, b):
+        lat.set_temperature(T0)
+        lat.step(11)
+    tape = a.new_states(5)
+    a.step_tape(5, tape)
+    b.step(5)
+    assert torch.equal(a.populations(), b.populations())
+    a.load_state(tape[2], 14)
+    a.step(9)
+    b.load_state(tape[2], 14)
+    b.step(9)
+    assert torch.equal(a.populations(), b.populations())
+    a.close()
+    b.close()
