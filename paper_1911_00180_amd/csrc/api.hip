@@ -111,6 +111,9 @@ wlbm_status validate(const wlbm_params* p) {
   if (p->dir_split && p->q % (kMaxGroupPlanes * p->dir_split) != 0)
     return fail(WLBM_EINVAL, "q = %d cannot be split over %d waves (needs a multiple of %d)",
                 p->q, p->dir_split, kMaxGroupPlanes * p->dir_split);
+  if (p->dir_split && step_batch_lds_bytes(p->q, p->dir_split) > 48 * 1024)
+    return fail(WLBM_EINVAL, "q = %d is too large for a split over %d waves", p->q,
+                p->dir_split);
   if (p->sched_chunk != 0 && (p->sched_chunk < 16 || p->sched_chunk > 65536))
     return fail(WLBM_EINVAL, "sched_chunk must be 0 or 16..65536");
   for (int k = 0; k < 3; ++k)
@@ -220,8 +223,9 @@ wlbm_status check_lat(const wlbm_lattice* l) {
 // which keeps waves short-lived; measured best on 1024^2 x 64 and
 // 4096^2 x 256 lattices.
 int auto_split(int q) {
-  if (q % (4 * kMaxGroupPlanes) == 0) return 4;
-  if (q % (2 * kMaxGroupPlanes) == 0) return 2;
+  constexpr size_t kMaxBatchLds = 48 * 1024;
+  if (q % (4 * kMaxGroupPlanes) == 0 && step_batch_lds_bytes(q, 4) <= kMaxBatchLds) return 4;
+  if (q % (2 * kMaxGroupPlanes) == 0 && step_batch_lds_bytes(q, 2) <= kMaxBatchLds) return 2;
   return 1;
 }
 
@@ -675,7 +679,7 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
   // and a direction share per wave the fused kernel is built for
   const bool fuse = l->p.step_fusion && !tape && l->nsrc == 0 &&
                     l->g.x_edge == kPeriodic && l->g.y_edge == kPeriodic &&
-                    step2_supported(q, l->split);
+                    step2_supported(q);
 
   // the two-step kernel reads the second ghost column; other producers
   // write the first one only, so the frame is refreshed before the first
@@ -757,7 +761,7 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
             e = fill_ghosts(l->ptr(l->c.Wf), a.plane, 1, a.nx, a.ny, a.pitch, l->stream);
           refresh_ghosts = false;
         }
-        if (e == hipSuccess) e = launch_step2(a2, l->split, l->per_cell, l->stream);
+        if (e == hipSuccess) e = launch_step2(a2, l->per_cell, l->stream);
         if (e != hipSuccess) {
           l->broken = true;
           return fail(WLBM_EHIP, "fused step kernel launch failed: %s", hipGetErrorString(e));
@@ -1176,6 +1180,8 @@ wlbm_status wlbm_set_dir_split(wlbm_lattice* l, int32_t split) {
     return fail(WLBM_EINVAL, "dir_split must be 0, 1, 2 or 4");
   if (l->p.q % (kMaxGroupPlanes * split) != 0)
     return fail(WLBM_EINVAL, "q = %d cannot be split over %d waves", l->p.q, split);
+  if (step_batch_lds_bytes(l->p.q, split) > 48 * 1024)
+    return fail(WLBM_EINVAL, "q = %d is too large for a split over %d waves", l->p.q, split);
   l->split = split;
   return WLBM_OK;
 }
@@ -1297,6 +1303,7 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
   ba.first = reinterpret_cast<const int*>(b->ws + b->off_first);
   ba.n = n;
   ba.nblocks = first[size_t(n)];
+  ba.q = q;
   const int64_t flux_from = l0->flux_window > 0 ? nsteps - l0->flux_window : nsteps;
   TasState tas = l0->tas;
   std::vector<int8_t> dx(q), dy(q);
@@ -1413,7 +1420,8 @@ wlbm_status wlbm_autotune(wlbm_lattice* l, void* d_state, size_t bytes, int32_t 
   l->flux_window = 0;  // the tuning steps leave the flux-window sums alone
   for (int k = 0; k < 3 && st == WLBM_OK; ++k) {
     float ms = -1.f;
-    if (l->p.q % (kMaxGroupPlanes * cand[k]) == 0) {
+    if (l->p.q % (kMaxGroupPlanes * cand[k]) == 0 &&
+        step_batch_lds_bytes(l->p.q, cand[k]) <= 48 * 1024) {
       l->split = cand[k];
       st = run_steps(l, 2, nullptr, 0);  // warm-up
       if (!st && (he = hipEventRecord(e0, l->stream)) != hipSuccess)

@@ -81,10 +81,13 @@ constexpr int kMaxGroupPlanes = 8;
 hipError_t launch_step(const StepArgs& a, int split, bool per_cell, bool flux, hipStream_t s);
 int tiles_x_for(int nx);
 int tiles_y_for(int ny, int split);
+// Dynamic LDS of a step block: the 8-direction batch sums of E' when the
+// directions of a cell are split over several waves.
+size_t step_batch_lds_bytes(int q, int split);
 
 // Two time steps (n+1, n+2) of a lattice with periodic x and y edges in one
 // launch; codes1 / codes2 are the schedule rows of the two steps.  Same
-// results as two launch_step calls with the same split.
+// results as two launch_step calls.
 struct Step2Args {
   const float* e_in;
   float* e_out;
@@ -99,16 +102,16 @@ struct Step2Args {
   long long plane;
   int strips_x, strips_y;
 };
-hipError_t launch_step2(const Step2Args& a, int split, bool per_cell, hipStream_t s);
+hipError_t launch_step2(const Step2Args& a, bool per_cell, hipStream_t s);
 // Ghost frame (both ghost columns each side, ghost rows) of nplanes periodic
 // planes from the cells they wrap to.
 hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny, int pitch,
                        hipStream_t s);
 int step2_strips_x(int nx);
 int step2_strips_y(int ny);
-// Whether the fused kernel is built for this q and direction split (q / split
-// directions per wave: 8 or 16).
-bool step2_supported(int q, int split);
+// Whether the two-step kernel is built for this q (multiples of 8 up to 64,
+// of 16 up to 128).
+bool step2_supported(int q);
 
 // One time step of n lattices in one launch (same q, direction set and
 // schedule row).  lats holds, for each lattice j, its arguments for buffer
@@ -121,6 +124,7 @@ struct BatchStepArgs {
   const uint32_t* codes;
   float in_lo_hop, in_lo_all, in_hi_hop, in_hi_all;
   int n, nblocks, parity, q_first;
+  int q;
 };
 hipError_t launch_step_batch(const BatchStepArgs& b, int split, bool per_cell, bool flux,
                              hipStream_t s);

@@ -5,8 +5,8 @@
 // from HBM once and written once per two steps, instead of once per step.
 //
 // A block owns a strip of 60 columns and kRows2 rows of the output.  Its NW
-// waves cover the same 64 columns x0-2 .. x0+61, one per lane, and split the
-// directions as k_step does (Q/NW = SH each).  Rows are pipelined: for
+// waves cover the same 64 columns x0-2 .. x0+61, one per lane, and take SH
+// directions each (8, or 16 above Q = 64).  Rows are pipelined: for
 // intermediate row r = y0-1 .. y0+kRows2 the waves compute step n+1 from the
 // step-n populations in HBM and keep it in registers, a ring of three rows;
 // as soon as rows r-2 .. r are there they compute step n+2 of row r-1.  The
@@ -16,9 +16,9 @@
 // ghost frame of periodic x edges, which must be valid on entry (the caller
 // refreshes it after other producers) and which k_fill_ghosts refreshes
 // after the launch (the kernel itself writes the cells only).  E of the intermediate rows is summed over
-// the waves in LDS in k_step's fixed order, and every update uses k_step's
-// arithmetic, so one k_step2 launch gives the same bits as two k_step
-// launches with the same direction split.
+// the waves in LDS in k_step's order (8-direction batch sums in batch order),
+// and every update uses k_step's arithmetic, so one k_step2 launch gives the
+// same bits as two k_step launches.
 #include "device.hpp"
 #include "kernel_common.hpp"
 
@@ -26,7 +26,7 @@ namespace wlbm {
 namespace {
 
 constexpr int kStrip = 60;   // output columns per block (lanes 2 .. 61)
-constexpr int kRows2 = 16;   // output rows per block (kRows2 + 2 divisible by 3)
+constexpr int kRows2 = 4;    // output rows per block (kRows2 + 2 divisible by 3)
 static_assert((kRows2 + 2) % 3 == 0, "the row loop is unrolled by three");
 
 // Value held by lane l - 1 (the cell at x - 1), lane l + 1 (x + 1).
@@ -127,10 +127,12 @@ __device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float*
   const int i_begin = part * SH;
 
   // ---- step n+1, row r ----
-  float Eacc = 0.f;
+  constexpr int NB = NW * SH / kMaxGroupPlanes;   // batches of 8 directions
+  float* p1 = sP + (t & 1) * NB * 64;
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
+    float bsum = 0.f;
     uint32_t words[kMaxGroupPlanes / 4];
 #pragma unroll
     for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes1[(i0 >> 2) + k];
@@ -153,21 +155,20 @@ __device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float*
         out = e + fmaf(wi, Es, -(Wh * e));
       }
       g.X[S][b0 + d] = out;
-      Eacc += out;
+      bsum += out;
     }
+    p1[(i0 / kMaxGroupPlanes) * 64 + lane] = bsum;
   }
   // W of this row for the second step, before slot S is refilled
   if constexpr (WF) g.W1[S] = g.Wn[S1];
   const float Wrow = WF ? g.Wn[S1] : 1.f;
   // loads of the next intermediate row (its step-n row r + 2 goes to slot S)
   if (t + 1 < kRows2 + 2) issue_row<SH, WF, S>(a, g, r + 1, i_begin, lcol);
-  // E of row r over all waves, in k_step's order
-  float* p1 = sP + (t & 1) * NW * 64;
-  p1[part * 64 + lane] = Eacc;
+  // E of row r: the batch sums in batch order, as k_step adds them
   lds_barrier();
-  float E1 = p1[lane];
+  float E1 = 0.f;
 #pragma unroll
-  for (int k = 1; k < NW; ++k) E1 += p1[k * 64 + lane];
+  for (int k = 0; k < NB; ++k) E1 += p1[k * 64 + lane];
   if constexpr (WF)
     g.E1[S] = E1 * Wrow;
   else
@@ -180,10 +181,11 @@ __device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float*
   (void)pitch;
   const int xo = x0 - 2 + lane;
   const uint32_t ob = uint32_t(cell(store ? xo : 0, store ? ro : 0, pitch) * 4);
-  float E2acc = 0.f;
+  float* p2 = sP + (2 + (t & 1)) * NB * 64;
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
+    float bsum = 0.f;
     uint32_t words[kMaxGroupPlanes / 4];
 #pragma unroll
     for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes2[(i0 >> 2) + k];
@@ -208,17 +210,16 @@ __device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float*
         const float Wh = at_minus(pick3(g.W1[S], g.W1[S2], g.W1[S1], hy + 1), hx);
         out = e + fmaf(wi, Es, -(Wh * e));
       }
-      E2acc += out;
+      bsum += out;
       if (store) buf_store_stream(out, ro_rs, ob, uint32_t(d * plane_bytes));
     }
+    p2[(i0 / kMaxGroupPlanes) * 64 + lane] = bsum;
   }
-  float* p2 = sP + (2 + (t & 1)) * NW * 64;
-  p2[part * 64 + lane] = E2acc;
   lds_barrier();
   if (part == 0 && store) {
-    float E2 = p2[lane];
+    float E2 = 0.f;
 #pragma unroll
-    for (int k = 1; k < NW; ++k) E2 += p2[k * 64 + lane];
+    for (int k = 0; k < NB; ++k) E2 += p2[k * 64 + lane];
     buf_store(E2, make_rsrc(a.E_out, plane_bytes), ob);
   }
 }
@@ -251,7 +252,8 @@ __global__ __launch_bounds__(kBlock) void k_fill_ghosts(float* base, long long p
 
 template <int NW, int SH, bool WF>
 __global__ __launch_bounds__(64 * NW) void k_step2(const Step2Args a) {
-  __shared__ float sP[4 * NW * 64];   // E partial sums: [intermediate | output][parity][wave]
+  // E batch sums: [intermediate | output][row parity][batch of 8 directions][lane]
+  __shared__ float sP[4 * (NW * SH / kMaxGroupPlanes) * 64];
   const int lane = threadIdx.x & 63;
   const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = xcd_tile(blockIdx.x, gridDim.x);
@@ -313,21 +315,30 @@ hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny
 
 int step2_strips_x(int nx) { return (nx + kStrip - 1) / kStrip; }
 int step2_strips_y(int ny) { return (ny + kRows2 - 1) / kRows2; }
-bool step2_supported(int q, int split) {
-  if (split != 1 && split != 2 && split != 4) return false;
-  const int sh = q / split;
-  return sh == 8 || sh == 16;
+// Waves per block: one per 8 directions up to q = 64, one per 16 up to 128.
+bool step2_supported(int q) {
+  return q % kMaxGroupPlanes == 0 && (q <= 64 || (q <= 128 && q % 16 == 0));
 }
 
-hipError_t launch_step2(const Step2Args& a, int split, bool per_cell, hipStream_t s) {
-  const int sh = a.q / split;
-  switch (split * 100 + sh) {
-    case 108: return launch2<1, 8>(a, per_cell, s);
-    case 116: return launch2<1, 16>(a, per_cell, s);
-    case 208: return launch2<2, 8>(a, per_cell, s);
-    case 216: return launch2<2, 16>(a, per_cell, s);
-    case 408: return launch2<4, 8>(a, per_cell, s);
-    case 416: return launch2<4, 16>(a, per_cell, s);
+hipError_t launch_step2(const Step2Args& a, bool per_cell, hipStream_t s) {
+  if (a.q <= 64) {
+    switch (a.q / 8) {
+      case 1: return launch2<1, 8>(a, per_cell, s);
+      case 2: return launch2<2, 8>(a, per_cell, s);
+      case 3: return launch2<3, 8>(a, per_cell, s);
+      case 4: return launch2<4, 8>(a, per_cell, s);
+      case 5: return launch2<5, 8>(a, per_cell, s);
+      case 6: return launch2<6, 8>(a, per_cell, s);
+      case 7: return launch2<7, 8>(a, per_cell, s);
+      case 8: return launch2<8, 8>(a, per_cell, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (a.q / 16) {
+    case 5: return launch2<5, 16>(a, per_cell, s);
+    case 6: return launch2<6, 16>(a, per_cell, s);
+    case 7: return launch2<7, 16>(a, per_cell, s);
+    case 8: return launch2<8, 16>(a, per_cell, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -103,10 +103,15 @@ __device__ __forceinline__ void load_batch(const StepArgs& a, int i0, uint32_t b
 // outside the lattice, apply the wall conditions and write the ghost copies
 // of periodic edges.  Interior tiles need none of that: every source cell of
 // a pull lies inside the padded arrays, with no wrap arithmetic.
+// E' = sum_i out_i is added in a fixed order that does not depend on the
+// direction split: each batch of D = 8 directions is summed in direction
+// order, then the batch sums are added in batch order (sBat holds them when
+// several waves share a cell).  The two-step kernel adds in the same order.
 template <int NW, bool WF, bool FLUX, bool EDGE>
 __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const float* sW,
-                                      const float* sTg, const float* sWTg, float* sRed, int x0,
-                                      int y0, uint32_t boff, const float (&v0)[TileShape<NW>::D]) {
+                                      const float* sTg, const float* sWTg, float* sRed,
+                                      float* sBat, int x0, int y0, uint32_t boff,
+                                      const float (&v0)[TileShape<NW>::D]) {
   using T = TileShape<NW>;
   constexpr int D = T::D;
   const WLBM_CONST uint32_t* codes = scalar_ptr(a.codes);
@@ -133,7 +138,9 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
 
   float Eacc = 0.f, qx = 0.f, qy = 0.f;
   const int share = a.q / NW;
+  constexpr int nrow = T::TY * 64;           // cells of the tile
   auto relax_batch = [&](int i0, const float (&v)[D]) {
+    float bsum = 0.f;
     uint32_t words[D / 4];
 #pragma unroll
     for (int k = 0; k < D / 4; ++k) words[k] = codes[(i0 >> 2) + k];
@@ -192,12 +199,16 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
       } else {
         buf_store_stream(out, ro, boff, d * plane_bytes);
       }
-      Eacc += out;
+      bsum += out;
       if constexpr (FLUX) {
         qx = fmaf(out, sxtab[i], qx);
         qy = fmaf(out, sytab[i], qy);
       }
     }
+    if constexpr (NW == 1)
+      Eacc += bsum;
+    else
+      sBat[(i0 / D) * nrow + row * 64 + lane] = bsum;
   };
   // the first batch was loaded before the E tile was staged
   relax_batch(part * share, v0);
@@ -208,28 +219,25 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
   }
 
   if constexpr (NW > 1) {
-    // partial sums of the NW waves of a row, added in a fixed order
-    constexpr int n = T::TY * 64;
+    // batch sums of E' in batch order; flux partials of the NW waves in
+    // wave order
+    constexpr int n = nrow;
     const int slot = (part * T::TY + row) * 64 + lane;
-    sRed[slot] = Eacc;
     if constexpr (FLUX) {
-      sRed[NW * n + slot] = qx;
-      sRed[2 * NW * n + slot] = qy;
+      sRed[slot] = qx;
+      sRed[NW * n + slot] = qy;
     }
     lds_barrier();
     if (part != 0) return;
     const int base = row * 64 + lane;
-    Eacc = sRed[base];
+    for (int k = 0; k < a.q / D; ++k) Eacc += sBat[k * n + base];
     if constexpr (FLUX) {
-      qx = sRed[NW * n + base];
-      qy = sRed[2 * NW * n + base];
-    }
+      qx = sRed[base];
+      qy = sRed[NW * n + base];
 #pragma unroll
-    for (int k = 1; k < NW; ++k) {
-      Eacc += sRed[k * n + base];
-      if constexpr (FLUX) {
-        qx += sRed[NW * n + k * n + base];
-        qy += sRed[2 * NW * n + k * n + base];
+      for (int k = 1; k < NW; ++k) {
+        qx += sRed[k * n + base];
+        qy += sRed[NW * n + k * n + base];
       }
     }
   }
@@ -258,7 +266,7 @@ struct StepShared {
   float sW[WF ? T::LH * T::LP : 1];
   float sTg[2 * T::LP];
   float sWTg[2 * T::LP];
-  float sRed[NW > 1 ? (FLUX ? 3 : 1) * kBlock : 1];
+  float sRed[NW > 1 && FLUX ? 2 * kBlock : 1];
 };
 
 // One block's tile t of one time step of lattice a.
@@ -271,6 +279,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
   float* sTg = sh.sTg;
   float* sWTg = sh.sWTg;
   float* sRed = sh.sRed;
+  extern __shared__ float sBat[];   // [q / 8][tile cells] when NW > 1
   const int tx = t % a.tiles_x;
   const int ty = t / a.tiles_x;
   const int x0 = tx * T::TX;
@@ -322,9 +331,9 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
   }
   __syncthreads();
   if (edge)
-    sweep<NW, WF, FLUX, true>(a, sE, sW, sTg, sWTg, sRed, x0, y0, boff, v0);
+    sweep<NW, WF, FLUX, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0);
   else
-    sweep<NW, WF, FLUX, false>(a, sE, sW, sTg, sWTg, sRed, x0, y0, boff, v0);
+    sweep<NW, WF, FLUX, false>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0);
 }
 
 template <int NW, bool WF, bool FLUX>
@@ -359,7 +368,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 
 template <int NW, bool WF, bool FLUX>
 hipError_t launch_tmpl(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL((k_step<NW, WF, FLUX>), dim3(a.ntiles), dim3(kBlock), 0, s, a);
+  hipLaunchKernelGGL((k_step<NW, WF, FLUX>), dim3(a.ntiles), dim3(kBlock),
+                     step_batch_lds_bytes(a.q, NW), s, a);
   return hipGetLastError();
 }
 
@@ -609,6 +619,11 @@ unsigned cell_blocks(const Geometry& g) {
 
 }  // namespace
 
+size_t step_batch_lds_bytes(int q, int split) {
+  if (split <= 1) return 0;
+  return size_t(q / kMaxGroupPlanes) * (4 / split) * 64 * sizeof(float);
+}
+
 int tiles_x_for(int nx) { return (nx + 63) / 64; }
 int tiles_y_for(int ny, int split) {
   const int ty = 4 / split;
@@ -617,7 +632,8 @@ int tiles_y_for(int ny, int split) {
 
 template <int NW, bool WF, bool FLUX>
 hipError_t launch_batch_tmpl(const BatchStepArgs& b, hipStream_t s) {
-  hipLaunchKernelGGL((k_step_batch<NW, WF, FLUX>), dim3(b.nblocks), dim3(kBlock), 0, s, b);
+  hipLaunchKernelGGL((k_step_batch<NW, WF, FLUX>), dim3(b.nblocks), dim3(kBlock),
+                     step_batch_lds_bytes(b.q, NW), s, b);
   return hipGetLastError();
 }
 

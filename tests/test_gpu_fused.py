@@ -1,8 +1,8 @@
 """Two steps per launch (k_step2) against one step per launch (k_step).
 
 The fused kernel uses the same arithmetic and the same summation order as the
-single-step kernel, so with the same direction split the populations must
-agree bit for bit, on ragged and tiny lattices, for odd step counts (the last
+single-step kernel, so the populations must agree bit for bit, whatever
+direction split the single steps use, on ragged and tiny lattices, for odd step counts (the last
 step runs alone), across schedule chunks and around flux windows (whose steps
 run alone).  Oracle parity of the fused path is covered by every periodic
 parity test, which now runs it by default.

@@ -289,3 +289,28 @@ def test_crop_256_q64_4000_steps(kn):
     assert abs(float(np.abs(T).max()) - ref["max_abs_T"]) <= tol
     e, _, _ = lat.totals()
     assert abs(e - ref["energy"]) <= 1e-6 * ref["energy"]
+
+
+@pytest.mark.parametrize("q", [16, 32, 64])
+def test_direction_splits_are_bit_identical(q):
+    """E is summed in the same order (8-direction batch sums, added in batch
+    order) whatever the split of the directions over waves, so every split,
+    and the two-steps-per-launch path, gives the same bits."""
+    nx, ny = 141, 29
+    e0 = torch.from_numpy(inputs.random_populations(5, q, ny, nx))
+    runs = []
+    for split in (1, 2, 4):
+        if q // split < 8:
+            continue
+        for fusion in (False, True):
+            for edges in (dict(x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0), dict()):
+                lat = _lattice(nx=nx, ny=ny, q=q, mfp=6.0, dir_split=split,
+                               step_fusion=fusion, **edges)
+                lat.set_populations(e0)
+                lat.step(13)
+                runs.append((bool(edges), split, fusion, lat.populations().cpu()))
+                lat.close()
+    for walls in (False, True):
+        same = [r for r in runs if r[0] == walls]
+        for r in same[1:]:
+            assert torch.equal(r[3], same[0][3]), r[:3]
