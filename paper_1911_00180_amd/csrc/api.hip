@@ -679,7 +679,7 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
   // and a direction share per wave the fused kernel is built for
   const bool fuse = l->p.step_fusion && !tape && l->nsrc == 0 &&
                     l->g.x_edge == kPeriodic && l->g.y_edge == kPeriodic &&
-                    step2_supported(q);
+                    step2_supported(q, l->g.nx, l->g.ny);
 
   // the two-step kernel reads the second ghost column; other producers
   // write the first one only, so the frame is refreshed before the first

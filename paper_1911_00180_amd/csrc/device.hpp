@@ -109,9 +109,9 @@ hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny
                        hipStream_t s);
 int step2_strips_x(int nx);
 int step2_strips_y(int ny);
-// Whether the two-step kernel is built for this q (multiples of 8 up to 64,
-// of 16 up to 128).
-bool step2_supported(int q);
+// Whether the two-step kernel takes this lattice: q a multiple of 8 up to 64
+// or of 16 up to 128, nx >= 4, ny >= 2.
+bool step2_supported(int q, int nx, int ny);
 
 // One time step of n lattices in one launch (same q, direction set and
 // schedule row).  lats holds, for each lattice j, its arguments for buffer

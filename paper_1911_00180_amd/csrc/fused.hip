@@ -14,8 +14,8 @@
 // wave_shr / wave_shl), so step n+1 is valid on lanes 1..62 and step n+2 on
 // lanes 2..61.  Rows wrap by index arithmetic; columns read the two-deep
 // ghost frame of periodic x edges, which must be valid on entry (the caller
-// refreshes it after other producers) and which k_fill_ghosts refreshes
-// after the launch (the kernel itself writes the cells only).  E of the intermediate rows is summed over
+// refreshes it with k_fill_ghosts after other producers) and which the
+// kernel writes for its output.  E of each row is summed over
 // the waves in LDS in k_step's order (8-direction batch sums in batch order),
 // and every update uses k_step's arithmetic, so one k_step2 launch gives the
 // same bits as two k_step launches.
@@ -29,25 +29,82 @@ constexpr int kStrip = 60;   // output columns per block (lanes 2 .. 61)
 constexpr int kRows2 = 4;    // output rows per block (kRows2 + 2 divisible by 3)
 static_assert((kRows2 + 2) % 3 == 0, "the row loop is unrolled by three");
 
-// Value held by lane l - 1 (the cell at x - 1), lane l + 1 (x + 1).
+// Value held by lane l - 1 (the cell at x - 1), lane l + 1 (x + 1); lanes
+// with no such neighbour (0, resp. 63) read zero (bound control), which no
+// result uses.
 __device__ __forceinline__ float from_lower_lane(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0x138, 0xF, 0xF, false));
+                                                               0x138, 0xF, 0xF, true));
 }
 __device__ __forceinline__ float from_upper_lane(float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v),
-                                                               0x130, 0xF, 0xF, false));
+                                                               0x130, 0xF, 0xF, true));
 }
-// The value at column x - dx; dx is the same in every lane.  Both shifts are
-// computed and one is selected, so that no branch surrounds the (convergent)
-// lane shifts.
-__device__ __forceinline__ float at_minus(float v, int dx) {
+// Selections by a direction's move are wave-uniform.  Rather than comparing
+// and selecting on the decoded move in scalar code for every direction and
+// row, the kernel loads the lane masks of the move's code from this table
+// (one scalar load per direction) and selects with bitwise operations.
+// Entry c: the masks for dy, dx (the move) and hy, hx (the move if the code
+// hops, else no move) of code c (dx + 1 | (dy + 1) << 2 | hop << 4), and the
+// byte shift 4 (1 - hx) of a pull's column.
+// Words 0..7 serve the relaxation and the second step, 8..11 the pulls of the
+// first step, so that each use site loads one contiguous run.
+enum SelWord : int {
+  kDyLo, kDyMid, kDxPos, kDxNeg, kHyLo, kHyMid, kHxPos, kHxNeg,
+  kPullHyLo, kPullHyMid, kPullHyHi, kCol4, kSelWords = 16
+};
+struct CodeSel {
+  uint32_t m[32][kSelWords];
+};
+constexpr CodeSel make_code_sel() {
+  CodeSel t{};
+  for (int c = 0; c < 32; ++c) {
+    const int dx = (c & 3) - 1, dy = ((c >> 2) & 3) - 1;
+    const bool hop = (c >> 4) & 1;
+    const int hx = hop ? dx : 0, hy = hop ? dy : 0;
+    auto m = [](bool b) { return b ? 0xffffffffu : 0u; };
+    t.m[c][kDyLo] = m(dy == -1);
+    t.m[c][kDyMid] = m(dy == 0);
+    t.m[c][kDxPos] = m(dx > 0);
+    t.m[c][kDxNeg] = m(dx < 0);
+    t.m[c][kHyLo] = t.m[c][kPullHyLo] = m(hy == -1);
+    t.m[c][kHyMid] = t.m[c][kPullHyMid] = m(hy == 0);
+    t.m[c][kPullHyHi] = m(hy == 1);
+    t.m[c][kHxPos] = m(hx > 0);
+    t.m[c][kHxNeg] = m(hx < 0);
+    t.m[c][kCol4] = uint32_t(4 * (1 - hx));
+  }
+  return t;
+}
+__constant__ CodeSel kCodeSel = make_code_sel();
+
+// The selection masks of direction d of a batch whose codes are `words`.
+__device__ __forceinline__ const WLBM_CONST uint32_t* sel_of(const WLBM_CONST uint32_t* tab,
+                                                             const uint32_t* words, int d) {
+  return tab + ((words[d >> 2] >> (8 * (d & 3))) & 31u) * kSelWords;
+}
+__device__ __forceinline__ float bsel(uint32_t m, float a, float b) {
+  return __builtin_bit_cast(float, (__builtin_bit_cast(uint32_t, a) & m) |
+                                       (__builtin_bit_cast(uint32_t, b) & ~m));
+}
+// a where m_lo, b where m_mid, else c
+__device__ __forceinline__ float pick3m(float a, float b, float c, uint32_t m_lo, uint32_t m_mid) {
+  return bsel(m_lo, a, bsel(m_mid, b, c));
+}
+// The value at column x - dx (dx uniform, given by its masks).  Both shifts
+// are computed and one is selected, so that no branch surrounds the
+// (convergent) lane shifts.
+__device__ __forceinline__ float at_minus(float v, uint32_t m_pos, uint32_t m_neg) {
   const float lo = from_lower_lane(v), up = from_upper_lane(v);
-  return dx > 0 ? lo : (dx < 0 ? up : v);
+  return bsel(m_pos, lo, bsel(m_neg, up, v));
 }
+// A scalar-cache pointer that the optimizer cannot see through: loads through
+// it are re-issued in every row instead of being hoisted out of the row loop
+// and kept (spilled) in scalar registers with everything derived from them.
 template <class T>
-__device__ __forceinline__ T pick3(T a, T b, T c, int k) {
-  return k == 0 ? a : (k == 1 ? b : c);
+__device__ __forceinline__ const WLBM_CONST T* row_ptr(const T* p) {
+  __asm__ volatile("" : "+s"(p));
+  return scalar_ptr(p);
 }
 
 template <int SH>
@@ -66,7 +123,8 @@ struct Ring {
 template <int SH, bool WF, int SN>
 __device__ __forceinline__ void issue_row(const Step2Args& a, Ring<SH>& g, int r, int i_begin,
                                           uint32_t lcol) {
-  const WLBM_CONST uint32_t* codes1 = scalar_ptr(a.codes1);
+  const WLBM_CONST uint32_t* codes1 = row_ptr(a.codes1);
+  const WLBM_CONST uint32_t* tab = row_ptr(&kCodeSel.m[0][0]);
   const long long plane = a.plane;
   const uint32_t plane_bytes = uint32_t(plane * 4);
   auto row_bytes = [&](int rr) { return uint32_t((wrap_index(rr, a.ny) + 1) * a.pitch * 4); };
@@ -92,13 +150,9 @@ __device__ __forceinline__ void issue_row(const Step2Args& a, Ring<SH>& g, int r
                                 uint32_t((kMaxGroupPlanes * plane + 2) * 4));
 #pragma unroll
     for (int d = 0; d < kMaxGroupPlanes; ++d) {
-      int dx, dy;
-      bool hop;
-      decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
-      const int hx = hop ? dx : 0, hy = hop ? dy : 0;
-      g.V[b0 + d] = buf_load(rs, lcol,
-                             uint32_t(d * plane_bytes) + pick3(rb_m, rb_0, rb_p, hy + 1) +
-                                 uint32_t(4 * (1 - hx)));
+      const WLBM_CONST uint32_t* m = sel_of(tab, words, d);
+      const uint32_t rowb = (rb_m & m[kPullHyLo]) | (rb_0 & m[kPullHyMid]) | (rb_p & m[kPullHyHi]);
+      g.V[b0 + d] = buf_load(rs, lcol, uint32_t(d) * plane_bytes + rowb + m[kCol4]);
     }
   }
 }
@@ -113,16 +167,18 @@ __device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float*
                                          int x0, int y0, int lane, int part, uint32_t lcol,
                                          bool out_lane) {
   constexpr int S1 = (S + 1) % 3, S2 = (S + 2) % 3;
-  // Keep the compiler from hoisting the schedule decoding of every direction
-  // out of the row loop (it would hold all of it in scalar registers and
-  // spill); the codes are re-read from the scalar cache for each row.
-  __asm__ volatile("" ::: "memory");
-  const WLBM_CONST uint32_t* codes1 = scalar_ptr(a.codes1);
-  const WLBM_CONST uint32_t* codes2 = scalar_ptr(a.codes2);
-  const WLBM_CONST float* wtab = scalar_ptr(a.wtab);
+  // the schedule codes and weights are re-read from the scalar cache for
+  // each row
+  const WLBM_CONST uint32_t* codes1 = row_ptr(a.codes1);
+  const WLBM_CONST uint32_t* codes2 = row_ptr(a.codes2);
+  const WLBM_CONST float* wtab = row_ptr(a.wtab);
+  const WLBM_CONST uint32_t* tab = row_ptr(&kCodeSel.m[0][0]);
   const int ny = a.ny, pitch = a.pitch;
   const long long plane = a.plane;
-  const uint32_t plane_bytes = uint32_t(plane * 4);
+  // opaque to the optimizer, so that the per-direction plane offsets are
+  // recomputed in every row rather than held in (spilled) scalar registers
+  uint32_t plane_bytes = uint32_t(plane * 4);
+  __asm__ volatile("" : "+s"(plane_bytes));
   const int r = y0 - 1 + t;
   const int i_begin = part * SH;
 
@@ -139,19 +195,19 @@ __device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float*
 #pragma unroll
     for (int d = 0; d < kMaxGroupPlanes; ++d) {
       const int i = i0 + d;
-      int dx, dy;
-      bool hop;
-      decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
+      const WLBM_CONST uint32_t* m = sel_of(tab, words, d);
       const float wi = wtab[i];
       const float e = g.V[b0 + d];
       // source rows r - dy: dy = -1 -> slot S2, 0 -> S1, 1 -> S
-      const float Es = at_minus(pick3(g.En[S2], g.En[S1], g.En[S], dy + 1), dx);
+      const float Es = at_minus(pick3m(g.En[S2], g.En[S1], g.En[S], m[kDyLo], m[kDyMid]),
+                                m[kDxPos], m[kDxNeg]);
       float out;
       if constexpr (!WF) {
         out = fmaf(a.W, fmaf(wi, Es, -e), e);
       } else {
-        const float Wh = hop ? at_minus(pick3(g.Wn[S2], g.Wn[S1], g.Wn[S], dy + 1), dx)
-                             : g.Wn[S1];
+        // W where the pulled population was: moved by (hx, hy)
+        const float Wh = at_minus(pick3m(g.Wn[S2], g.Wn[S1], g.Wn[S], m[kHyLo], m[kHyMid]),
+                                  m[kHxPos], m[kHxNeg]);
         out = e + fmaf(wi, Es, -(Wh * e));
       }
       g.X[S][b0 + d] = out;
@@ -178,9 +234,25 @@ __device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float*
   // ---- step n+2, row ro = r - 1 ----
   const int ro = r - 1;
   const bool store = out_lane && ro < ny;
-  (void)pitch;
+  const int nx = a.nx;
   const int xo = x0 - 2 + lane;
-  const uint32_t ob = uint32_t(cell(store ? xo : 0, store ? ro : 0, pitch) * 4);
+  // byte offsets of the cell and its ghosts (used only where stored)
+  const int row_o = (ro + 1) * pitch + kXOff;
+  const uint32_t ob = uint32_t((row_o + xo) * 4);
+  // Ghost copies of this cell in the two-deep frame (nx >= 4 and ny >= 2, so
+  // a cell has at most one ghost column and one ghost row): columns 0, 1 are
+  // copied to nx, nx + 1 and columns nx - 2, nx - 1 to -2, -1; rows 0 and
+  // ny - 1 to ny and -1.  Only blocks on the lattice's edge have any, which
+  // the whole block knows.
+  const bool edge = x0 == 0 || x0 + kStrip + 1 >= nx || ro == 0 || ro == ny - 1;
+  const bool gx = store && (xo < 2 || xo >= nx - 2);
+  const bool gy = store && (ro == 0 || ro == ny - 1);
+  const int xg = xo < 2 ? xo + nx : xo - nx;
+  const int yg = ro == 0 ? ny : -1;
+  const int row_g = (yg + 1) * pitch + kXOff;
+  const uint32_t obx = uint32_t((row_o + xg) * 4);
+  const uint32_t oby = uint32_t((row_g + xo) * 4);
+  const uint32_t obxy = uint32_t((row_g + xg) * 4);
   float* p2 = sP + (2 + (t & 1)) * NB * 64;
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
@@ -191,41 +263,60 @@ __device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float*
     for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes2[(i0 >> 2) + k];
     const rsrc_t ro_rs = make_rsrc(a.e_out + (long long)i0 * plane,
                                    uint32_t(kMaxGroupPlanes * plane * 4));
+    float o[kMaxGroupPlanes];
 #pragma unroll
     for (int d = 0; d < kMaxGroupPlanes; ++d) {
       const int i = i0 + d;
-      int dx, dy;
-      bool hop;
-      decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
-      const int hx = hop ? dx : 0, hy = hop ? dy : 0;
+      const WLBM_CONST uint32_t* m = sel_of(tab, words, d);
       const float wi = wtab[i];
       // source rows ro - dy: dy = -1 -> r (slot S), 0 -> r - 1 (S2), 1 -> r - 2 (S1)
-      const float e = at_minus(pick3(g.X[S][b0 + d], g.X[S2][b0 + d], g.X[S1][b0 + d], hy + 1),
-                               hx);
-      const float Es = at_minus(pick3(g.E1[S], g.E1[S2], g.E1[S1], dy + 1), dx);
+      const float e = at_minus(
+          pick3m(g.X[S][b0 + d], g.X[S2][b0 + d], g.X[S1][b0 + d], m[kHyLo], m[kHyMid]),
+          m[kHxPos], m[kHxNeg]);
+      const float Es = at_minus(pick3m(g.E1[S], g.E1[S2], g.E1[S1], m[kDyLo], m[kDyMid]),
+                                m[kDxPos], m[kDxNeg]);
       float out;
       if constexpr (!WF) {
         out = fmaf(a.W, fmaf(wi, Es, -e), e);
       } else {
-        const float Wh = at_minus(pick3(g.W1[S], g.W1[S2], g.W1[S1], hy + 1), hx);
+        const float Wh = at_minus(pick3m(g.W1[S], g.W1[S2], g.W1[S1], m[kHyLo], m[kHyMid]),
+                                  m[kHxPos], m[kHxNeg]);
         out = e + fmaf(wi, Es, -(Wh * e));
       }
       bsum += out;
-      if (store) buf_store_stream(out, ro_rs, ob, uint32_t(d * plane_bytes));
+      o[d] = out;
     }
     p2[(i0 / kMaxGroupPlanes) * 64 + lane] = bsum;
+    // the batch's stores, under one lane mask each
+    auto put = [&](uint32_t off) {
+#pragma unroll
+      for (int d = 0; d < kMaxGroupPlanes; ++d)
+        buf_store_stream(o[d], ro_rs, off, uint32_t(d) * plane_bytes);
+    };
+    if (store) put(ob);
+    if (edge) {
+      if (gx) put(obx);
+      if (gy) put(oby);
+      if (gx && gy) put(obxy);
+    }
   }
   lds_barrier();
   if (part == 0 && store) {
     float E2 = 0.f;
 #pragma unroll
     for (int k = 0; k < NB; ++k) E2 += p2[k * 64 + lane];
-    buf_store(E2, make_rsrc(a.E_out, plane_bytes), ob);
+    const rsrc_t Ers = make_rsrc(a.E_out, plane_bytes);
+    buf_store(E2, Ers, ob);
+    if (edge) {
+      if (gx) buf_store(E2, Ers, obx);
+      if (gy) buf_store(E2, Ers, oby);
+      if (gx && gy) buf_store(E2, Ers, obxy);
+    }
   }
 }
 
-// Ghost frame of a periodic lattice after k_step2 (which writes the cells
-// only): every ghost cell (columns -2, -1, nx, nx + 1 of rows 0 .. ny - 1, and
+// Ghost frame of a periodic lattice written by another producer (k_step
+// writes the first ghost column and row only): every ghost cell (columns -2, -1, nx, nx + 1 of rows 0 .. ny - 1, and
 // rows -1, ny of columns -2 .. nx + 1) of planes 0 .. nplanes - 1 copies the
 // cell it wraps to.
 __global__ __launch_bounds__(kBlock) void k_fill_ghosts(float* base, long long plane, int nplanes,
@@ -297,10 +388,7 @@ hipError_t launch2(const Step2Args& a, bool wf, hipStream_t s) {
     hipLaunchKernelGGL((k_step2<NW, SH, true>), grid, block, 0, s, a);
   else
     hipLaunchKernelGGL((k_step2<NW, SH, false>), grid, block, 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e == hipSuccess) e = fill_ghosts(a.e_out, a.plane, a.q, a.nx, a.ny, a.pitch, s);
-  if (e == hipSuccess) e = fill_ghosts(a.E_out, a.plane, 1, a.nx, a.ny, a.pitch, s);
-  return e;
+  return hipGetLastError();
 }
 
 }  // namespace
@@ -316,8 +404,9 @@ hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny
 int step2_strips_x(int nx) { return (nx + kStrip - 1) / kStrip; }
 int step2_strips_y(int ny) { return (ny + kRows2 - 1) / kRows2; }
 // Waves per block: one per 8 directions up to q = 64, one per 16 up to 128.
-bool step2_supported(int q) {
-  return q % kMaxGroupPlanes == 0 && (q <= 64 || (q <= 128 && q % 16 == 0));
+bool step2_supported(int q, int nx, int ny) {
+  return nx >= 4 && ny >= 2 && q % kMaxGroupPlanes == 0 &&
+         (q <= 64 || (q <= 128 && q % 16 == 0));
 }
 
 hipError_t launch_step2(const Step2Args& a, bool per_cell, hipStream_t s) {

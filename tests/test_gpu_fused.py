@@ -39,6 +39,10 @@ def _pair(nx, ny, q, **kw):
     (20, 10, 32, 1, 9.0, "ring"),
     (5, 3, 8, 1, 2.0, "uniform"),
     (200, 17, 24, 1, 1e9, "ring"),
+    (4, 2, 16, 2, 3.0, "uniform"),     # smallest lattice the fused kernel takes
+    (61, 5, 64, 0, 8.0, "uniform"),    # last strip holds one column
+    (3, 9, 8, 1, 2.0, "uniform"),      # too narrow: single steps
+    (128, 6, 128, 0, 20.0, "uniform"),
 ])
 def test_fused_equals_single_steps(nx, ny, q, split, mfp, kind):
     a, b = _pair(nx, ny, q, mfp=mfp, dirs=kind, dir_split=split, sched_chunk=16)
