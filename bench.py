@@ -26,9 +26,14 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 CSRC = os.path.join(ROOT, "paper_1911_00180_amd", "csrc")
 STEP_SOURCES = ("kernels.hip", "kernel_common.hpp", "device.hpp")
+FUSED_SOURCES = ("fused.hip", "kernel_common.hpp", "device.hpp")
 ADJOINT_SOURCES = ("adjoint.hip", "kernel_common.hpp", "device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_1024x1024_q64_traffic.md")
+FUSED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step2_1024x1024_q64_traffic.md")
 ADJOINT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_adjoint_1024x1024_q64.md")
+# the kernels that run the default workload (1024 x 1024 periodic, Q = 64)
+FUSED_KERNEL = "k_step2<8, 8, false>"      # two time steps per launch
+STEP_KERNEL = "k_step<4, false, false>"    # one time step per launch
 
 
 def bytes_per_update(q: int, per_cell_w: bool = False) -> float:
@@ -300,15 +305,25 @@ def main():
     nx = ny = 1024
     q = 64
     mfp = args.kn * nx
+    fused = not args.single_step
+    if fused and args.steps % 2:
+        sys.exit("bench.py: --steps must be even (two time steps per launch)")
     ms, wall, energy = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.split,
-                               fusion=not args.single_step)
+                               fusion=fused)
     updates = nx * ny * q * args.steps
     gups = updates / (ms * 1e-3) / 1e9
     ms_step = ms / args.steps
     bpu = bytes_per_update(q)
+    # Dominant kernel: every population is read once and written once per
+    # launch, so the algorithmic bytes of a launch are those of one time step
+    # whether the launch advances one step or two.
+    steps_per_launch = 2 if fused else 1
+    launches = args.steps // steps_per_launch
+    ms_launch = ms / launches
     alg_bytes_launch = bpu * nx * ny * q
-    achieved = alg_bytes_launch / (ms_step * 1e-3) / 1e9
-    traffic = recorded_traffic()
+    achieved = alg_bytes_launch / (ms_launch * 1e-3) / 1e9
+    traffic = (recorded_traffic(FUSED_TRAFFIC_FILE, FUSED_SOURCES) if fused
+               else recorded_traffic())
     out = {
         "metric": "G cell-direction updates/s",
         "value": round(gups, 3),
@@ -328,6 +343,7 @@ def main():
             "nx": nx, "ny": ny, "q": q, "kn": args.kn, "mfp_cells": mfp,
             "initial": "Gaussian pulse sigma0=16 at default_rng(1911) position",
             "bytes_per_update": bpu,
+            "steps_per_launch": steps_per_launch,
         },
         "roofline": {
             "bound": "hbm",
@@ -336,10 +352,29 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "kernel": FUSED_KERNEL if fused else STEP_KERNEL,
+            "launches": launches,
+            "ms_per_launch": round(ms_launch, 5),
+            "algorithmic_bytes_per_launch": alg_bytes_launch,
         },
         "wall_s": round(wall, 4),
         "energy_after": energy,
     }
+    if fused:
+        # context: the same workload at one time step per launch
+        ms1, _, _ = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.split,
+                            fusion=False)
+        st1 = ms1 / args.steps
+        a1 = alg_bytes_launch / (st1 * 1e-3) / 1e9
+        out["single_step"] = {
+            "kernel": STEP_KERNEL,
+            "value": round(updates / (ms1 * 1e-3) / 1e9, 3),
+            "unit": "Gupdates/s",
+            "ms_per_step": round(st1, 5),
+            "achieved_GBs": round(a1, 1),
+            "frac": round(a1 / HBM_PEAK_GBS, 4),
+            "traffic": recorded_traffic(),
+        }
     if args.large:
         nl, ql = 4096, 256
         edges = dict(x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0, t_x_hi=0.0)
