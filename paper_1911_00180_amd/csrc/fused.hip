@@ -4,7 +4,7 @@
 // (Sec. 2.3 Eq. algorithm, pull form as in k_step): each population is read
 // from HBM once and written once per two steps, instead of once per step.
 //
-// A block owns a strip of 60 columns and kRows2 rows of the output.  Its NW
+// A block owns a strip of 56 columns and kRows2 rows of the output.  Its NW
 // waves cover the same 64 columns x0-2 .. x0+61, one per lane, and take SH
 // directions each (8, or 16 above Q = 64).  Rows are pipelined: for
 // intermediate row r = y0-1 .. y0+kRows2 the waves compute step n+1 from the
@@ -25,7 +25,11 @@
 namespace wlbm {
 namespace {
 
-constexpr int kStrip = 60;   // output columns per block (lanes 2 .. 61)
+// Output columns per block (lanes 2 .. 57).  A multiple of 8, so that every
+// block's output rows are whole 32-byte sectors (x = 0 starts a 128-byte line):
+// 60 columns would give every row of half the blocks a partial sector at each
+// end, and those partial writes cost more than the four idle lanes.
+constexpr int kStrip = 56;
 constexpr int kRows2 = 4;    // output rows per block (kRows2 + 2 divisible by 3)
 static_assert((kRows2 + 2) % 3 == 0, "the row loop is unrolled by three");
 
