@@ -4,7 +4,7 @@
 // (Sec. 2.3 Eq. algorithm, pull form as in k_step): each population is read
 // from HBM once and written once per two steps, instead of once per step.
 //
-// A block owns a strip of 56 columns and kRows2 rows of the output.  Its NW
+// A block owns a strip of 48 columns and kRows2 rows of the output.  Its NW
 // waves cover the same 64 columns x0-2 .. x0+61, one per lane, and take SH
 // directions each (8, or 16 above Q = 64).  Rows are pipelined: for
 // intermediate row r = y0-1 .. y0+kRows2 the waves compute step n+1 from the
@@ -25,12 +25,18 @@
 namespace wlbm {
 namespace {
 
-// Output columns per block (lanes 2 .. 57).  A multiple of 8, so that every
-// block's output rows are whole 32-byte sectors (x = 0 starts a 128-byte line):
-// 60 columns would give every row of half the blocks a partial sector at each
-// end, and those partial writes cost more than the four idle lanes.
-constexpr int kStrip = 56;
-constexpr int kRows2 = 4;    // output rows per block (kRows2 + 2 divisible by 3)
+// Output columns per block (lanes 2 .. 49).  A multiple of 16, so that every
+// block's output rows are whole 64-byte write segments (x = 0 starts a
+// 128-byte line): with 60 or 56 columns most rows end in partial segments on
+// both sides, and those partial writes cost more than the idle lanes
+// (measured at 1024 x 1024, Q = 64: 60 columns 788, 56 columns 851, 48
+// columns 928, 32 columns 723 G updates/s, 4-row blocks).
+constexpr int kStrip = 48;
+// Output rows per block (kRows2 + 2 divisible by 3): taller blocks re-read
+// fewer halo rows, shorter ones give more blocks (48-column strips at
+// 1024 x 1024, Q = 64: 4 rows 928, 7 rows 952, 10 rows 966, 13 rows 947, 16
+// rows 926 G updates/s).
+constexpr int kRows2 = 10;
 static_assert((kRows2 + 2) % 3 == 0, "the row loop is unrolled by three");
 
 // Value held by lane l - 1 (the cell at x - 1), lane l + 1 (x + 1); lanes
