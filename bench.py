@@ -29,11 +29,13 @@ STEP_SOURCES = ("kernels.hip", "kernel_common.hpp", "device.hpp")
 FUSED_SOURCES = ("fused.hip", "kernel_common.hpp", "device.hpp")
 ADJOINT_SOURCES = ("adjoint.hip", "kernel_common.hpp", "device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_1024x1024_q64_traffic.md")
-FUSED_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step2_1024x1024_q64_traffic.md")
+FUSED_TRAFFIC_FILES = {k: os.path.join(ROOT, "profiles", f"k_stepk{k}_1024x1024_q64_traffic.md")
+                       for k in (2, 3)}
 ADJOINT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_adjoint_1024x1024_q64.md")
-# the kernels that run the default workload (1024 x 1024 periodic, Q = 64)
-FUSED_KERNEL = "k_step2<8, 8, false>"      # two time steps per launch
-STEP_KERNEL = "k_step<4, false, false>"    # one time step per launch
+# the kernels that run the default workload (1024 x 1024 periodic, Q = 64),
+# by time steps per launch
+KERNELS = {1: "k_step<4, false, false>", 2: "k_stepk<8, 8, false, 2>",
+           3: "k_stepk<8, 8, false, 3>"}
 
 
 def bytes_per_update(q: int, per_cell_w: bool = False) -> float:
@@ -71,7 +73,7 @@ def recorded_traffic(path=TRAFFIC_FILE, sources=STEP_SOURCES):
         return None
 
 
-def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=True):
+def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1):
     import numpy as np
     import torch
 
@@ -262,8 +264,8 @@ def cpu_baseline(budget_s: float = 15.0):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4000)
-    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=3840)
+    ap.add_argument("--warmup", type=int, default=120)
     ap.add_argument("--kn", type=float, default=0.1, help="Knudsen number vs L = 1024")
     ap.add_argument("--split", type=int, default=0,
                     help="waves sharing one cell's directions (0 = library default)")
@@ -273,8 +275,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurements")
     ap.add_argument("--no-films", action="store_true", help="skip the batched film sweep")
+    ap.add_argument("--steps-per-launch", type=int, default=3, choices=(1, 2, 3),
+                    help="time steps per kernel launch on the default lattice")
     ap.add_argument("--single-step", action="store_true",
-                    help="one time step per kernel launch (no two-step fusion)")
+                    help="same as --steps-per-launch 1")
     ap.add_argument("--film-steps", type=int, default=10000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -305,24 +309,27 @@ def main():
     nx = ny = 1024
     q = 64
     mfp = args.kn * nx
-    fused = not args.single_step
-    if fused and args.steps % 2:
-        sys.exit("bench.py: --steps must be even (two time steps per launch)")
+    spl = 1 if args.single_step else args.steps_per_launch
+    # every launch must advance spl steps: whole schedule chunks (240 steps)
+    # split evenly
+    if args.steps % 240 % spl or args.steps % spl:
+        sys.exit(f"bench.py: --steps must split into launches of {spl} steps "
+                 "within 240-step schedule chunks")
     ms, wall, energy = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.split,
-                               fusion=fused)
+                               fusion=spl if spl > 1 else 0)
     updates = nx * ny * q * args.steps
     gups = updates / (ms * 1e-3) / 1e9
     ms_step = ms / args.steps
     bpu = bytes_per_update(q)
     # Dominant kernel: every population is read once and written once per
     # launch, so the algorithmic bytes of a launch are those of one time step
-    # whether the launch advances one step or two.
-    steps_per_launch = 2 if fused else 1
+    # however many steps the launch advances.
+    steps_per_launch = spl
     launches = args.steps // steps_per_launch
     ms_launch = ms / launches
     alg_bytes_launch = bpu * nx * ny * q
     achieved = alg_bytes_launch / (ms_launch * 1e-3) / 1e9
-    traffic = (recorded_traffic(FUSED_TRAFFIC_FILE, FUSED_SOURCES) if fused
+    traffic = (recorded_traffic(FUSED_TRAFFIC_FILES[spl], FUSED_SOURCES) if spl > 1
                else recorded_traffic())
     out = {
         "metric": "G cell-direction updates/s",
@@ -352,7 +359,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
-            "kernel": FUSED_KERNEL if fused else STEP_KERNEL,
+            "kernel": KERNELS[spl],
             "launches": launches,
             "ms_per_launch": round(ms_launch, 5),
             "algorithmic_bytes_per_launch": alg_bytes_launch,
@@ -360,20 +367,23 @@ def main():
         "wall_s": round(wall, 4),
         "energy_after": energy,
     }
-    if fused:
-        # context: the same workload at one time step per launch
-        ms1, _, _ = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.split,
-                            fusion=False)
-        st1 = ms1 / args.steps
-        a1 = alg_bytes_launch / (st1 * 1e-3) / 1e9
-        out["single_step"] = {
-            "kernel": STEP_KERNEL,
-            "value": round(updates / (ms1 * 1e-3) / 1e9, 3),
+    # context: the same workload at fewer time steps per launch
+    out["fewer_steps_per_launch"] = {}
+    for k in range(1, spl):
+        msk, _, _ = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.split,
+                            fusion=k if k > 1 else 0)
+        stk = msk / args.steps
+        ak = alg_bytes_launch / (stk * k * 1e-3) / 1e9
+        out["fewer_steps_per_launch"][str(k)] = {
+            "kernel": KERNELS[k],
+            "value": round(updates / (msk * 1e-3) / 1e9, 3),
             "unit": "Gupdates/s",
-            "ms_per_step": round(st1, 5),
-            "achieved_GBs": round(a1, 1),
-            "frac": round(a1 / HBM_PEAK_GBS, 4),
-            "traffic": recorded_traffic(),
+            "ms_per_step": round(stk, 5),
+            "ms_per_launch": round(stk * k, 5),
+            "achieved_GBs": round(ak, 1),
+            "frac": round(ak / HBM_PEAK_GBS, 4),
+            "traffic": (recorded_traffic(FUSED_TRAFFIC_FILES[k], FUSED_SOURCES) if k > 1
+                        else recorded_traffic()),
         }
     if args.large:
         nl, ql = 4096, 256

@@ -98,10 +98,13 @@ typedef struct wlbm_params {
                              /* crosses them that is reflected specularly        */
                              /* (Eq. adiabatic-specular); 1 - p is scattered     */
                              /* diffusely (Eq. adiabatic-diffuse)                */
-  int32_t step_fusion;       /* 1: advance two steps per kernel launch where     */
-                             /* possible (periodic edges, no sources, q <= 64,   */
-                             /* outside flux windows and tapes), with results    */
-                             /* identical to single steps; 0: one step per launch */
+  int32_t step_fusion;       /* time steps per kernel launch where possible      */
+                             /* (periodic edges, no sources, q a multiple of 8   */
+                             /* up to 64 or of 16 up to 128, nx >= 6, ny >= 2,   */
+                             /* outside flux windows and tapes): 1 = default     */
+                             /* (up to three), 2 or 3 = at most that many, 0 =   */
+                             /* one step per launch.  Results are identical to   */
+                             /* single steps in every case.                      */
   int32_t reserved[3];       /* must be zero                                     */
 } wlbm_params;
 

@@ -45,7 +45,7 @@ wlbm_status fail(wlbm_status st, const char* fmt, ...) {
 
 constexpr size_t kAlign = 256;
 constexpr int kReduceBlocks = 1024;
-constexpr int kDefaultChunk = 256;
+constexpr int kDefaultChunk = 240;   // a multiple of 2 and 3 (steps per launch)
 constexpr int64_t kMaxSteps = (int64_t(1) << 31) - 1;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -118,8 +118,8 @@ wlbm_status validate(const wlbm_params* p) {
     return fail(WLBM_EINVAL, "sched_chunk must be 0 or 16..65536");
   for (int k = 0; k < 3; ++k)
     if (p->reserved[k] != 0) return fail(WLBM_EINVAL, "reserved fields must be zero");
-  if (p->step_fusion != 0 && p->step_fusion != 1)
-    return fail(WLBM_EINVAL, "step_fusion is 0 or 1");
+  if (p->step_fusion < 0 || p->step_fusion > 3)
+    return fail(WLBM_EINVAL, "step_fusion is 0 (one step per launch), 1 (default), 2 or 3");
   if (!(p->y_specularity >= 0.0 && p->y_specularity <= 1.0))
     return fail(WLBM_EINVAL, "y_specularity must lie in [0, 1]");
   if (!std::isfinite(p->t_x_lo) || !std::isfinite(p->t_x_hi) || !std::isfinite(p->t_y_lo) ||
@@ -675,15 +675,16 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
   a.y_edge = l->g.y_edge;
   a.tiles_x = tiles_x_for(l->g.nx);
   a.ntiles = a.tiles_x * tiles_y_for(l->g.ny, l->split);
-  // two steps per launch: periodic edges only, no sources, not into a tape,
-  // and a direction share per wave the fused kernel is built for
-  const bool fuse = l->p.step_fusion && !tape && l->nsrc == 0 &&
+  // several steps per launch: periodic edges only, no sources, not into a
+  // tape, and a lattice the multi-step kernels are built for
+  const bool fuse = l->p.step_fusion != 0 && !tape && l->nsrc == 0 &&
                     l->g.x_edge == kPeriodic && l->g.y_edge == kPeriodic &&
-                    step2_supported(q, l->g.nx, l->g.ny);
+                    fused_supported(q, l->g.nx, l->g.ny);
+  const int k_max = l->p.step_fusion == 1 ? 3 : l->p.step_fusion;
 
-  // the two-step kernel reads the second ghost column; other producers
-  // write the first one only, so the frame is refreshed before the first
-  // two-step launch and after any single step in between
+  // the multi-step kernels read three ghost columns; other producers write
+  // the first one only, so the frame is refreshed before the first
+  // multi-step launch and after any single step in between
   bool refresh_ghosts = true;
 
   int64_t done = 0;
@@ -733,16 +734,18 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
     for (int j = 0; j < cnt; ++j) {
       const int64_t k = done + j;
       const bool flux = k >= flux_from;
-      if (fuse && j + 1 < cnt && k + 1 < flux_from) {
-        // steps k and k+1 in one launch
+      // steps k .. k+K-1 in one launch (all in this chunk, none in a flux
+      // window)
+      const int K = int(std::min<int64_t>({int64_t(k_max), int64_t(cnt - j), flux_from - k}));
+      if (fuse && K >= 2) {
         Step2Args a2{};
         a2.e_in = l->ptr(l->c.e[l->cur]);
         a2.e_out = l->ptr(l->c.e[1 - l->cur]);
         a2.E_in = l->ptr(l->c.E[l->cur]);
         a2.E_out = l->ptr(l->c.E[1 - l->cur]);
         a2.Wf = a.Wf;
-        a2.codes1 = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j) * q);
-        a2.codes2 = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j + 1) * q);
+        for (int m = 0; m < K; ++m)
+          a2.codes[m] = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j + m) * q);
         a2.wtab = a.wtab;
         a2.W = a.W;
         a2.nx = a.nx;
@@ -750,8 +753,8 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
         a2.q = q;
         a2.pitch = a.pitch;
         a2.plane = a.plane;
-        a2.strips_x = step2_strips_x(a.nx);
-        a2.strips_y = step2_strips_y(a.ny);
+        a2.strips_x = fused_strips_x(a.nx);
+        a2.strips_y = fused_strips_y(a.ny, K);
         e = hipSuccess;
         if (refresh_ghosts) {
           e = fill_ghosts(l->ptr(l->c.e[l->cur]), a.plane, q, a.nx, a.ny, a.pitch, l->stream);
@@ -761,13 +764,13 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
             e = fill_ghosts(l->ptr(l->c.Wf), a.plane, 1, a.nx, a.ny, a.pitch, l->stream);
           refresh_ghosts = false;
         }
-        if (e == hipSuccess) e = launch_step2(a2, l->per_cell, l->stream);
+        if (e == hipSuccess) e = launch_fused(a2, K, l->per_cell, l->stream);
         if (e != hipSuccess) {
           l->broken = true;
           return fail(WLBM_EHIP, "fused step kernel launch failed: %s", hipGetErrorString(e));
         }
         l->cur = 1 - l->cur;
-        ++j;
+        j += K - 1;
         continue;
       }
       a.codes = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j) * q);

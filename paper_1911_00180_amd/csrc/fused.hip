@@ -1,24 +1,26 @@
-// Two time steps of the worm-LBM per launch (temporal blocking) for gfx950.
+// Several time steps of the worm-LBM per launch (temporal blocking) for
+// gfx950.
 //
-// One launch of k_step2 advances a periodic lattice by steps n+1 and n+2
-// (Sec. 2.3 Eq. algorithm, pull form as in k_step): each population is read
-// from HBM once and written once per two steps, instead of once per step.
+// One launch of k_stepk<..., K> advances a periodic lattice by steps n+1 ..
+// n+K, K = 2 or 3 (Sec. 2.3 Eq. algorithm, pull form as in k_step): each
+// population is read from HBM once and written once per K steps, instead of
+// once per step.
 //
-// A block owns a strip of 48 columns and kRows2 rows of the output.  Its NW
-// waves cover the same 64 columns x0-2 .. x0+61, one per lane, and take SH
-// directions each (8, or 16 above Q = 64).  Rows are pipelined: for
-// intermediate row r = y0-1 .. y0+kRows2 the waves compute step n+1 from the
-// step-n populations in HBM and keep it in registers, a ring of three rows;
-// as soon as rows r-2 .. r are there they compute step n+2 of row r-1.  The
-// one-cell shifts in x of the pull are lane shifts of a whole wave (DPP
-// wave_shr / wave_shl), so step n+1 is valid on lanes 1..62 and step n+2 on
-// lanes 2..61.  Rows wrap by index arithmetic; columns read the two-deep
-// ghost frame of periodic x edges, which must be valid on entry (the caller
-// refreshes it with k_fill_ghosts after other producers) and which the
-// kernel writes for its output.  E of each row is summed over
-// the waves in LDS in k_step's order (8-direction batch sums in batch order),
-// and every update uses k_step's arithmetic, so one k_step2 launch gives the
-// same bits as two k_step launches.
+// A block owns a strip of 48 columns and kRows(K) rows of the output.  Its NW
+// waves cover the same 64 columns x0-K .. x0+63-K, one per lane, and take SH
+// directions each (8, or 16 above Q = 64).  Rows are pipelined: at iteration
+// t the waves compute level 1 (step n+1) of row r = y0-(K-1)+t from the
+// step-n populations in HBM, then level l of row r-(l-1) for l = 2 .. K from
+// level l-1, whose rows r-l .. r-l+2 are held in registers, a ring of three
+// rows per level; level K is the output.  The one-cell shifts in x of the
+// pull are lane shifts of a whole wave (DPP wave_shr / wave_shl), so level l
+// is valid on lanes l .. 63-l.  Rows wrap by index arithmetic; columns read
+// the ghost frame of periodic x edges (kGhost columns deep), which must be
+// valid on entry (the caller refreshes it with k_fill_ghosts after other
+// producers) and which the kernel writes for its output.  E of each row of
+// each level is summed over the waves in LDS in k_step's order (8-direction
+// batch sums in batch order), and every update uses k_step's arithmetic, so
+// one launch gives the same bits as K k_step launches.
 #include "device.hpp"
 #include "kernel_common.hpp"
 
@@ -32,12 +34,15 @@ namespace {
 // (measured at 1024 x 1024, Q = 64: 60 columns 788, 56 columns 851, 48
 // columns 928, 32 columns 723 G updates/s, 4-row blocks).
 constexpr int kStrip = 48;
-// Output rows per block (kRows2 + 2 divisible by 3): taller blocks re-read
-// fewer halo rows, shorter ones give more blocks (48-column strips at
-// 1024 x 1024, Q = 64: 4 rows 928, 7 rows 952, 10 rows 966, 13 rows 947, 16
-// rows 926 G updates/s).
-constexpr int kRows2 = 10;
-static_assert((kRows2 + 2) % 3 == 0, "the row loop is unrolled by three");
+// Output rows per block (kRows + 2 (K - 1) divisible by 3): taller blocks
+// re-read fewer halo rows, shorter ones give more blocks (two steps,
+// 48-column strips at 1024 x 1024, Q = 64: 4 rows 928, 7 rows 952, 10 rows
+// 966, 13 rows 947, 16 rows 926 G updates/s).
+template <int K>
+constexpr int kRows = K == 2 ? 10 : 8;
+// Ghost columns written on each side by every multi-step launch (the most
+// any K reads), so that launches of different K can follow each other.
+constexpr int kGhost = 3;
 
 // Value held by lane l - 1 (the cell at x - 1), lane l + 1 (x + 1); lanes
 // with no such neighbour (0, resp. 63) read zero (bound control), which no
@@ -117,23 +122,23 @@ __device__ __forceinline__ const WLBM_CONST T* row_ptr(const T* p) {
   return scalar_ptr(p);
 }
 
-template <int SH>
+template <int SH, int K>
 struct Ring {
-  float X[3][SH];   // step n+1 populations of this wave's directions, rows by slot
-  float E1[3];      // step n+1 E (per-cell mode: W E) at this lane's column
-  float W1[3];      // W at this lane's column (per-cell mode)
-  float En[3];      // step n E (per-cell mode: W E), rows by slot
-  float Wn[3];      // step n W (per-cell mode)
-  float V[SH];      // step n populations pulled into the next intermediate row
+  float X[K - 1][3][SH];   // levels 1 .. K-1: populations of this wave's directions
+  float E[K - 1][3];       // E of those rows (per-cell mode: W E) at this lane's column
+  float W[K - 1][3];       // W of those rows at this lane's column (per-cell mode)
+  float En[3];             // step n E (per-cell mode: W E), rows by slot
+  float Wn[3];             // step n W (per-cell mode)
+  float V[SH];             // step n populations pulled into the next level-1 row
 };
 
-// Issue the loads of intermediate row r: the step-n populations each of this
+// Issue the loads of level-1 row r: the step-n populations each of this
 // wave's directions pulls (row r - hy, column x - hx) into g.V, and step-n E
 // (and W) of row r + 1 into ring slot SN.  Nothing waits for them here.
-template <int SH, bool WF, int SN>
-__device__ __forceinline__ void issue_row(const Step2Args& a, Ring<SH>& g, int r, int i_begin,
+template <int SH, int K, bool WF, int SN>
+__device__ __forceinline__ void issue_row(const Step2Args& a, Ring<SH, K>& g, int r, int i_begin,
                                           uint32_t lcol) {
-  const WLBM_CONST uint32_t* codes1 = row_ptr(a.codes1);
+  const WLBM_CONST uint32_t* codes1 = row_ptr(a.codes[0]);
   const WLBM_CONST uint32_t* tab = row_ptr(&kCodeSel.m[0][0]);
   const long long plane = a.plane;
   const uint32_t plane_bytes = uint32_t(plane * 4);
@@ -167,33 +172,35 @@ __device__ __forceinline__ void issue_row(const Step2Args& a, Ring<SH>& g, int r
   }
 }
 
-// Intermediate row t (r = y0 - 1 + t, ring slot S = t mod 3), then output row
-// r - 1 once t >= 2.  Slots: step-n rows r-1, r, r+1 are S, S+1, S+2 (mod 3);
-// step-(n+1) rows r-2, r-1, r are S+1, S+2, S.  The loads of row t were
-// issued by the previous call; this one issues those of row t + 1 before its
-// second step, so that they are in flight meanwhile.
-template <int NW, int SH, bool WF, int S>
-__device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float* sP, int t,
-                                         int x0, int y0, int lane, int part, uint32_t lcol,
-                                         bool out_lane) {
-  constexpr int S1 = (S + 1) % 3, S2 = (S + 2) % 3;
-  // the schedule codes and weights are re-read from the scalar cache for
-  // each row
-  const WLBM_CONST uint32_t* codes1 = row_ptr(a.codes1);
-  const WLBM_CONST uint32_t* codes2 = row_ptr(a.codes2);
-  const WLBM_CONST float* wtab = row_ptr(a.wtab);
-  const WLBM_CONST uint32_t* tab = row_ptr(&kCodeSel.m[0][0]);
-  const int ny = a.ny, pitch = a.pitch;
-  const long long plane = a.plane;
-  // opaque to the optimizer, so that the per-direction plane offsets are
-  // recomputed in every row rather than held in (spilled) scalar registers
-  uint32_t plane_bytes = uint32_t(plane * 4);
-  __asm__ volatile("" : "+s"(plane_bytes));
-  const int r = y0 - 1 + t;
-  const int i_begin = part * SH;
+// Per-row constants: schedule, weight and selection-table pointers opaque to
+// the optimizer (re-read from the scalar cache each row rather than hoisted
+// and spilled), and the plane size in bytes, likewise.
+struct RowCtx {
+  const WLBM_CONST float* wtab;
+  const WLBM_CONST uint32_t* tab;
+  uint32_t plane_bytes;
+};
+__device__ __forceinline__ RowCtx row_ctx(const Step2Args& a) {
+  RowCtx c;
+  c.wtab = row_ptr(a.wtab);
+  c.tab = row_ptr(&kCodeSel.m[0][0]);
+  c.plane_bytes = uint32_t(a.plane * 4);
+  __asm__ volatile("" : "+s"(c.plane_bytes));
+  return c;
+}
 
-  // ---- step n+1, row r ----
+// Level 1 at iteration t (row r = y0 - (K-1) + t, ring slot S = t mod 3)
+// from the step-n loads; then the loads of the next row are issued, and E of
+// row r is summed.  Step-n slots: rows r-1, r, r+1 are S, S+1, S+2 (mod 3).
+template <int NW, int SH, int K, bool WF, int S>
+__device__ __forceinline__ void level1(const Step2Args& a, Ring<SH, K>& g, float* sP, int t,
+                                       int y0, int lane, int part, uint32_t lcol) {
+  constexpr int S1 = (S + 1) % 3, S2 = (S + 2) % 3;
   constexpr int NB = NW * SH / kMaxGroupPlanes;   // batches of 8 directions
+  const RowCtx c = row_ctx(a);
+  const WLBM_CONST uint32_t* codes = row_ptr(a.codes[0]);
+  const int r = y0 - (K - 1) + t;
+  const int i_begin = part * SH;
   float* p1 = sP + (t & 1) * NB * 64;
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
@@ -201,12 +208,12 @@ __device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float*
     float bsum = 0.f;
     uint32_t words[kMaxGroupPlanes / 4];
 #pragma unroll
-    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes1[(i0 >> 2) + k];
+    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes[(i0 >> 2) + k];
 #pragma unroll
     for (int d = 0; d < kMaxGroupPlanes; ++d) {
       const int i = i0 + d;
-      const WLBM_CONST uint32_t* m = sel_of(tab, words, d);
-      const float wi = wtab[i];
+      const WLBM_CONST uint32_t* m = sel_of(c.tab, words, d);
+      const float wi = c.wtab[i];
       const float e = g.V[b0 + d];
       // source rows r - dy: dy = -1 -> slot S2, 0 -> S1, 1 -> S
       const float Es = at_minus(pick3m(g.En[S2], g.En[S1], g.En[S], m[kDyLo], m[kDyMid]),
@@ -220,88 +227,138 @@ __device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float*
                                   m[kHxPos], m[kHxNeg]);
         out = e + fmaf(wi, Es, -(Wh * e));
       }
-      g.X[S][b0 + d] = out;
+      g.X[0][S][b0 + d] = out;
       bsum += out;
     }
     p1[(i0 / kMaxGroupPlanes) * 64 + lane] = bsum;
   }
-  // W of this row for the second step, before slot S is refilled
-  if constexpr (WF) g.W1[S] = g.Wn[S1];
+  // W of this row for the next level, before slot S is refilled
+  if constexpr (WF) g.W[0][S] = g.Wn[S1];
   const float Wrow = WF ? g.Wn[S1] : 1.f;
-  // loads of the next intermediate row (its step-n row r + 2 goes to slot S)
-  if (t + 1 < kRows2 + 2) issue_row<SH, WF, S>(a, g, r + 1, i_begin, lcol);
+  // loads of the next level-1 row (its step-n row r + 2 goes to slot S)
+  if (t + 1 < kRows<K> + 2 * (K - 1)) issue_row<SH, K, WF, S>(a, g, r + 1, i_begin, lcol);
   // E of row r: the batch sums in batch order, as k_step adds them
   lds_barrier();
-  float E1 = 0.f;
+  float E = 0.f;
 #pragma unroll
-  for (int k = 0; k < NB; ++k) E1 += p1[k * 64 + lane];
-  if constexpr (WF)
-    g.E1[S] = E1 * Wrow;
-  else
-    g.E1[S] = E1;
-  if (t < 2) return;
+  for (int k = 0; k < NB; ++k) E += p1[k * 64 + lane];
+  g.E[0][S] = WF ? E * Wrow : E;
+}
 
-  // ---- step n+2, row ro = r - 1 ----
-  const int ro = r - 1;
-  const bool store = out_lane && ro < ny;
-  const int nx = a.nx;
-  const int xo = x0 - 2 + lane;
-  // byte offsets of the cell and its ghosts (used only where stored)
-  const int row_o = (ro + 1) * pitch + kXOff;
-  const uint32_t ob = uint32_t((row_o + xo) * 4);
-  // Ghost copies of this cell in the two-deep frame (nx >= 4 and ny >= 2, so
-  // a cell has at most one ghost column and one ghost row): columns 0, 1 are
-  // copied to nx, nx + 1 and columns nx - 2, nx - 1 to -2, -1; rows 0 and
-  // ny - 1 to ny and -1.  Only blocks on the lattice's edge have any, which
-  // the whole block knows.
-  const bool edge = x0 == 0 || x0 + kStrip + 1 >= nx || ro == 0 || ro == ny - 1;
-  const bool gx = store && (xo < 2 || xo >= nx - 2);
-  const bool gy = store && (ro == 0 || ro == ny - 1);
-  const int xg = xo < 2 ? xo + nx : xo - nx;
-  const int yg = ro == 0 ? ny : -1;
-  const int row_g = (yg + 1) * pitch + kXOff;
-  const uint32_t obx = uint32_t((row_o + xg) * 4);
-  const uint32_t oby = uint32_t((row_g + xo) * 4);
-  const uint32_t obxy = uint32_t((row_g + xg) * 4);
-  float* p2 = sP + (2 + (t & 1)) * NB * 64;
+// The relaxation of level L (2 .. K) at one cell from level L-1: rows
+// rho-1 .. rho+1 of level L-1 are in slots S1, S2, S (computed at iterations
+// t-2, t-1, t).
+template <int SH, int K, bool WF, int L, int S>
+__device__ __forceinline__ float relax_up(const Step2Args& a, const Ring<SH, K>& g,
+                                          const WLBM_CONST uint32_t* m, float wi, int j) {
+  constexpr int S1 = (S + 1) % 3, S2 = (S + 2) % 3;
+  constexpr int P = L - 2;   // ring index of level L-1
+  // source rows rho - dy: dy = -1 -> slot S, 0 -> S2, 1 -> S1
+  const float e = at_minus(pick3m(g.X[P][S][j], g.X[P][S2][j], g.X[P][S1][j], m[kHyLo],
+                                  m[kHyMid]),
+                           m[kHxPos], m[kHxNeg]);
+  const float Es = at_minus(pick3m(g.E[P][S], g.E[P][S2], g.E[P][S1], m[kDyLo], m[kDyMid]),
+                            m[kDxPos], m[kDxNeg]);
+  if constexpr (!WF) {
+    return fmaf(a.W, fmaf(wi, Es, -e), e);
+  } else {
+    const float Wh = at_minus(pick3m(g.W[P][S], g.W[P][S2], g.W[P][S1], m[kHyLo], m[kHyMid]),
+                              m[kHxPos], m[kHxNeg]);
+    return e + fmaf(wi, Es, -(Wh * e));
+  }
+}
+
+// An intermediate level L (2 .. K-1) at iteration t: row r - (L-1) into ring
+// slot S of level L, and its E.
+template <int NW, int SH, int K, bool WF, int L, int S>
+__device__ __forceinline__ void level_mid(const Step2Args& a, Ring<SH, K>& g, float* sP, int t,
+                                          int lane, int part) {
+  constexpr int S2 = (S + 2) % 3;
+  constexpr int NB = NW * SH / kMaxGroupPlanes;
+  const RowCtx c = row_ctx(a);
+  const WLBM_CONST uint32_t* codes = row_ptr(a.codes[L - 1]);
+  const int i_begin = part * SH;
+  float* pl = sP + (2 * (L - 1) + (t & 1)) * NB * 64;
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
     float bsum = 0.f;
     uint32_t words[kMaxGroupPlanes / 4];
 #pragma unroll
-    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes2[(i0 >> 2) + k];
+    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes[(i0 >> 2) + k];
+#pragma unroll
+    for (int d = 0; d < kMaxGroupPlanes; ++d) {
+      const float out = relax_up<SH, K, WF, L, S>(a, g, sel_of(c.tab, words, d), c.wtab[i0 + d],
+                                                  b0 + d);
+      g.X[L - 1][S][b0 + d] = out;
+      bsum += out;
+    }
+    pl[(i0 / kMaxGroupPlanes) * 64 + lane] = bsum;
+  }
+  // W of this row (level L-1 holds it in slot S2)
+  if constexpr (WF) g.W[L - 1][S] = g.W[L - 2][S2];
+  lds_barrier();
+  float E = 0.f;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) E += pl[k * 64 + lane];
+  g.E[L - 1][S] = WF ? E * g.W[L - 1][S] : E;
+}
+
+// The output level K at iteration t: row ro = r - (K-1), stored with its
+// ghost copies.
+template <int NW, int SH, int K, bool WF, int S>
+__device__ __forceinline__ void level_out(const Step2Args& a, Ring<SH, K>& g, float* sP, int t,
+                                          int x0, int y0, int lane, int part, bool out_lane) {
+  constexpr int NB = NW * SH / kMaxGroupPlanes;
+  const RowCtx c = row_ctx(a);
+  const WLBM_CONST uint32_t* codes = row_ptr(a.codes[K - 1]);
+  const int ny = a.ny, pitch = a.pitch, nx = a.nx;
+  const long long plane = a.plane;
+  const int i_begin = part * SH;
+  const int ro = y0 - (K - 1) + t - (K - 1);
+  const bool store = out_lane && ro < ny;
+  const int xo = x0 - K + lane;
+  // byte offsets of the cell and its ghosts (used only where stored)
+  const int row_o = (ro + 1) * pitch + kXOff;
+  const uint32_t ob = uint32_t((row_o + xo) * 4);
+  // Ghost copies of this cell in the frame (nx >= 2 kGhost and ny >= 2, so
+  // a cell has at most one ghost column and one ghost row): columns 0 ..
+  // kGhost-1 are copied to nx .. nx+kGhost-1 and columns nx-kGhost .. nx-1 to
+  // -kGhost .. -1; rows 0 and ny - 1 to ny and -1.  Only blocks on the
+  // lattice's edge have any, which the whole block knows.
+  const bool edge = x0 == 0 || x0 + kStrip + kGhost - 1 >= nx || ro == 0 || ro == ny - 1;
+  const bool gx = store && (xo < kGhost || xo >= nx - kGhost);
+  const bool gy = store && (ro == 0 || ro == ny - 1);
+  const int xg = xo < kGhost ? xo + nx : xo - nx;
+  const int yg = ro == 0 ? ny : -1;
+  const int row_g = (yg + 1) * pitch + kXOff;
+  const uint32_t obx = uint32_t((row_o + xg) * 4);
+  const uint32_t oby = uint32_t((row_g + xo) * 4);
+  const uint32_t obxy = uint32_t((row_g + xg) * 4);
+  float* po = sP + (2 * (K - 1) + (t & 1)) * NB * 64;
+#pragma unroll
+  for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
+    const int i0 = i_begin + b0;
+    float bsum = 0.f;
+    uint32_t words[kMaxGroupPlanes / 4];
+#pragma unroll
+    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes[(i0 >> 2) + k];
     const rsrc_t ro_rs = make_rsrc(a.e_out + (long long)i0 * plane,
                                    uint32_t(kMaxGroupPlanes * plane * 4));
     float o[kMaxGroupPlanes];
 #pragma unroll
     for (int d = 0; d < kMaxGroupPlanes; ++d) {
-      const int i = i0 + d;
-      const WLBM_CONST uint32_t* m = sel_of(tab, words, d);
-      const float wi = wtab[i];
-      // source rows ro - dy: dy = -1 -> r (slot S), 0 -> r - 1 (S2), 1 -> r - 2 (S1)
-      const float e = at_minus(
-          pick3m(g.X[S][b0 + d], g.X[S2][b0 + d], g.X[S1][b0 + d], m[kHyLo], m[kHyMid]),
-          m[kHxPos], m[kHxNeg]);
-      const float Es = at_minus(pick3m(g.E1[S], g.E1[S2], g.E1[S1], m[kDyLo], m[kDyMid]),
-                                m[kDxPos], m[kDxNeg]);
-      float out;
-      if constexpr (!WF) {
-        out = fmaf(a.W, fmaf(wi, Es, -e), e);
-      } else {
-        const float Wh = at_minus(pick3m(g.W1[S], g.W1[S2], g.W1[S1], m[kHyLo], m[kHyMid]),
-                                  m[kHxPos], m[kHxNeg]);
-        out = e + fmaf(wi, Es, -(Wh * e));
-      }
+      const float out = relax_up<SH, K, WF, K, S>(a, g, sel_of(c.tab, words, d), c.wtab[i0 + d],
+                                                  b0 + d);
       bsum += out;
       o[d] = out;
     }
-    p2[(i0 / kMaxGroupPlanes) * 64 + lane] = bsum;
+    po[(i0 / kMaxGroupPlanes) * 64 + lane] = bsum;
     // the batch's stores, under one lane mask each
     auto put = [&](uint32_t off) {
 #pragma unroll
       for (int d = 0; d < kMaxGroupPlanes; ++d)
-        buf_store_stream(o[d], ro_rs, off, uint32_t(d) * plane_bytes);
+        buf_store_stream(o[d], ro_rs, off, uint32_t(d) * c.plane_bytes);
     };
     if (store) put(ob);
     if (edge) {
@@ -312,68 +369,87 @@ __device__ __forceinline__ void row_pair(const Step2Args& a, Ring<SH>& g, float*
   }
   lds_barrier();
   if (part == 0 && store) {
-    float E2 = 0.f;
+    float E = 0.f;
 #pragma unroll
-    for (int k = 0; k < NB; ++k) E2 += p2[k * 64 + lane];
-    const rsrc_t Ers = make_rsrc(a.E_out, plane_bytes);
-    buf_store(E2, Ers, ob);
+    for (int k = 0; k < NB; ++k) E += po[k * 64 + lane];
+    const rsrc_t Ers = make_rsrc(a.E_out, c.plane_bytes);
+    buf_store(E, Ers, ob);
     if (edge) {
-      if (gx) buf_store(E2, Ers, obx);
-      if (gy) buf_store(E2, Ers, oby);
-      if (gx && gy) buf_store(E2, Ers, obxy);
+      if (gx) buf_store(E, Ers, obx);
+      if (gy) buf_store(E, Ers, oby);
+      if (gx && gy) buf_store(E, Ers, obxy);
     }
   }
 }
 
+// Iteration t (ring slot S = t mod 3): level 1, then each higher level once
+// the three rows it reads exist.
+template <int NW, int SH, int K, bool WF, int S>
+__device__ __forceinline__ void iteration(const Step2Args& a, Ring<SH, K>& g, float* sP, int t,
+                                          int x0, int y0, int lane, int part, uint32_t lcol,
+                                          bool out_lane) {
+  level1<NW, SH, K, WF, S>(a, g, sP, t, y0, lane, part, lcol);
+  if constexpr (K == 3) {
+    if (t < 2) return;
+    level_mid<NW, SH, K, WF, 2, S>(a, g, sP, t, lane, part);
+  }
+  if (t < 2 * (K - 1)) return;
+  level_out<NW, SH, K, WF, S>(a, g, sP, t, x0, y0, lane, part, out_lane);
+}
+
 // Ghost frame of a periodic lattice written by another producer (k_step
-// writes the first ghost column and row only): every ghost cell (columns -2, -1, nx, nx + 1 of rows 0 .. ny - 1, and
-// rows -1, ny of columns -2 .. nx + 1) of planes 0 .. nplanes - 1 copies the
-// cell it wraps to.
+// writes the first ghost column and row only): every ghost cell (columns
+// -kGhost .. -1 and nx .. nx+kGhost-1 of rows 0 .. ny-1, and rows -1, ny of
+// columns -kGhost .. nx+kGhost-1) of planes 0 .. nplanes-1 copies the cell it
+// wraps to.
 __global__ __launch_bounds__(kBlock) void k_fill_ghosts(float* base, long long plane, int nplanes,
                                                        int nx, int ny, int pitch) {
-  const long long nper = 4LL * ny + 2LL * (nx + 4);
+  const long long ncol = 2LL * kGhost * ny, nrow = 2LL * (nx + 2 * kGhost);
+  const long long nper = ncol + nrow;
   const long long t = (long long)blockIdx.x * kBlock + threadIdx.x;
   if (t >= nper * nplanes) return;
   const int p = int(t / nper);
   const long long g = t - (long long)p * nper;
   int gx, gy;
-  if (g < 4LL * ny) {
+  if (g < ncol) {
     const int k = int(g / ny);
     gy = int(g - (long long)k * ny);
-    gx = k < 2 ? k - 2 : nx + k - 2;
+    gx = k < kGhost ? k - kGhost : nx + k - kGhost;
   } else {
-    const long long h = g - 4LL * ny;
-    const int k = int(h / (nx + 4));
-    gx = int(h - (long long)k * (nx + 4)) - 2;
+    const long long h = g - ncol;
+    const int k = int(h / (nx + 2 * kGhost));
+    gx = int(h - (long long)k * (nx + 2 * kGhost)) - kGhost;
     gy = k == 0 ? -1 : ny;
   }
   float* pl = base + (long long)p * plane;
   pl[cell(gx, gy, pitch)] = pl[cell(wrap_index(gx, nx), wrap_index(gy, ny), pitch)];
 }
 
-template <int NW, int SH, bool WF>
-__global__ __launch_bounds__(64 * NW) void k_step2(const Step2Args a) {
-  // E batch sums: [intermediate | output][row parity][batch of 8 directions][lane]
-  __shared__ float sP[4 * (NW * SH / kMaxGroupPlanes) * 64];
+template <int NW, int SH, bool WF, int K>
+__global__ __launch_bounds__(64 * NW) void k_stepk(const Step2Args a) {
+  // E batch sums: [level 1 .. K][row parity][batch of 8 directions][lane]
+  __shared__ float sP[2 * K * (NW * SH / kMaxGroupPlanes) * 64];
   const int lane = threadIdx.x & 63;
   const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (b % a.strips_x) * kStrip;
-  const int y0 = (b / a.strips_x) * kRows2;
-  // this lane's column; lanes past nx + 1 read column nx + 1 (their values are
-  // never used), so that every read stays inside the row and its padding
-  const int x = x0 - 2 + lane;
-  const int xl = x < a.nx + 1 ? x : a.nx + 1;
+  const int y0 = (b / a.strips_x) * kRows<K>;
+  // this lane's column; lanes past the ghost frame read its last column
+  // (their values are never used), so that every read stays inside the row
+  // and its padding
+  const int x = x0 - K + lane;
+  const int xl = x < a.nx + kGhost - 1 ? x : a.nx + kGhost - 1;
   const uint32_t lcol = uint32_t((kXOff + xl) * 4);
-  const bool out_lane = lane >= 2 && lane < 2 + kStrip && x < a.nx;
+  const bool out_lane = lane >= K && lane < K + kStrip && x < a.nx;
 
-  Ring<SH> g;
-  // step-n rows y0 - 2 and y0 - 1 into slots 0 and 1; the loads of the first
-  // intermediate row (r = y0 - 1) bring row y0 into slot 2
+  Ring<SH, K> g;
+  // step-n E of rows r0 - 1 and r0 (r0 = y0 - (K-1), the first level-1 row)
+  // into slots 0 and 1; the loads of row r0 bring row r0 + 1 into slot 2
   const uint32_t plane_bytes = uint32_t(a.plane * 4);
+  const int r0 = y0 - (K - 1);
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
-    const uint32_t rb = uint32_t((wrap_index(y0 - 2 + k, a.ny) + 1) * a.pitch * 4);
+    const uint32_t rb = uint32_t((wrap_index(r0 - 1 + k, a.ny) + 1) * a.pitch * 4);
     const float Ev = buf_load(make_rsrc(a.E_in, plane_bytes), lcol, rb);
     if constexpr (WF) {
       const float Wv = buf_load(make_rsrc(a.Wf, plane_bytes), lcol, rb);
@@ -383,21 +459,32 @@ __global__ __launch_bounds__(64 * NW) void k_step2(const Step2Args a) {
       g.En[k] = Ev;
     }
   }
-  issue_row<SH, WF, 2>(a, g, y0 - 1, part * SH, lcol);
-  for (int t = 0; t < kRows2 + 2; t += 3) {
-    row_pair<NW, SH, WF, 0>(a, g, sP, t, x0, y0, lane, part, lcol, out_lane);
-    row_pair<NW, SH, WF, 1>(a, g, sP, t + 1, x0, y0, lane, part, lcol, out_lane);
-    row_pair<NW, SH, WF, 2>(a, g, sP, t + 2, x0, y0, lane, part, lcol, out_lane);
+  issue_row<SH, K, WF, 2>(a, g, r0, part * SH, lcol);
+  constexpr int T = kRows<K> + 2 * (K - 1);
+  static_assert(T % 3 == 0, "the row loop is unrolled by three");
+  for (int t = 0; t < T; t += 3) {
+    iteration<NW, SH, K, WF, 0>(a, g, sP, t, x0, y0, lane, part, lcol, out_lane);
+    iteration<NW, SH, K, WF, 1>(a, g, sP, t + 1, x0, y0, lane, part, lcol, out_lane);
+    iteration<NW, SH, K, WF, 2>(a, g, sP, t + 2, x0, y0, lane, part, lcol, out_lane);
   }
 }
 
 template <int NW, int SH>
-hipError_t launch2(const Step2Args& a, bool wf, hipStream_t s) {
+hipError_t launchk(const Step2Args& a, int k, bool wf, hipStream_t s) {
   const dim3 grid(a.strips_x * a.strips_y), block(64 * NW);
-  if (wf)
-    hipLaunchKernelGGL((k_step2<NW, SH, true>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((k_step2<NW, SH, false>), grid, block, 0, s, a);
+  if (k == 2) {
+    if (wf)
+      hipLaunchKernelGGL((k_stepk<NW, SH, true, 2>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_stepk<NW, SH, false, 2>), grid, block, 0, s, a);
+  } else if (k == 3) {
+    if (wf)
+      hipLaunchKernelGGL((k_stepk<NW, SH, true, 3>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_stepk<NW, SH, false, 3>), grid, block, 0, s, a);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -405,39 +492,42 @@ hipError_t launch2(const Step2Args& a, bool wf, hipStream_t s) {
 
 hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny, int pitch,
                        hipStream_t s) {
-  const long long n = (4LL * ny + 2LL * (nx + 4)) * nplanes;
+  const long long n = (2LL * kGhost * ny + 2LL * (nx + 2 * kGhost)) * nplanes;
   hipLaunchKernelGGL(k_fill_ghosts, dim3(unsigned((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
                      base, plane, nplanes, nx, ny, pitch);
   return hipGetLastError();
 }
 
-int step2_strips_x(int nx) { return (nx + kStrip - 1) / kStrip; }
-int step2_strips_y(int ny) { return (ny + kRows2 - 1) / kRows2; }
+int fused_strips_x(int nx) { return (nx + kStrip - 1) / kStrip; }
+int fused_strips_y(int ny, int k) {
+  const int rows = k == 3 ? kRows<3> : kRows<2>;
+  return (ny + rows - 1) / rows;
+}
 // Waves per block: one per 8 directions up to q = 64, one per 16 up to 128.
-bool step2_supported(int q, int nx, int ny) {
-  return nx >= 4 && ny >= 2 && q % kMaxGroupPlanes == 0 &&
+bool fused_supported(int q, int nx, int ny) {
+  return nx >= 2 * kGhost && ny >= 2 && q % kMaxGroupPlanes == 0 &&
          (q <= 64 || (q <= 128 && q % 16 == 0));
 }
 
-hipError_t launch_step2(const Step2Args& a, bool per_cell, hipStream_t s) {
+hipError_t launch_fused(const Step2Args& a, int k, bool per_cell, hipStream_t s) {
   if (a.q <= 64) {
     switch (a.q / 8) {
-      case 1: return launch2<1, 8>(a, per_cell, s);
-      case 2: return launch2<2, 8>(a, per_cell, s);
-      case 3: return launch2<3, 8>(a, per_cell, s);
-      case 4: return launch2<4, 8>(a, per_cell, s);
-      case 5: return launch2<5, 8>(a, per_cell, s);
-      case 6: return launch2<6, 8>(a, per_cell, s);
-      case 7: return launch2<7, 8>(a, per_cell, s);
-      case 8: return launch2<8, 8>(a, per_cell, s);
+      case 1: return launchk<1, 8>(a, k, per_cell, s);
+      case 2: return launchk<2, 8>(a, k, per_cell, s);
+      case 3: return launchk<3, 8>(a, k, per_cell, s);
+      case 4: return launchk<4, 8>(a, k, per_cell, s);
+      case 5: return launchk<5, 8>(a, k, per_cell, s);
+      case 6: return launchk<6, 8>(a, k, per_cell, s);
+      case 7: return launchk<7, 8>(a, k, per_cell, s);
+      case 8: return launchk<8, 8>(a, k, per_cell, s);
       default: return hipErrorInvalidValue;
     }
   }
   switch (a.q / 16) {
-    case 5: return launch2<5, 16>(a, per_cell, s);
-    case 6: return launch2<6, 16>(a, per_cell, s);
-    case 7: return launch2<7, 16>(a, per_cell, s);
-    case 8: return launch2<8, 16>(a, per_cell, s);
+    case 5: return launchk<5, 16>(a, k, per_cell, s);
+    case 6: return launchk<6, 16>(a, k, per_cell, s);
+    case 7: return launchk<7, 16>(a, k, per_cell, s);
+    case 8: return launchk<8, 16>(a, k, per_cell, s);
     default: return hipErrorInvalidValue;
   }
 }

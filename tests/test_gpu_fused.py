@@ -25,11 +25,29 @@ def _need_gpu():
     wormlbm.lib()
 
 
-def _pair(nx, ny, q, **kw):
+def _pair(nx, ny, q, fusion=1, **kw):
     from paper_1911_00180_amd.lattice import Lattice
-    a = Lattice(nx, ny, q, step_fusion=True, **kw)
-    b = Lattice(nx, ny, q, step_fusion=False, **kw)
+    a = Lattice(nx, ny, q, step_fusion=fusion, **kw)
+    b = Lattice(nx, ny, q, step_fusion=0, **kw)
     return a, b
+
+
+@pytest.mark.parametrize("fusion", [2, 3])
+@pytest.mark.parametrize("nx,ny,q,mfp", [(150, 41, 64, 9.0), (97, 23, 32, 4.0), (7, 8, 8, 1e9)])
+def test_two_and_three_steps_per_launch(fusion, nx, ny, q, mfp):
+    """At most two, resp. three, steps per launch against single steps, for
+    counts that leave every remainder (and odd chunk ends)."""
+    a, b = _pair(nx, ny, q, fusion=fusion, mfp=mfp, sched_chunk=17)
+    e0 = torch.from_numpy(inputs.random_populations(8, q, ny, nx))
+    for lat in (a, b):
+        lat.set_populations(e0)
+    for n in (3, 4, 5, 1, 2, 40):
+        a.step(n)
+        b.step(n)
+        assert torch.equal(a.populations(), b.populations()), n
+        assert torch.equal(a.temperature(), b.temperature()), n
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("nx,ny,q,split,mfp,kind", [
@@ -39,9 +57,9 @@ def _pair(nx, ny, q, **kw):
     (20, 10, 32, 1, 9.0, "ring"),
     (5, 3, 8, 1, 2.0, "uniform"),
     (200, 17, 24, 1, 1e9, "ring"),
-    (4, 2, 16, 2, 3.0, "uniform"),     # smallest lattice the fused kernel takes
-    (61, 5, 64, 0, 8.0, "uniform"),    # last strip holds one column
-    (3, 9, 8, 1, 2.0, "uniform"),      # too narrow: single steps
+    (6, 2, 16, 2, 3.0, "uniform"),     # smallest lattice the multi-step kernels take
+    (49, 5, 64, 0, 8.0, "uniform"),    # last strip holds one column
+    (5, 9, 8, 1, 2.0, "uniform"),      # too narrow: single steps
     (128, 6, 128, 0, 20.0, "uniform"),
 ])
 def test_fused_equals_single_steps(nx, ny, q, split, mfp, kind):
