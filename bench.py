@@ -98,6 +98,8 @@ def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1):
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
     energy, _, _ = lat.totals()
+    # block height the library chose for the multi-step kernel, if any
+    run_gpu.block_rows = lat.block_rows(fusion) if fusion in (2, 3) else None
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -265,7 +267,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3840)
-    ap.add_argument("--warmup", type=int, default=120)
+    ap.add_argument("--warmup", type=int, default=540)
     ap.add_argument("--kn", type=float, default=0.1, help="Knudsen number vs L = 1024")
     ap.add_argument("--split", type=int, default=0,
                     help="waves sharing one cell's directions (0 = library default)")
@@ -360,6 +362,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
             "kernel": KERNELS[spl],
+            "block_rows": run_gpu.block_rows,
             "launches": launches,
             "ms_per_launch": round(ms_launch, 5),
             "algorithmic_bytes_per_launch": alg_bytes_launch,
@@ -376,6 +379,7 @@ def main():
         ak = alg_bytes_launch / (stk * k * 1e-3) / 1e9
         out["fewer_steps_per_launch"][str(k)] = {
             "kernel": KERNELS[k],
+            "block_rows": run_gpu.block_rows,
             "value": round(updates / (msk * 1e-3) / 1e9, 3),
             "unit": "Gupdates/s",
             "ms_per_step": round(stk, 5),

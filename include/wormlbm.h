@@ -332,9 +332,9 @@ int64_t wlbm_adjoint_step_index(const wlbm_lattice* lat);
 
 /* ---- Launch configuration and autotuning ---------------------------------
  * The step kernel splits the q directions of each cell over 1, 2 or 4
- * waves.  Results of different splits agree to rounding (the per-cell sum E
- * is added in a split-dependent order); a run with a fixed split is
- * bit-reproducible. */
+ * waves.  The per-cell sum E is added in the same order for every split
+ * (sums of 8-direction batches, in batch order), so all splits, the batched
+ * step and the multi-step kernels give identical bits. */
 
 /* Set the split (0: library default for q; else 1, 2 or 4 with q a multiple
  * of 8 * split).  Takes effect from the next step. */
@@ -342,6 +342,14 @@ wlbm_status wlbm_set_dir_split(wlbm_lattice* lat, int32_t split);
 
 /* Current split, or -1 for NULL. */
 int32_t wlbm_get_dir_split(const wlbm_lattice* lat);
+
+/* Output rows per block of the kernel that advances k = 2 or 3 steps per
+ * launch, for the lattice's current weight mode (uniform or per-cell field).
+ * The library picks this height by timing its first multi-step launches of
+ * the lattice with each candidate height (two passes of 6 launches per
+ * candidate; results do not depend on the height); 0 while it is still doing
+ * so or before the first such launch, -1 for NULL or k outside 2 .. 3. */
+int32_t wlbm_get_block_rows(const wlbm_lattice* lat, int32_t k);
 
 /* Time `steps` steps (1 .. 10000, after 2 warm-up steps) with each valid
  * split on the current state and keep the fastest.  The state and step count

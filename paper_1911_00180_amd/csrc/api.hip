@@ -175,6 +175,24 @@ size_t state_bytes_of(const wlbm_params& p) {
 
 }  // namespace
 
+// Block height (output rows per block) of a multi-step kernel, chosen by
+// timing real launches: in each of kPasses passes over the candidates, a
+// candidate height runs kSample back-to-back launches, timed from the end of
+// the first to the end of the last (so that the warm-up of the first and the
+// overlap of consecutive launches are as in a long run); the candidate with
+// the best time over the passes is kept.  The populations do not depend on
+// the height, so nothing is repeated or undone.
+struct RowTuner {
+  static constexpr int kMaxCand = 24;
+  static constexpr int kSample = 6;
+  static constexpr int kPasses = 2;
+  int cand[kMaxCand] = {};
+  float ms[kMaxCand] = {};
+  int ncand = 0;
+  int next = 0;     // launches run while tuning
+  int chosen = 0;   // 0 while tuning
+};
+
 struct wlbm_lattice {
   wlbm_params p{};
   DirSet dirs;
@@ -188,6 +206,10 @@ struct wlbm_lattice {
   bool per_cell = false;    // per-cell weight field active
   int split = 1;            // waves sharing the directions of one cell
   int chunk = kDefaultChunk;
+  // Rows per block of the multi-step kernels, per [per_cell][k]: chosen by
+  // timing the first launches (the results do not depend on it).
+  RowTuner tuner[2][4];
+  hipEvent_t tev[2] = {nullptr, nullptr};   // timing events of those launches
   uint8_t* pinned[2] = {nullptr, nullptr};
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_pending[2] = {false, false};
@@ -444,6 +466,7 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
     for (int k = 0; k < 2; ++k) {
       if (l->pinned[k]) (void)hipHostFree(l->pinned[k]);
       if (l->ev[k]) (void)hipEventDestroy(l->ev[k]);
+      if (l->tev[k]) (void)hipEventDestroy(l->tev[k]);
     }
     delete l;
     return s;
@@ -456,6 +479,7 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
       return cleanup(s);
     }
     e = hipEventCreateWithFlags(&l->ev[k], hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreate(&l->tev[k]);
     if (e != hipSuccess) {
       wlbm_status s = fail(WLBM_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
       return cleanup(s);
@@ -753,9 +777,16 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
         a2.q = q;
         a2.pitch = a.pitch;
         a2.plane = a.plane;
-        a2.strips_x = fused_strips_x(a.nx);
-        a2.strips_y = fused_strips_y(a.ny, K);
         e = hipSuccess;
+        RowTuner& tu = l->tuner[l->per_cell ? 1 : 0][K];
+        if (tu.ncand == 0) tu.ncand = fused_row_candidates(a.ny, K, tu.cand, RowTuner::kMaxCand);
+        const bool timing = tu.chosen == 0;
+        const int ci = (tu.next / RowTuner::kSample) % tu.ncand;
+        const int phase = tu.next % RowTuner::kSample;
+        const bool first_pass = tu.next < RowTuner::kSample * tu.ncand;
+        a2.rows = timing ? tu.cand[ci] : tu.chosen;
+        a2.strips_x = fused_strips_x(a.nx);
+        a2.strips_y = (a.ny + a2.rows - 1) / a2.rows;
         if (refresh_ghosts) {
           e = fill_ghosts(l->ptr(l->c.e[l->cur]), a.plane, q, a.nx, a.ny, a.pitch, l->stream);
           if (e == hipSuccess)
@@ -765,6 +796,23 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
           refresh_ghosts = false;
         }
         if (e == hipSuccess) e = launch_fused(a2, K, l->per_cell, l->stream);
+        if (e == hipSuccess && timing) {
+          if (phase == 0) {
+            e = hipEventRecord(l->tev[0], l->stream);
+          } else if (phase == RowTuner::kSample - 1) {
+            float ms = 0.f;
+            e = hipEventRecord(l->tev[1], l->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(l->tev[1]);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, l->tev[0], l->tev[1]);
+            if (first_pass || ms < tu.ms[ci]) tu.ms[ci] = ms;
+          }
+          if (e == hipSuccess && ++tu.next == RowTuner::kPasses * RowTuner::kSample * tu.ncand) {
+            int b = 0;
+            for (int c = 1; c < tu.ncand; ++c)
+              if (tu.ms[c] < tu.ms[b]) b = c;
+            tu.chosen = tu.cand[b];
+          }
+        }
         if (e != hipSuccess) {
           l->broken = true;
           return fail(WLBM_EHIP, "fused step kernel launch failed: %s", hipGetErrorString(e));
@@ -1191,6 +1239,11 @@ wlbm_status wlbm_set_dir_split(wlbm_lattice* l, int32_t split) {
 
 int32_t wlbm_get_dir_split(const wlbm_lattice* l) { return l ? l->split : -1; }
 
+int32_t wlbm_get_block_rows(const wlbm_lattice* l, int32_t k) {
+  if (!l || k < 2 || k > 3) return -1;
+  return l->tuner[l->per_cell ? 1 : 0][k].chosen;
+}
+
 wlbm_status wlbm_batch_bytes(wlbm_lattice* const* lats, int32_t n, size_t* bytes) {
   wlbm_status st = check_members(lats, n);
   if (st) return st;
@@ -1496,6 +1549,7 @@ wlbm_status wlbm_destroy(wlbm_lattice* l) {
   for (int k = 0; k < 2; ++k) {
     if (l->pinned[k]) (void)hipHostFree(l->pinned[k]);
     if (l->ev[k]) (void)hipEventDestroy(l->ev[k]);
+    if (l->tev[k]) (void)hipEventDestroy(l->tev[k]);
   }
   delete l;
   if (e != hipSuccess) return fail(WLBM_EHIP, "stream sync at destroy: %s", hipGetErrorString(e));

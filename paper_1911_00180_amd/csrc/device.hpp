@@ -101,6 +101,7 @@ struct Step2Args {
   int nx, ny, q, pitch;
   long long plane;
   int strips_x, strips_y;
+  int rows;   // output rows per block: rows + 2 (k - 1) a multiple of 3
 };
 hipError_t launch_fused(const Step2Args& a, int k, bool per_cell, hipStream_t s);
 // Ghost frame (three ghost columns each side, ghost rows) of nplanes periodic
@@ -108,7 +109,9 @@ hipError_t launch_fused(const Step2Args& a, int k, bool per_cell, hipStream_t s)
 hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny, int pitch,
                        hipStream_t s);
 int fused_strips_x(int nx);
-int fused_strips_y(int ny, int k);
+// Candidate output rows per block for k steps per launch (at most max_cand,
+// written to cand); returns their number.
+int fused_row_candidates(int ny, int k, int* cand, int max_cand);
 // Whether the multi-step kernels take this lattice: q a multiple of 8 up to
 // 64 or of 16 up to 128, nx >= 6, ny >= 2.
 bool fused_supported(int q, int nx, int ny);

@@ -6,7 +6,7 @@
 // population is read from HBM once and written once per K steps, instead of
 // once per step.
 //
-// A block owns a strip of 48 columns and kRows(K) rows of the output.  Its NW
+// A block owns a strip of 48 columns and a.rows rows of the output.  Its NW
 // waves cover the same 64 columns x0-K .. x0+63-K, one per lane, and take SH
 // directions each (8, or 16 above Q = 64).  Rows are pipelined: at iteration
 // t the waves compute level 1 (step n+1) of row r = y0-(K-1)+t from the
@@ -34,12 +34,6 @@ namespace {
 // (measured at 1024 x 1024, Q = 64: 60 columns 788, 56 columns 851, 48
 // columns 928, 32 columns 723 G updates/s, 4-row blocks).
 constexpr int kStrip = 48;
-// Output rows per block (kRows + 2 (K - 1) divisible by 3): taller blocks
-// re-read fewer halo rows, shorter ones give more blocks (two steps,
-// 48-column strips at 1024 x 1024, Q = 64: 4 rows 928, 7 rows 952, 10 rows
-// 966, 13 rows 947, 16 rows 926 G updates/s).
-template <int K>
-constexpr int kRows = K == 2 ? 10 : 8;
 // Ghost columns written on each side by every multi-step launch (the most
 // any K reads), so that launches of different K can follow each other.
 constexpr int kGhost = 3;
@@ -236,7 +230,7 @@ __device__ __forceinline__ void level1(const Step2Args& a, Ring<SH, K>& g, float
   if constexpr (WF) g.W[0][S] = g.Wn[S1];
   const float Wrow = WF ? g.Wn[S1] : 1.f;
   // loads of the next level-1 row (its step-n row r + 2 goes to slot S)
-  if (t + 1 < kRows<K> + 2 * (K - 1)) issue_row<SH, K, WF, S>(a, g, r + 1, i_begin, lcol);
+  if (t + 1 < a.rows + 2 * (K - 1)) issue_row<SH, K, WF, S>(a, g, r + 1, i_begin, lcol);
   // E of row r: the batch sums in batch order, as k_step adds them
   lds_barrier();
   float E = 0.f;
@@ -433,7 +427,7 @@ __global__ __launch_bounds__(64 * NW) void k_stepk(const Step2Args a) {
   const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (b % a.strips_x) * kStrip;
-  const int y0 = (b / a.strips_x) * kRows<K>;
+  const int y0 = (b / a.strips_x) * a.rows;
   // this lane's column; lanes past the ghost frame read its last column
   // (their values are never used), so that every read stays inside the row
   // and its padding
@@ -460,8 +454,8 @@ __global__ __launch_bounds__(64 * NW) void k_stepk(const Step2Args a) {
     }
   }
   issue_row<SH, K, WF, 2>(a, g, r0, part * SH, lcol);
-  constexpr int T = kRows<K> + 2 * (K - 1);
-  static_assert(T % 3 == 0, "the row loop is unrolled by three");
+  // a.rows + 2 (K - 1) is a multiple of 3 (the loop is unrolled by three)
+  const int T = a.rows + 2 * (K - 1);
   for (int t = 0; t < T; t += 3) {
     iteration<NW, SH, K, WF, 0>(a, g, sP, t, x0, y0, lane, part, lcol, out_lane);
     iteration<NW, SH, K, WF, 1>(a, g, sP, t + 1, x0, y0, lane, part, lcol, out_lane);
@@ -499,10 +493,22 @@ hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny
 }
 
 int fused_strips_x(int nx) { return (nx + kStrip - 1) / kStrip; }
-int fused_strips_y(int ny, int k) {
-  const int rows = k == 3 ? kRows<3> : kRows<2>;
-  return (ny + rows - 1) / rows;
+
+// Candidate block heights for k steps per launch: R + 2 (k - 1) a multiple
+// of 3, R up to 47, and no taller than needed to cover ny in one block row.
+// Taller blocks re-read fewer halo rows but give fewer blocks, and how the
+// last round of resident blocks fills the GPU depends on the lattice, so the
+// caller times them (at 1024 x 1024, Q = 64, three steps per launch: R = 23
+// 1159, 29 963, 35 1058, 47 1064 G updates/s).
+int fused_row_candidates(int ny, int k, int* cand, int max_cand) {
+  int n = 0;
+  for (int r = (k == 3 ? 5 : 4); r <= 47 && n < max_cand; r += 3) {
+    cand[n++] = r;
+    if (r >= ny) break;
+  }
+  return n;
 }
+
 // Waves per block: one per 8 directions up to q = 64, one per 16 up to 128.
 bool fused_supported(int q, int nx, int ny) {
   return nx >= 2 * kGhost && ny >= 2 && q % kMaxGroupPlanes == 0 &&

@@ -157,6 +157,11 @@ class Lattice:
     def dir_split(self) -> int:
         return W.wlbm_get_dir_split(self.handle)
 
+    def block_rows(self, k: int) -> int:
+        """Output rows per block the library chose for k = 2 or 3 steps per
+        launch (0 while still timing candidates)."""
+        return W.wlbm_get_block_rows(self.handle, k)
+
     def set_dir_split(self, split: int) -> None:
         W.wlbm_set_dir_split(self.handle, split)
 

@@ -44,7 +44,7 @@ EXPORTS = (
     "wlbm_set_dir_split", "wlbm_get_dir_split", "wlbm_autotune", "wlbm_batch_bytes",
     "wlbm_batch_create", "wlbm_batch_step", "wlbm_batch_destroy", "wlbm_read_flux_mean",
     "wlbm_set_sources", "wlbm_flux_distribution", "wlbm_set_speeds",
-    "wlbm_accumulate_temperature",
+    "wlbm_accumulate_temperature", "wlbm_get_block_rows",
 )
 
 
@@ -120,6 +120,7 @@ def lib() -> ctypes.CDLL:
         "wlbm_adjoint_step_index": (c_int64, [c_void_p]),
         "wlbm_set_dir_split": (c_int, [c_void_p, c_int32]),
         "wlbm_get_dir_split": (c_int32, [c_void_p]),
+        "wlbm_get_block_rows": (c_int32, [c_void_p, c_int32]),
         "wlbm_autotune": (c_int, [c_void_p, c_void_p, c_size_t, c_int32, POINTER(ctypes.c_float),
                                   POINTER(c_int32)]),
         "wlbm_batch_bytes": (c_int, [POINTER(c_void_p), c_int32, POINTER(c_size_t)]),
@@ -340,6 +341,10 @@ def wlbm_set_dir_split(h: int, split: int) -> None:
 
 def wlbm_get_dir_split(h: int) -> int:
     return lib().wlbm_get_dir_split(c_void_p(h))
+
+
+def wlbm_get_block_rows(h: int, k: int) -> int:
+    return lib().wlbm_get_block_rows(c_void_p(h), k)
 
 
 def wlbm_autotune(h: int, d_state, nbytes: int, steps: int):

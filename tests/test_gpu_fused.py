@@ -116,3 +116,26 @@ def test_fused_then_adjoint_tape_and_restart():
     assert torch.equal(a.populations(), b.populations())
     a.close()
     b.close()
+
+
+def test_block_height_tuning_settles_and_keeps_bits():
+    """The library times each candidate block height on its first launches
+    and then keeps the fastest; the populations match single steps through
+    the tuning and after it."""
+    nx, ny, q = 200, 130, 32
+    a, b = _pair(nx, ny, q, fusion=3, mfp=12.0)
+    assert a.block_rows(3) == 0 and a.block_rows(5) == -1
+    e0 = torch.from_numpy(inputs.random_populations(4, q, ny, nx))
+    for lat in (a, b):
+        lat.set_populations(e0)
+    a.step(1200)
+    b.step(1200)
+    assert torch.equal(a.populations(), b.populations())
+    rows = a.block_rows(3)
+    assert rows in range(5, 48, 3) and rows <= ny + 2
+    a.step(30)
+    b.step(30)
+    assert torch.equal(a.populations(), b.populations())
+    assert a.block_rows(3) == rows
+    a.close()
+    b.close()
