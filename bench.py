@@ -30,12 +30,12 @@ FUSED_SOURCES = ("fused.hip", "kernel_common.hpp", "device.hpp")
 ADJOINT_SOURCES = ("adjoint.hip", "kernel_common.hpp", "device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_1024x1024_q64_traffic.md")
 FUSED_TRAFFIC_FILES = {k: os.path.join(ROOT, "profiles", f"k_stepk{k}_1024x1024_q64_traffic.md")
-                       for k in (2, 3)}
+                       for k in (2, 3, 4)}
 ADJOINT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_adjoint_1024x1024_q64.md")
 # the kernels that run the default workload (1024 x 1024 periodic, Q = 64),
 # by time steps per launch
 KERNELS = {1: "k_step<4, false, false>", 2: "k_stepk<8, 8, false, 2>",
-           3: "k_stepk<8, 8, false, 3>"}
+           3: "k_stepk<8, 8, false, 3>", 4: "k_stepk<8, 8, false, 4>"}
 
 
 def bytes_per_update(q: int, per_cell_w: bool = False) -> float:
@@ -99,7 +99,7 @@ def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1):
     ms = ev0.elapsed_time(ev1)
     energy, _, _ = lat.totals()
     # block height the library chose for the multi-step kernel, if any
-    run_gpu.block_rows = lat.block_rows(fusion) if fusion in (2, 3) else None
+    run_gpu.block_rows = lat.block_rows(fusion) if fusion in (2, 3, 4) else None
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -267,7 +267,7 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3840)
-    ap.add_argument("--warmup", type=int, default=540)
+    ap.add_argument("--warmup", type=int, default=960)
     ap.add_argument("--kn", type=float, default=0.1, help="Knudsen number vs L = 1024")
     ap.add_argument("--split", type=int, default=0,
                     help="waves sharing one cell's directions (0 = library default)")
@@ -277,7 +277,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurements")
     ap.add_argument("--no-films", action="store_true", help="skip the batched film sweep")
-    ap.add_argument("--steps-per-launch", type=int, default=3, choices=(1, 2, 3),
+    ap.add_argument("--steps-per-launch", type=int, default=4, choices=(1, 2, 3, 4),
                     help="time steps per kernel launch on the default lattice")
     ap.add_argument("--single-step", action="store_true",
                     help="same as --steps-per-launch 1")

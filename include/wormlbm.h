@@ -100,9 +100,9 @@ typedef struct wlbm_params {
                              /* diffusely (Eq. adiabatic-diffuse)                */
   int32_t step_fusion;       /* time steps per kernel launch where possible      */
                              /* (periodic edges, no sources, q a multiple of 8   */
-                             /* up to 64 or of 16 up to 128, nx >= 6, ny >= 2,   */
+                             /* up to 64 or of 16 up to 128, nx >= 8, ny >= 2,   */
                              /* outside flux windows and tapes): 1 = default     */
-                             /* (up to three), 2 or 3 = at most that many, 0 =   */
+                             /* (up to four), 2 .. 4 = at most that many, 0 =    */
                              /* one step per launch.  Results are identical to   */
                              /* single steps in every case.                      */
   int32_t reserved[3];       /* must be zero                                     */
@@ -343,12 +343,12 @@ wlbm_status wlbm_set_dir_split(wlbm_lattice* lat, int32_t split);
 /* Current split, or -1 for NULL. */
 int32_t wlbm_get_dir_split(const wlbm_lattice* lat);
 
-/* Output rows per block of the kernel that advances k = 2 or 3 steps per
+/* Output rows per block of the kernel that advances k = 2, 3 or 4 steps per
  * launch, for the lattice's current weight mode (uniform or per-cell field).
  * The library picks this height by timing its first multi-step launches of
  * the lattice with each candidate height (two passes of 6 launches per
  * candidate; results do not depend on the height); 0 while it is still doing
- * so or before the first such launch, -1 for NULL or k outside 2 .. 3. */
+ * so or before the first such launch, -1 for NULL or k outside 2 .. 4. */
 int32_t wlbm_get_block_rows(const wlbm_lattice* lat, int32_t k);
 
 /* Time `steps` steps (1 .. 10000, after 2 warm-up steps) with each valid

@@ -45,7 +45,7 @@ wlbm_status fail(wlbm_status st, const char* fmt, ...) {
 
 constexpr size_t kAlign = 256;
 constexpr int kReduceBlocks = 1024;
-constexpr int kDefaultChunk = 240;   // a multiple of 2 and 3 (steps per launch)
+constexpr int kDefaultChunk = 240;   // a multiple of 2, 3 and 4 (steps per launch)
 constexpr int64_t kMaxSteps = (int64_t(1) << 31) - 1;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
@@ -118,8 +118,8 @@ wlbm_status validate(const wlbm_params* p) {
     return fail(WLBM_EINVAL, "sched_chunk must be 0 or 16..65536");
   for (int k = 0; k < 3; ++k)
     if (p->reserved[k] != 0) return fail(WLBM_EINVAL, "reserved fields must be zero");
-  if (p->step_fusion < 0 || p->step_fusion > 3)
-    return fail(WLBM_EINVAL, "step_fusion is 0 (one step per launch), 1 (default), 2 or 3");
+  if (p->step_fusion < 0 || p->step_fusion > 4)
+    return fail(WLBM_EINVAL, "step_fusion is 0 (one step per launch), 1 (default), 2, 3 or 4");
   if (!(p->y_specularity >= 0.0 && p->y_specularity <= 1.0))
     return fail(WLBM_EINVAL, "y_specularity must lie in [0, 1]");
   if (!std::isfinite(p->t_x_lo) || !std::isfinite(p->t_x_hi) || !std::isfinite(p->t_y_lo) ||
@@ -208,7 +208,7 @@ struct wlbm_lattice {
   int chunk = kDefaultChunk;
   // Rows per block of the multi-step kernels, per [per_cell][k]: chosen by
   // timing the first launches (the results do not depend on it).
-  RowTuner tuner[2][4];
+  RowTuner tuner[2][5];
   hipEvent_t tev[2] = {nullptr, nullptr};   // timing events of those launches
   uint8_t* pinned[2] = {nullptr, nullptr};
   hipEvent_t ev[2] = {nullptr, nullptr};
@@ -704,7 +704,7 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
   const bool fuse = l->p.step_fusion != 0 && !tape && l->nsrc == 0 &&
                     l->g.x_edge == kPeriodic && l->g.y_edge == kPeriodic &&
                     fused_supported(q, l->g.nx, l->g.ny);
-  const int k_max = l->p.step_fusion == 1 ? 3 : l->p.step_fusion;
+  const int k_max = l->p.step_fusion == 1 ? 4 : l->p.step_fusion;
 
   // the multi-step kernels read three ghost columns; other producers write
   // the first one only, so the frame is refreshed before the first
@@ -1240,7 +1240,7 @@ wlbm_status wlbm_set_dir_split(wlbm_lattice* l, int32_t split) {
 int32_t wlbm_get_dir_split(const wlbm_lattice* l) { return l ? l->split : -1; }
 
 int32_t wlbm_get_block_rows(const wlbm_lattice* l, int32_t k) {
-  if (!l || k < 2 || k > 3) return -1;
+  if (!l || k < 2 || k > 4) return -1;
   return l->tuner[l->per_cell ? 1 : 0][k].chosen;
 }
 

@@ -9,15 +9,15 @@
 namespace wlbm {
 
 // Padded HBM layout of every per-cell field (populations, E, W field).
-// A field plane holds rows y = -1 .. ny and columns x = -3 .. nx + 2, where
-// rows -1 and ny and columns -3 .. -1, nx .. nx + 2 are ghosts: for a
+// A field plane holds rows y = -1 .. ny and columns x = -4 .. nx + 3, where
+// rows -1 and ny and columns -4 .. -1, nx .. nx + 3 are ghosts: for a
 // periodic edge they hold copies of the opposite edge, otherwise they stay
 // zero.  k_step writes the first ghost column / row (-1, nx, ny) of what it
-// produces; the multi-step kernels, which read up to three ghost columns,
-// write all three, and fill_ghosts refreshes them after other producers.
+// produces; the multi-step kernels, which read up to four ghost columns,
+// write all four, and fill_ghosts refreshes them after other producers.
 // Cell (x, y) sits at (y + 1) * pitch + kXOff + x, so that x = 0 starts a
 // 128-byte line and a wave's 64 consecutive cells are two whole lines; each
-// row has at least four cells of padding after x = nx - 1.  Populations are
+// row has at least five cells of padding after x = nx - 1.  Populations are
 // [q] such planes (structure of arrays).
 constexpr int kXOff = 32;
 constexpr int kBlock = 256;
@@ -25,7 +25,7 @@ constexpr int kMaxQ = 1024;
 
 enum Edge { kPeriodic = 0, kBlackbody = 1, kDiffuse = 2 };
 
-inline int padded_pitch(int nx) { return ((nx + kXOff + 4 + 31) / 32) * 32; }
+inline int padded_pitch(int nx) { return ((nx + kXOff + 5 + 31) / 32) * 32; }
 inline int64_t padded_plane(int nx, int ny) { return int64_t(ny + 2) * padded_pitch(nx); }
 
 // Schedule code of one direction on one step: bits 0-1 dx+1, bits 2-3 dy+1,
@@ -86,7 +86,7 @@ int tiles_y_for(int ny, int split);
 // directions of a cell are split over several waves.
 size_t step_batch_lds_bytes(int q, int split);
 
-// K = 2 or 3 time steps (n+1 .. n+K) of a lattice with periodic x and y
+// K = 2, 3 or 4 time steps (n+1 .. n+K) of a lattice with periodic x and y
 // edges in one launch; codes[k] is the schedule row of step n+1+k.  Same
 // results as K launch_step calls.
 struct Step2Args {
@@ -95,7 +95,7 @@ struct Step2Args {
   const float* E_in;
   float* E_out;
   const float* Wf;
-  const uint32_t* codes[3];
+  const uint32_t* codes[4];
   const float* wtab;
   float W;
   int nx, ny, q, pitch;
@@ -104,7 +104,7 @@ struct Step2Args {
   int rows;   // output rows per block: rows + 2 (k - 1) a multiple of 3
 };
 hipError_t launch_fused(const Step2Args& a, int k, bool per_cell, hipStream_t s);
-// Ghost frame (three ghost columns each side, ghost rows) of nplanes periodic
+// Ghost frame (four ghost columns each side, ghost rows) of nplanes periodic
 // planes from the cells they wrap to.
 hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny, int pitch,
                        hipStream_t s);
@@ -113,7 +113,7 @@ int fused_strips_x(int nx);
 // written to cand); returns their number.
 int fused_row_candidates(int ny, int k, int* cand, int max_cand);
 // Whether the multi-step kernels take this lattice: q a multiple of 8 up to
-// 64 or of 16 up to 128, nx >= 6, ny >= 2.
+// 64 or of 16 up to 128, nx >= 8, ny >= 2.
 bool fused_supported(int q, int nx, int ny);
 
 // One time step of n lattices in one launch (same q, direction set and

@@ -2,7 +2,7 @@
 // gfx950.
 //
 // One launch of k_stepk<..., K> advances a periodic lattice by steps n+1 ..
-// n+K, K = 2 or 3 (Sec. 2.3 Eq. algorithm, pull form as in k_step): each
+// n+K, K = 2, 3 or 4 (Sec. 2.3 Eq. algorithm, pull form as in k_step): each
 // population is read from HBM once and written once per K steps, instead of
 // once per step.
 //
@@ -36,7 +36,7 @@ namespace {
 constexpr int kStrip = 48;
 // Ghost columns written on each side by every multi-step launch (the most
 // any K reads), so that launches of different K can follow each other.
-constexpr int kGhost = 3;
+constexpr int kGhost = 4;
 
 // Value held by lane l - 1 (the cell at x - 1), lane l + 1 (x + 1); lanes
 // with no such neighbour (0, resp. 63) read zero (bound control), which no
@@ -383,9 +383,13 @@ __device__ __forceinline__ void iteration(const Step2Args& a, Ring<SH, K>& g, fl
                                           int x0, int y0, int lane, int part, uint32_t lcol,
                                           bool out_lane) {
   level1<NW, SH, K, WF, S>(a, g, sP, t, y0, lane, part, lcol);
-  if constexpr (K == 3) {
+  if constexpr (K >= 3) {
     if (t < 2) return;
     level_mid<NW, SH, K, WF, 2, S>(a, g, sP, t, lane, part);
+  }
+  if constexpr (K >= 4) {
+    if (t < 4) return;
+    level_mid<NW, SH, K, WF, 3, S>(a, g, sP, t, lane, part);
   }
   if (t < 2 * (K - 1)) return;
   level_out<NW, SH, K, WF, S>(a, g, sP, t, x0, y0, lane, part, out_lane);
@@ -476,6 +480,11 @@ hipError_t launchk(const Step2Args& a, int k, bool wf, hipStream_t s) {
       hipLaunchKernelGGL((k_stepk<NW, SH, true, 3>), grid, block, 0, s, a);
     else
       hipLaunchKernelGGL((k_stepk<NW, SH, false, 3>), grid, block, 0, s, a);
+  } else if (k == 4) {
+    if (wf)
+      hipLaunchKernelGGL((k_stepk<NW, SH, true, 4>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_stepk<NW, SH, false, 4>), grid, block, 0, s, a);
   } else {
     return hipErrorInvalidValue;
   }
@@ -495,14 +504,16 @@ hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny
 int fused_strips_x(int nx) { return (nx + kStrip - 1) / kStrip; }
 
 // Candidate block heights for k steps per launch: R + 2 (k - 1) a multiple
-// of 3, R up to 47, and no taller than needed to cover ny in one block row.
+// of 3, R up to 62, and no taller than needed to cover ny in one block row.
 // Taller blocks re-read fewer halo rows but give fewer blocks, and how the
 // last round of resident blocks fills the GPU depends on the lattice, so the
 // caller times them (at 1024 x 1024, Q = 64, three steps per launch: R = 23
 // 1159, 29 963, 35 1058, 47 1064 G updates/s).
 int fused_row_candidates(int ny, int k, int* cand, int max_cand) {
   int n = 0;
-  for (int r = (k == 3 ? 5 : 4); r <= 47 && n < max_cand; r += 3) {
+  // R + 2 (k - 1) = 0 (mod 3)
+  const int r0 = k == 2 ? 4 : (k == 3 ? 5 : 6);
+  for (int r = r0; r <= 62 && n < max_cand; r += 3) {
     cand[n++] = r;
     if (r >= ny) break;
   }

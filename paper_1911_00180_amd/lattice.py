@@ -158,7 +158,7 @@ class Lattice:
         return W.wlbm_get_dir_split(self.handle)
 
     def block_rows(self, k: int) -> int:
-        """Output rows per block the library chose for k = 2 or 3 steps per
+        """Output rows per block the library chose for k = 2, 3 or 4 steps per
         launch (0 while still timing candidates)."""
         return W.wlbm_get_block_rows(self.handle, k)
 

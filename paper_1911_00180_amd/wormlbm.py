@@ -406,8 +406,8 @@ def make_params(nx: int, ny: int, q: int, mfp: float = float("inf"), dirs: str =
                 sched_chunk: int = 0, y_specularity: float = 0.0,
                 step_fusion: int = 1) -> WlbmParams:
     """Parameters from keyword arguments (edge and direction names as strings).
-    step_fusion: 1 / True = library default (up to three time steps per launch
-    where the lattice allows it), 2 or 3 = at most that many, 0 / False = one
+    step_fusion: 1 / True = library default (up to four time steps per launch
+    where the lattice allows it), 2 .. 4 = at most that many, 0 / False = one
     step per launch."""
     edges = {"periodic": EDGE_PERIODIC, "blackbody": EDGE_BLACKBODY, "diffuse": EDGE_DIFFUSE}
     p = wlbm_default_params()

@@ -95,7 +95,7 @@ def test_directions_and_constants_against_oracle(q, kind):
     ("dir_split", 3, W.WLBM_EINVAL), ("dir_split", 8, W.WLBM_EINVAL),
     ("sched_chunk", 5, W.WLBM_EINVAL), ("t_x_lo", float("inf"), W.WLBM_EINVAL),
     ("dirs", 5, W.WLBM_EINVAL), ("emulate_3d", 2, W.WLBM_EINVAL),
-    ("step_fusion", 4, W.WLBM_EINVAL), ("step_fusion", -1, W.WLBM_EINVAL),
+    ("step_fusion", 5, W.WLBM_EINVAL), ("step_fusion", -1, W.WLBM_EINVAL),
 ])
 def test_validation_errors(field, value, status):
     p = W.make_params(16, 16, 16, mfp=8.0)

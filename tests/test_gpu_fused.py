@@ -32,10 +32,10 @@ def _pair(nx, ny, q, fusion=1, **kw):
     return a, b
 
 
-@pytest.mark.parametrize("fusion", [2, 3])
-@pytest.mark.parametrize("nx,ny,q,mfp", [(150, 41, 64, 9.0), (97, 23, 32, 4.0), (7, 8, 8, 1e9)])
+@pytest.mark.parametrize("fusion", [2, 3, 4])
+@pytest.mark.parametrize("nx,ny,q,mfp", [(150, 41, 64, 9.0), (97, 23, 32, 4.0), (9, 8, 8, 1e9)])
 def test_two_and_three_steps_per_launch(fusion, nx, ny, q, mfp):
-    """At most two, resp. three, steps per launch against single steps, for
+    """At most two, three or four steps per launch against single steps, for
     counts that leave every remainder (and odd chunk ends)."""
     a, b = _pair(nx, ny, q, fusion=fusion, mfp=mfp, sched_chunk=17)
     e0 = torch.from_numpy(inputs.random_populations(8, q, ny, nx))
@@ -57,9 +57,9 @@ def test_two_and_three_steps_per_launch(fusion, nx, ny, q, mfp):
     (20, 10, 32, 1, 9.0, "ring"),
     (5, 3, 8, 1, 2.0, "uniform"),
     (200, 17, 24, 1, 1e9, "ring"),
-    (6, 2, 16, 2, 3.0, "uniform"),     # smallest lattice the multi-step kernels take
+    (8, 2, 16, 2, 3.0, "uniform"),     # smallest lattice the multi-step kernels take
     (49, 5, 64, 0, 8.0, "uniform"),    # last strip holds one column
-    (5, 9, 8, 1, 2.0, "uniform"),      # too narrow: single steps
+    (7, 9, 8, 1, 2.0, "uniform"),      # too narrow: single steps
     (128, 6, 128, 0, 20.0, "uniform"),
 ])
 def test_fused_equals_single_steps(nx, ny, q, split, mfp, kind):
@@ -124,7 +124,7 @@ def test_block_height_tuning_settles_and_keeps_bits():
     the tuning and after it."""
     nx, ny, q = 200, 130, 32
     a, b = _pair(nx, ny, q, fusion=3, mfp=12.0)
-    assert a.block_rows(3) == 0 and a.block_rows(5) == -1
+    assert a.block_rows(3) == 0 and a.block_rows(5) == -1 and a.block_rows(1) == -1
     e0 = torch.from_numpy(inputs.random_populations(4, q, ny, nx))
     for lat in (a, b):
         lat.set_populations(e0)
@@ -132,7 +132,7 @@ def test_block_height_tuning_settles_and_keeps_bits():
     b.step(1200)
     assert torch.equal(a.populations(), b.populations())
     rows = a.block_rows(3)
-    assert rows in range(5, 48, 3) and rows <= ny + 2
+    assert rows in range(5, 63, 3) and rows <= ny + 2
     a.step(30)
     b.step(30)
     assert torch.equal(a.populations(), b.populations())
