@@ -366,6 +366,10 @@ def main():
             "launches": launches,
             "ms_per_launch": round(ms_launch, 5),
             "algorithmic_bytes_per_launch": alg_bytes_launch,
+            # bytes a one-step-per-launch path would have to move per step,
+            # per unit time: above the HBM peak when several steps share a
+            # launch's traffic
+            "single_step_equivalent_GBs": round(alg_bytes_launch / (ms_step * 1e-3) / 1e9, 1),
         },
         "wall_s": round(wall, 4),
         "energy_after": energy,
