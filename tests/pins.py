@@ -277,6 +277,92 @@ def pin_ballistic_wall(o):
     assert np.max(np.abs(qy)) < 1e-12
 
 
+# -- Sec. 3.1: the one-pixel source and the angular-space-filling criterion --
+def pin_one_pixel_source(o):
+    """A pixel held at T = 1 by an isotropic source (Eq. isotropic) in a
+    51 x 51 periodic domain at T = 0, ballistic, 20 steps, ring sets of the
+    paper's figure (Q = 8, 16, 32, 512).  Q >= 2 pi n (ASF) fills every cell
+    within the propagated radius; fewer directions leave rays with gaps that
+    shrink as Q grows; nothing is lit farther than n + 1 cells (the
+    propagation error is at most one pixel, the bound stated in the same
+    section)."""
+    N, n = 51, 20
+    c = N // 2
+    x = np.arange(N) - c
+    r = np.sqrt(x[None, :] ** 2 + x[:, None] ** 2)
+    ann = (r > 12) & (r <= n - 2)
+    frac = {}
+    for q in (8, 16, 32, 512):
+        w = o.Lattice(o.Config(nx=N, ny=N, q=q, dirs="ring")).w
+        lat = o.Lattice(o.Config(nx=N, ny=N, q=q, dirs="ring", source_cells=np.array([[c, c]]),
+                                 source_values=w[None, :]))
+        lat.set_temperature(np.zeros((N, N)))
+        lat.run(n)
+        lit = lat.temperature() > 0
+        assert r[lit].max() <= n + 1, (q, r[lit].max())
+        frac[q] = lit[ann].mean()
+    assert 512 >= 2 * math.pi * n and frac[512] == 1.0
+    assert frac[8] < frac[16] < frac[32] < 0.5, frac
+
+
+# -- Sec. 3.4, Eq. 1DT: cross-plane transport in the Fourier limit -----------
+def _cross_plane_series(X, a, terms=400):
+    th = 1.0 - X
+    for l in range(1, terms):
+        th -= 2.0 / (math.pi * l) * np.sin(l * math.pi * X) * np.exp(-(l * math.pi) ** 2 * a)
+    return th
+
+
+def pin_cross_plane_fourier(o):
+    """Ny = 1 periodic, blackbody walls T = 1 / 0 at x = 0 / Nx - 1, start at
+    T = 0, MFP 2 cells (Kn 0.02), Q = 16: the profile follows the transient
+    series of Eq. 1DT with the lattice diffusivity MFP / 2 (d = 2), to within
+    the wall slip of order Kn, the closer the later."""
+    nx, mfp = 101, 2.0
+    L = nx - 1
+    X = np.arange(nx) / L
+    lat = o.Lattice(o.Config(nx=nx, ny=1, q=16, mfp=mfp, x_edge="blackbody", t_x_lo=1.0,
+                             t_x_hi=0.0))
+    lat.set_temperature(np.zeros((1, nx)))
+    done = 0
+    for n, tol in ((500, 0.04), (2000, 0.025), (6000, 0.012)):
+        lat.run(n - done)
+        done = n
+        ref = _cross_plane_series(X, (mfp / 2.0) * n / L ** 2)
+        err = np.abs(lat.temperature()[0] - ref).max()
+        assert err < tol, (n, err)
+
+
+# -- Sec. 3.6, Eq. 2DT: one hot - three cold walls, steady Fourier limit -----
+def one_hot_three_cold_series(X, Y, terms=200):
+    th = np.zeros(np.broadcast(X, Y).shape)
+    for l in range(1, terms, 2):   # 1 - cos(l pi) = 2 for odd l, 0 for even
+        # sinh(l pi Y) / sinh(l pi), written without overflow
+        ratio = np.exp(l * math.pi * (Y - 1.0)) * (1.0 - np.exp(-2.0 * l * math.pi * Y)) / (
+            1.0 - np.exp(-2.0 * l * math.pi))
+        th += 4.0 / (l * math.pi) * np.sin(l * math.pi * X) * ratio
+    return th
+
+
+def pin_one_hot_three_cold(o):
+    """Blackbody walls, the upper one at T = 1 and the others at 0, 32 x 32,
+    MFP 1.5 cells, Q = 16: the steady state matches the Laplace series of
+    Eq. 2DT in the middle half of the square (walls at cells 0 and N - 1)."""
+    N = 32
+    lat = o.Lattice(o.Config(nx=N, ny=N, q=16, mfp=1.5, x_edge="blackbody", y_edge="blackbody",
+                             t_y_hi=1.0))
+    lat.set_temperature(np.zeros((N, N)))
+    lat.run(4000)
+    X = np.arange(N)[None, :] / (N - 1)
+    Y = np.arange(N)[:, None] / (N - 1)
+    mid = slice(N // 4, 3 * N // 4 + 1)
+    err = np.abs(lat.temperature() - one_hot_three_cold_series(X, Y))[mid, mid].max()
+    assert err < 0.02, err
+    # the series itself: 1/4 at the centre of the square (four rotated
+    # copies of the problem add up to T = 1 everywhere)
+    assert abs(one_hot_three_cold_series(np.array(0.5), np.array(0.5)) - 0.25) < 1e-12
+
+
 ALL_PINS = [
     pin_tas_d2q8_diagonal,
     pin_propagation_error,
@@ -292,4 +378,7 @@ ALL_PINS = [
     pin_von_neumann,
     pin_ballistic_wall,
     pin_fourier_limit,
+    pin_one_pixel_source,
+    pin_cross_plane_fourier,
+    pin_one_hot_three_cold,
 ]
