@@ -351,8 +351,9 @@ int32_t wlbm_get_dir_split(const wlbm_lattice* lat);
  * so or before the first such launch, -1 for NULL or k outside 2 .. 4. */
 int32_t wlbm_get_block_rows(const wlbm_lattice* lat, int32_t k);
 
-/* Time `steps` steps (1 .. 10000, after 2 warm-up steps) with each valid
- * split on the current state and keep the fastest.  The state and step count
+/* Time `steps` steps (1 .. 10000, after 2 warm-up steps, one step per launch:
+ * the split is the single-step kernel's) with each valid split on the
+ * current state and keep the fastest.  The state and step count
  * are saved in d_state (wlbm_state_bytes bytes) and restored after each
  * trial, so the lattice ends where it started; the flux-window sums are not
  * touched.  ms_by_split (host [3], may be NULL) receives the time per step of

@@ -1460,6 +1460,7 @@ wlbm_status wlbm_autotune(wlbm_lattice* l, void* d_state, size_t bytes, int32_t 
   const bool flux_valid = l->flux_valid;
   const int flux_window = l->flux_window;
   const int keep_split = l->split;
+  const int keep_fusion = l->p.step_fusion;
   st = wlbm_save_state(l, d_state, bytes);
   if (st) return st;
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1474,6 +1475,7 @@ wlbm_status wlbm_autotune(wlbm_lattice* l, void* d_state, size_t bytes, int32_t 
   int best_split = keep_split;
   bool have = false;
   l->flux_window = 0;  // the tuning steps leave the flux-window sums alone
+  l->p.step_fusion = 0;  // the split is the single-step kernel's: time that one
   for (int k = 0; k < 3 && st == WLBM_OK; ++k) {
     float ms = -1.f;
     if (l->p.q % (kMaxGroupPlanes * cand[k]) == 0 &&
@@ -1504,6 +1506,7 @@ wlbm_status wlbm_autotune(wlbm_lattice* l, void* d_state, size_t bytes, int32_t 
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   l->flux_window = flux_window;
+  l->p.step_fusion = keep_fusion;
   if (st) {
     l->split = keep_split;
     return st;
