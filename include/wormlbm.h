@@ -348,8 +348,16 @@ int32_t wlbm_get_dir_split(const wlbm_lattice* lat);
  * The library picks this height by timing its first multi-step launches of
  * the lattice with each candidate height (two passes of 6 launches per
  * candidate; results do not depend on the height); 0 while it is still doing
- * so or before the first such launch, -1 for NULL or k outside 2 .. 4. */
+ * so or before the first such launch, -1 for NULL or k outside 2 .. 4.
+ * The timing synchronizes the stream after each timed sample, so the first
+ * multi-step launches of a lattice must not be captured into a HIP graph;
+ * wlbm_set_block_rows fixes the height beforehand instead. */
 int32_t wlbm_get_block_rows(const wlbm_lattice* lat, int32_t k);
+
+/* Fix the output rows per block of the k-step kernel (k = 2 .. 4) for the
+ * lattice's current weight mode: rows + 2 (k - 1) a multiple of 3, 1 .. 62;
+ * 0 restarts the timing of candidate heights.  Results do not depend on it. */
+wlbm_status wlbm_set_block_rows(wlbm_lattice* lat, int32_t k, int32_t rows);
 
 /* Time `steps` steps (1 .. 10000, after 2 warm-up steps, one step per launch:
  * the split is the single-step kernel's) with each valid split on the

@@ -1244,6 +1244,19 @@ int32_t wlbm_get_block_rows(const wlbm_lattice* l, int32_t k) {
   return l->tuner[l->per_cell ? 1 : 0][k].chosen;
 }
 
+wlbm_status wlbm_set_block_rows(wlbm_lattice* l, int32_t k, int32_t rows) {
+  wlbm_status st = check_lat(l);
+  if (st) return st;
+  if (k < 2 || k > 4) return fail(WLBM_EINVAL, "k must be 2, 3 or 4 (got %d)", k);
+  if (rows < 0 || rows > 62 || (rows > 0 && (rows + 2 * (k - 1)) % 3 != 0))
+    return fail(WLBM_EINVAL,
+                "rows must be 0 or 1 .. 62 with rows + 2 (k - 1) a multiple of 3 (got %d)", rows);
+  RowTuner& tu = l->tuner[l->per_cell ? 1 : 0][k];
+  tu.next = 0;
+  tu.chosen = rows;
+  return WLBM_OK;
+}
+
 wlbm_status wlbm_batch_bytes(wlbm_lattice* const* lats, int32_t n, size_t* bytes) {
   wlbm_status st = check_members(lats, n);
   if (st) return st;

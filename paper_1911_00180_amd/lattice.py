@@ -162,6 +162,11 @@ class Lattice:
         launch (0 while still timing candidates)."""
         return W.wlbm_get_block_rows(self.handle, k)
 
+    def set_block_rows(self, k: int, rows: int) -> None:
+        """Fix the output rows per block for k steps per launch (0: time the
+        candidates again)."""
+        W.wlbm_set_block_rows(self.handle, k, rows)
+
     def set_dir_split(self, split: int) -> None:
         W.wlbm_set_dir_split(self.handle, split)
 

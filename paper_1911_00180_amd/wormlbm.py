@@ -44,7 +44,7 @@ EXPORTS = (
     "wlbm_set_dir_split", "wlbm_get_dir_split", "wlbm_autotune", "wlbm_batch_bytes",
     "wlbm_batch_create", "wlbm_batch_step", "wlbm_batch_destroy", "wlbm_read_flux_mean",
     "wlbm_set_sources", "wlbm_flux_distribution", "wlbm_set_speeds",
-    "wlbm_accumulate_temperature", "wlbm_get_block_rows",
+    "wlbm_accumulate_temperature", "wlbm_get_block_rows", "wlbm_set_block_rows",
 )
 
 
@@ -121,6 +121,7 @@ def lib() -> ctypes.CDLL:
         "wlbm_set_dir_split": (c_int, [c_void_p, c_int32]),
         "wlbm_get_dir_split": (c_int32, [c_void_p]),
         "wlbm_get_block_rows": (c_int32, [c_void_p, c_int32]),
+        "wlbm_set_block_rows": (c_int, [c_void_p, c_int32, c_int32]),
         "wlbm_autotune": (c_int, [c_void_p, c_void_p, c_size_t, c_int32, POINTER(ctypes.c_float),
                                   POINTER(c_int32)]),
         "wlbm_batch_bytes": (c_int, [POINTER(c_void_p), c_int32, POINTER(c_size_t)]),
@@ -345,6 +346,10 @@ def wlbm_get_dir_split(h: int) -> int:
 
 def wlbm_get_block_rows(h: int, k: int) -> int:
     return lib().wlbm_get_block_rows(c_void_p(h), k)
+
+
+def wlbm_set_block_rows(h: int, k: int, rows: int) -> None:
+    _check(lib().wlbm_set_block_rows(c_void_p(h), k, rows))
 
 
 def wlbm_autotune(h: int, d_state, nbytes: int, steps: int):

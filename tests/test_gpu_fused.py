@@ -139,3 +139,34 @@ def test_block_height_tuning_settles_and_keeps_bits():
     assert a.block_rows(3) == rows
     a.close()
     b.close()
+
+
+def test_fixed_block_heights():
+    """Heights set by the caller skip the timing and keep the bits; invalid
+    heights are rejected."""
+    from paper_1911_00180_amd import wormlbm as W
+    nx, ny, q = 120, 70, 16
+    e0 = torch.from_numpy(inputs.random_populations(6, q, ny, nx))
+    b = None
+    for k, rows in ((2, 1), (3, 8), (4, 9), (4, 30)):
+        a, b0 = _pair(nx, ny, q, fusion=k, mfp=5.0)
+        if b is None:
+            b = b0
+            b.set_populations(e0)
+            b.step(24)
+        else:
+            b0.close()
+        a.set_block_rows(k, rows)
+        assert a.block_rows(k) == rows
+        a.set_populations(e0)
+        a.step(24)
+        assert torch.equal(a.populations(), b.populations()), (k, rows)
+        for bad in (2, 63, -1):
+            if bad and (bad + 2 * (k - 1)) % 3 == 0 and 0 < bad <= 62:
+                continue
+            with pytest.raises(W.WormLBMError):
+                a.set_block_rows(k, bad)
+        a.close()
+    with pytest.raises(W.WormLBMError):
+        b.set_block_rows(5, 3)
+    b.close()
