@@ -762,7 +762,7 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
       // window)
       const int K = int(std::min<int64_t>({int64_t(k_max), int64_t(cnt - j), flux_from - k}));
       if (fuse && K >= 2) {
-        Step2Args a2{};
+        FusedArgs a2{};
         a2.e_in = l->ptr(l->c.e[l->cur]);
         a2.e_out = l->ptr(l->c.e[1 - l->cur]);
         a2.E_in = l->ptr(l->c.E[l->cur]);

@@ -89,7 +89,7 @@ size_t step_batch_lds_bytes(int q, int split);
 // K = 2, 3 or 4 time steps (n+1 .. n+K) of a lattice with periodic x and y
 // edges in one launch; codes[k] is the schedule row of step n+1+k.  Same
 // results as K launch_step calls.
-struct Step2Args {
+struct FusedArgs {
   const float* e_in;
   float* e_out;
   const float* E_in;
@@ -103,7 +103,7 @@ struct Step2Args {
   int strips_x, strips_y;
   int rows;   // output rows per block: rows + 2 (k - 1) a multiple of 3
 };
-hipError_t launch_fused(const Step2Args& a, int k, bool per_cell, hipStream_t s);
+hipError_t launch_fused(const FusedArgs& a, int k, bool per_cell, hipStream_t s);
 // Ghost frame (four ghost columns each side, ghost rows) of nplanes periodic
 // planes from the cells they wrap to.
 hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny, int pitch,

@@ -130,7 +130,7 @@ struct Ring {
 // wave's directions pulls (row r - hy, column x - hx) into g.V, and step-n E
 // (and W) of row r + 1 into ring slot SN.  Nothing waits for them here.
 template <int SH, int K, bool WF, int SN>
-__device__ __forceinline__ void issue_row(const Step2Args& a, Ring<SH, K>& g, int r, int i_begin,
+__device__ __forceinline__ void issue_row(const FusedArgs& a, Ring<SH, K>& g, int r, int i_begin,
                                           uint32_t lcol) {
   const WLBM_CONST uint32_t* codes1 = row_ptr(a.codes[0]);
   const WLBM_CONST uint32_t* tab = row_ptr(&kCodeSel.m[0][0]);
@@ -174,7 +174,7 @@ struct RowCtx {
   const WLBM_CONST uint32_t* tab;
   uint32_t plane_bytes;
 };
-__device__ __forceinline__ RowCtx row_ctx(const Step2Args& a) {
+__device__ __forceinline__ RowCtx row_ctx(const FusedArgs& a) {
   RowCtx c;
   c.wtab = row_ptr(a.wtab);
   c.tab = row_ptr(&kCodeSel.m[0][0]);
@@ -187,7 +187,7 @@ __device__ __forceinline__ RowCtx row_ctx(const Step2Args& a) {
 // from the step-n loads; then the loads of the next row are issued, and E of
 // row r is summed.  Step-n slots: rows r-1, r, r+1 are S, S+1, S+2 (mod 3).
 template <int NW, int SH, int K, bool WF, int S>
-__device__ __forceinline__ void level1(const Step2Args& a, Ring<SH, K>& g, float* sP, int t,
+__device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float* sP, int t,
                                        int y0, int lane, int part, uint32_t lcol) {
   constexpr int S1 = (S + 1) % 3, S2 = (S + 2) % 3;
   constexpr int NB = NW * SH / kMaxGroupPlanes;   // batches of 8 directions
@@ -243,7 +243,7 @@ __device__ __forceinline__ void level1(const Step2Args& a, Ring<SH, K>& g, float
 // rho-1 .. rho+1 of level L-1 are in slots S1, S2, S (computed at iterations
 // t-2, t-1, t).
 template <int SH, int K, bool WF, int L, int S>
-__device__ __forceinline__ float relax_up(const Step2Args& a, const Ring<SH, K>& g,
+__device__ __forceinline__ float relax_up(const FusedArgs& a, const Ring<SH, K>& g,
                                           const WLBM_CONST uint32_t* m, float wi, int j) {
   constexpr int S1 = (S + 1) % 3, S2 = (S + 2) % 3;
   constexpr int P = L - 2;   // ring index of level L-1
@@ -265,7 +265,7 @@ __device__ __forceinline__ float relax_up(const Step2Args& a, const Ring<SH, K>&
 // An intermediate level L (2 .. K-1) at iteration t: row r - (L-1) into ring
 // slot S of level L, and its E.
 template <int NW, int SH, int K, bool WF, int L, int S>
-__device__ __forceinline__ void level_mid(const Step2Args& a, Ring<SH, K>& g, float* sP, int t,
+__device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, float* sP, int t,
                                           int lane, int part) {
   constexpr int S2 = (S + 2) % 3;
   constexpr int NB = NW * SH / kMaxGroupPlanes;
@@ -301,7 +301,7 @@ __device__ __forceinline__ void level_mid(const Step2Args& a, Ring<SH, K>& g, fl
 // The output level K at iteration t: row ro = r - (K-1), stored with its
 // ghost copies.
 template <int NW, int SH, int K, bool WF, int S>
-__device__ __forceinline__ void level_out(const Step2Args& a, Ring<SH, K>& g, float* sP, int t,
+__device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, float* sP, int t,
                                           int x0, int y0, int lane, int part, bool out_lane) {
   constexpr int NB = NW * SH / kMaxGroupPlanes;
   const RowCtx c = row_ctx(a);
@@ -379,7 +379,7 @@ __device__ __forceinline__ void level_out(const Step2Args& a, Ring<SH, K>& g, fl
 // Iteration t (ring slot S = t mod 3): level 1, then each higher level once
 // the three rows it reads exist.
 template <int NW, int SH, int K, bool WF, int S>
-__device__ __forceinline__ void iteration(const Step2Args& a, Ring<SH, K>& g, float* sP, int t,
+__device__ __forceinline__ void iteration(const FusedArgs& a, Ring<SH, K>& g, float* sP, int t,
                                           int x0, int y0, int lane, int part, uint32_t lcol,
                                           bool out_lane) {
   level1<NW, SH, K, WF, S>(a, g, sP, t, y0, lane, part, lcol);
@@ -424,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_fill_ghosts(float* base, long long p
 }
 
 template <int NW, int SH, bool WF, int K>
-__global__ __launch_bounds__(64 * NW) void k_stepk(const Step2Args a) {
+__global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
   // E batch sums: [level 1 .. K][row parity][batch of 8 directions][lane]
   __shared__ float sP[2 * K * (NW * SH / kMaxGroupPlanes) * 64];
   const int lane = threadIdx.x & 63;
@@ -468,7 +468,7 @@ __global__ __launch_bounds__(64 * NW) void k_stepk(const Step2Args a) {
 }
 
 template <int NW, int SH>
-hipError_t launchk(const Step2Args& a, int k, bool wf, hipStream_t s) {
+hipError_t launchk(const FusedArgs& a, int k, bool wf, hipStream_t s) {
   const dim3 grid(a.strips_x * a.strips_y), block(64 * NW);
   if (k == 2) {
     if (wf)
@@ -526,7 +526,7 @@ bool fused_supported(int q, int nx, int ny) {
          (q <= 64 || (q <= 128 && q % 16 == 0));
 }
 
-hipError_t launch_fused(const Step2Args& a, int k, bool per_cell, hipStream_t s) {
+hipError_t launch_fused(const FusedArgs& a, int k, bool per_cell, hipStream_t s) {
   if (a.q <= 64) {
     switch (a.q / 8) {
       case 1: return launchk<1, 8>(a, k, per_cell, s);

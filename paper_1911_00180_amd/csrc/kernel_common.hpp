@@ -80,8 +80,8 @@ __device__ __forceinline__ int wrap_index(int v, int n) {
 
 // Store a cell value and, for periodic edges, its ghost copies: column nx
 // holds column 0, column -1 holds column nx - 1, likewise for rows, corners
-// both.  (The second ghost column each side, which the two-step kernel
-// reads, is refreshed by k_fill_ghosts.)
+// both.  (The further ghost columns each side, which the multi-step kernels
+// read, are refreshed by k_fill_ghosts.)
 __device__ __forceinline__ void store_ghosted(float* __restrict__ plane, int x, int y, float v,
                                               int nx, int ny, int pitch, bool px, bool py) {
   plane[cell(x, y, pitch)] = v;

@@ -106,7 +106,7 @@ __device__ __forceinline__ void load_batch(const StepArgs& a, int i0, uint32_t b
 // E' = sum_i out_i is added in a fixed order that does not depend on the
 // direction split: each batch of D = 8 directions is summed in direction
 // order, then the batch sums are added in batch order (sBat holds them when
-// several waves share a cell).  The two-step kernel adds in the same order.
+// several waves share a cell).  The multi-step kernels add in the same order.
 template <int NW, bool WF, bool FLUX, bool EDGE>
 __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const float* sW,
                                       const float* sTg, const float* sWTg, float* sRed,

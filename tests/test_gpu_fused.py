@@ -1,11 +1,13 @@
-"""Two steps per launch (k_step2) against one step per launch (k_step).
+"""Several steps per launch (k_stepk, K = 2 .. 4) against one step per launch
+(k_step).
 
-The fused kernel uses the same arithmetic and the same summation order as the
-single-step kernel, so the populations must agree bit for bit, whatever
-direction split the single steps use, on ragged and tiny lattices, for odd step counts (the last
-step runs alone), across schedule chunks and around flux windows (whose steps
-run alone).  Oracle parity of the fused path is covered by every periodic
-parity test, which now runs it by default.
+The multi-step kernels use the same arithmetic and the same summation order
+as the single-step kernel, so the populations must agree bit for bit,
+whatever direction split the single steps use and whatever block height the
+library picks, on ragged and tiny lattices, for step counts that leave single
+steps at the end, across schedule chunks and around flux windows (whose
+steps run alone).  Oracle parity of the multi-step path is covered by every
+periodic parity test, which runs it by default.
 """
 import numpy as np
 import pytest

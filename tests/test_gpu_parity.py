@@ -295,7 +295,7 @@ def test_crop_256_q64_4000_steps(kn):
 def test_direction_splits_are_bit_identical(q):
     """E is summed in the same order (8-direction batch sums, added in batch
     order) whatever the split of the directions over waves, so every split,
-    and the two-steps-per-launch path, gives the same bits."""
+    and the multi-step path, gives the same bits."""
     nx, ny = 141, 29
     e0 = torch.from_numpy(inputs.random_populations(5, q, ny, nx))
     runs = []
