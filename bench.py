@@ -252,6 +252,13 @@ def cpu_baseline(budget_s: float = 15.0):
         lat.step()
         n += 1
     dt = time.perf_counter() - t0
+    # the small parity lattice too: 64 x 64, Q = 16, MFP 16, 200 steps
+    c1 = o.Lattice(o.Config(nx=64, ny=64, q=16, mfp=16.0))
+    xx = np.arange(64) - 32
+    c1.set_temperature(np.exp(-(xx[None, :] ** 2 + xx[:, None] ** 2) / (2 * 4.0 ** 2)))
+    t1 = time.perf_counter()
+    c1.run(200)
+    d1 = time.perf_counter() - t1
     return {
         "value": nx * ny * q * n / dt / 1e9,
         "unit": "Gupdates/s",
@@ -260,6 +267,9 @@ def cpu_baseline(budget_s: float = 15.0):
         "sample": f"256x256 periodic crop, Q=64, MFP 102.4, {n} steps of the FP64 numpy "
                   f"oracle in {dt:.1f} s (numpy elementwise ops, one thread; host has "
                   f"{os.cpu_count()} logical CPUs)",
+        "small_lattice": {"workload": "64x64 periodic, Q=16, MFP 16, 200 steps",
+                          "value": round(64 * 64 * 16 * 200 / d1 / 1e9, 4),
+                          "unit": "Gupdates/s", "seconds": round(d1, 3)},
     }
 
 
