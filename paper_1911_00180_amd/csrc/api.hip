@@ -785,7 +785,7 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
         const int phase = tu.next % RowTuner::kSample;
         const bool first_pass = tu.next < RowTuner::kSample * tu.ncand;
         a2.rows = timing ? tu.cand[ci] : tu.chosen;
-        a2.strips_x = fused_strips_x(a.nx);
+        a2.strips_x = fused_strips_x(a.nx, K);
         a2.strips_y = (a.ny + a2.rows - 1) / a2.rows;
         if (refresh_ghosts) {
           e = fill_ghosts(l->ptr(l->c.e[l->cur]), a.plane, q, a.nx, a.ny, a.pitch, l->stream);

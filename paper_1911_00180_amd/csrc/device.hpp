@@ -108,7 +108,7 @@ hipError_t launch_fused(const FusedArgs& a, int k, bool per_cell, hipStream_t s)
 // planes from the cells they wrap to.
 hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny, int pitch,
                        hipStream_t s);
-int fused_strips_x(int nx);
+int fused_strips_x(int nx, int k);
 // Candidate output rows per block for k steps per launch (at most max_cand,
 // written to cand); returns their number.
 int fused_row_candidates(int ny, int k, int* cand, int max_cand);

@@ -6,7 +6,7 @@
 // population is read from HBM once and written once per K steps, instead of
 // once per step.
 //
-// A block owns a strip of 48 columns and a.rows rows of the output.  Its NW
+// A block owns a strip of kStrip columns and a.rows rows of the output.  Its NW
 // waves cover the same 64 columns x0-K .. x0+63-K, one per lane, and take SH
 // directions each (8, or 16 above Q = 64).  Rows are pipelined: at iteration
 // t the waves compute level 1 (step n+1) of row r = y0-(K-1)+t from the
@@ -27,13 +27,18 @@
 namespace wlbm {
 namespace {
 
-// Output columns per block (lanes 2 .. 49).  A multiple of 16, so that every
+// Output columns per block (lanes K .. K + kStrip - 1) for K steps per
+// launch.  With two or three steps, 48, a multiple of 16, so that every
 // block's output rows are whole 64-byte write segments (x = 0 starts a
 // 128-byte line): with 60 or 56 columns most rows end in partial segments on
-// both sides, and those partial writes cost more than the idle lanes
-// (measured at 1024 x 1024, Q = 64: 60 columns 788, 56 columns 851, 48
-// columns 928, 32 columns 723 G updates/s, 4-row blocks).
-constexpr int kStrip = 48;
+// both sides, and those partial writes cost more than the idle lanes (two
+// steps at 1024 x 1024, Q = 64: 60 columns 788, 56 columns 851, 48 columns
+// 928, 32 columns 723 G updates/s, 4-row blocks).  With four steps a launch
+// writes half as often per step and does more arithmetic per byte, and the
+// 56 columns the halo leaves are faster (1256 against 1195; with two steps
+// 56 columns cost 10 %).
+template <int K>
+constexpr int kStrip = K == 4 ? 56 : 48;
 // Ghost columns written on each side by every multi-step launch (the most
 // any K reads), so that launches of different K can follow each other.
 constexpr int kGhost = 4;
@@ -320,7 +325,7 @@ __device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, fl
   // kGhost-1 are copied to nx .. nx+kGhost-1 and columns nx-kGhost .. nx-1 to
   // -kGhost .. -1; rows 0 and ny - 1 to ny and -1.  Only blocks on the
   // lattice's edge have any, which the whole block knows.
-  const bool edge = x0 == 0 || x0 + kStrip + kGhost - 1 >= nx || ro == 0 || ro == ny - 1;
+  const bool edge = x0 == 0 || x0 + kStrip<K> + kGhost - 1 >= nx || ro == 0 || ro == ny - 1;
   const bool gx = store && (xo < kGhost || xo >= nx - kGhost);
   const bool gy = store && (ro == 0 || ro == ny - 1);
   const int xg = xo < kGhost ? xo + nx : xo - nx;
@@ -430,7 +435,7 @@ __global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
   const int lane = threadIdx.x & 63;
   const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = xcd_tile(blockIdx.x, gridDim.x);
-  const int x0 = (b % a.strips_x) * kStrip;
+  const int x0 = (b % a.strips_x) * kStrip<K>;
   const int y0 = (b / a.strips_x) * a.rows;
   // this lane's column; lanes past the ghost frame read its last column
   // (their values are never used), so that every read stays inside the row
@@ -438,7 +443,7 @@ __global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
   const int x = x0 - K + lane;
   const int xl = x < a.nx + kGhost - 1 ? x : a.nx + kGhost - 1;
   const uint32_t lcol = uint32_t((kXOff + xl) * 4);
-  const bool out_lane = lane >= K && lane < K + kStrip && x < a.nx;
+  const bool out_lane = lane >= K && lane < K + kStrip<K> && x < a.nx;
 
   Ring<SH, K> g;
   // step-n E of rows r0 - 1 and r0 (r0 = y0 - (K-1), the first level-1 row)
@@ -501,7 +506,10 @@ hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny
   return hipGetLastError();
 }
 
-int fused_strips_x(int nx) { return (nx + kStrip - 1) / kStrip; }
+int fused_strips_x(int nx, int k) {
+  const int w = k == 4 ? kStrip<4> : (k == 3 ? kStrip<3> : kStrip<2>);
+  return (nx + w - 1) / w;
+}
 
 // Candidate block heights for k steps per launch: R + 2 (k - 1) a multiple
 // of 3, R up to 62, and no taller than needed to cover ny in one block row.
