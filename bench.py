@@ -115,9 +115,9 @@ def adjoint_bytes_per_update(q: int, per_cell_w: bool = False) -> float:
     return 12.0 + (64.0 + 4.0 + 16.0 + (4.0 if per_cell_w else 0.0)) / q
 
 
-def run_adjoint_ratio(steps=1000, K=50, repeats=3):
+def run_adjoint_ratio(n=256, q=64, steps=1000, K=50, repeats=3):
     """Forward (with checkpoints and probe reads) and backward (recompute +
-    reverse steps) of the 256 x 256, Q = 64 inverse problem; median times."""
+    reverse steps) of the n x n, Q = q inverse problem; median times."""
     import numpy as np
     import torch
 
@@ -125,8 +125,8 @@ def run_adjoint_ratio(steps=1000, K=50, repeats=3):
     from paper_1911_00180_amd.autodiff import ProbeSeries
     from paper_1911_00180_amd.lattice import Lattice
 
-    n, mfp, tgt, T0, probes = inputs.inverse_problem_256()
-    lat = Lattice(n, n, 64, mfp=16.0, x_edge="blackbody", y_edge="periodic", device="cuda:0")
+    n, mfp, tgt, T0, probes = inputs.inverse_problem(n)
+    lat = Lattice(n, n, q, mfp=16.0, x_edge="blackbody", y_edge="periodic", device="cuda:0")
     series = ProbeSeries(lat, probes, steps, 10, checkpoint_every=K)
     dev = "cuda:0"
     walls = torch.tensor([0.5, 0.0, 0.0, 0.0], device=dev)
@@ -150,13 +150,18 @@ def run_adjoint_ratio(steps=1000, K=50, repeats=3):
             fwd.append(e0.elapsed_time(e1))
             bwd.append(e1.elapsed_time(e2))
     grad_ok = bool(torch.isfinite(m.grad).all())
+    state_gb = (series.ck.numel() + series.tape.numel()) / 1e9
     lat.close()
+    del out, loss, m, series, target
+    torch.cuda.empty_cache()
     f, b = float(np.median(fwd)), float(np.median(bwd))
-    return {"workload": "256x256, Q=64, lognormal MFP field (median 16, clipped 4..64), blackbody "
-                        "x walls 0.5/0, periodic y, 1000 steps, 32 probes, loss every 10 steps, "
-                        f"checkpoint every {K}",
+    return {"workload": f"{n}x{n}, Q={q}, lognormal MFP field (median 16, clipped 4..64, "
+                        f"correlation {16 * n // 256}), blackbody x walls 0.5/0, periodic y, "
+                        f"{steps} steps, 32 probes, loss every 10 steps, checkpoint every {K}",
             "forward_ms": round(f, 3), "backward_ms": round(b, 3),
-            "ratio": round(b / f, 3), "grad_finite": grad_ok}
+            "ratio": round(b / f, 3), "grad_finite": grad_ok,
+            "saved_states_GB": round(state_gb, 2),
+            "forward_gups": round(n * n * q * steps / (f * 1e-3) / 1e9, 2)}
 
 
 def run_adjoint_kernel(nx=1024, ny=1024, q=64, steps=20):
@@ -282,7 +287,8 @@ def main():
     ap.add_argument("--split", type=int, default=0,
                     help="waves sharing one cell's directions (0 = library default)")
     ap.add_argument("--large", action="store_true",
-                    help="also time the 4096 x 4096, Q = 256 wall-bounded lattice")
+                    help="also time the 4096 x 4096, Q = 256 wall-bounded lattice and the "
+                         "2048 x 2048, Q = 128 inverse problem (about 160 GB of checkpoints)")
     ap.add_argument("--large-steps", type=int, default=200)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurements")
@@ -417,6 +423,8 @@ def main():
             "ms_per_step": round(st, 4),
             "roofline_frac": round(bl / (st * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         }
+        # the 2048 x 2048, Q = 128 inverse problem, checkpoints sized to HBM
+        out["large_adjoint"] = run_adjoint_ratio(n=2048, q=128, steps=1000, K=50, repeats=1)
     if not args.no_adjoint:
         adj = run_adjoint_ratio()
         adj["kernel"] = run_adjoint_kernel()

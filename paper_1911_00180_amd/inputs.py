@@ -75,18 +75,25 @@ def random_temperature(seed: int, ny: int, nx: int, dtype=np.float32) -> np.ndar
     return rng.random((ny, nx)).astype(dtype)
 
 
-def inverse_problem_256(seed_field: int = 1, seed_target: int = 2):
-    """Inputs of the 256 x 256, Q = 64 inverse problem (MFP field recovered
-    from probe temperatures): the MFP field ln MFP = ln 16 + (ln 4 / 2) z,
-    z smooth (correlation 16 cells) and standardised, clipped to [4, 64],
-    from default_rng(seed_field); the target field from default_rng(seed_target);
-    a centred Gaussian pulse sigma0 = 16; 32 probe cells from default_rng(3),
-    at least 8 cells from the edges.  Returns (n, mfp, target_mfp, T0, probes)
-    with float32 fields and probes as int [32, 2] (x, y)."""
-    n = 256
+def inverse_problem(n: int = 256, seed_field: int = 1, seed_target: int = 2):
+    """Inputs of the n x n inverse problem (MFP field recovered from probe
+    temperatures), with lengths scaled by s = n / 256: the MFP field
+    ln MFP = ln 16 + (ln 4 / 2) z, z smooth (correlation 16 s cells) and
+    standardised, clipped to [4, 64] cells, from default_rng(seed_field); the
+    target field from default_rng(seed_target); a centred Gaussian pulse
+    sigma0 = 16 s; 32 probe cells from default_rng(3), at least 8 s cells
+    from the edges.  Returns (n, mfp, target_mfp, T0, probes) with float32
+    fields and probes as int [32, 2] (x, y)."""
+    s = n / 256.0
     spread = float(np.log(4.0) / 2.0)
-    mfp = smooth_lognormal_field(n, n, seed_field, 16.0, 16.0, spread, 4.0, 64.0)
-    tgt = smooth_lognormal_field(n, n, seed_target, 16.0, 16.0, spread, 4.0, 64.0)
-    T0 = gaussian_pulse(n, n, 16.0, n // 2, n // 2)
-    probes = probe_cells(3, n, n, 32, margin=8)
+    mfp = smooth_lognormal_field(n, n, seed_field, 16.0 * s, 16.0, spread, 4.0, 64.0)
+    tgt = smooth_lognormal_field(n, n, seed_target, 16.0 * s, 16.0, spread, 4.0, 64.0)
+    T0 = gaussian_pulse(n, n, 16.0 * s, n // 2, n // 2)
+    probes = probe_cells(3, n, n, 32, margin=int(round(8 * s)))
     return n, mfp.astype(np.float32), tgt.astype(np.float32), T0.astype(np.float32), probes
+
+
+def inverse_problem_256(seed_field: int = 1, seed_target: int = 2):
+    """The 256 x 256 inverse problem (correlation 16 cells, sigma0 = 16,
+    probes at least 8 cells from the edges)."""
+    return inverse_problem(256, seed_field, seed_target)

@@ -231,3 +231,60 @@ def test_c4_full_size_directional_derivatives():
         print(f"wall {k}: adjoint {an:.6e}  central difference {fd:.6e}")
         assert abs(an - fd) <= 2e-3 * abs(fd)
     lat.close()
+
+
+def test_c5_adjoint_2048_q128_directional_derivatives():
+    """The 2048 x 2048, Q = 128 inverse problem (MFP correlation 128 cells,
+    pulse sigma0 = 128, blackbody x walls at 0.5 and 0, periodic y) over 200
+    steps with a checkpoint every 20: <grad, v> against the chain rule through
+    central differences of the GPU forward's probe temperatures,
+    sum_k 2 (T_k - T^_k) (T_k(+h v) - T_k(-h v)) / 2h.  For a fixed MFP field
+    the probe temperatures are affine in T0 and the wall temperatures, so these
+    differences have no truncation error; the MFP direction uses a small
+    relative step.  The sum can cancel (mismatches of both signs), so the
+    error is held to 2e-3 of the sum of the magnitudes of its terms."""
+    from paper_1911_00180_amd.autodiff import ProbeSeries
+    from paper_1911_00180_amd.lattice import Lattice
+    n, mfp, tgt, T0, probes = inputs.inverse_problem(2048)
+    lat = Lattice(n, n, 128, mfp=16.0, x_edge="blackbody", y_edge="periodic")
+    series = ProbeSeries(lat, probes, 200, 10, checkpoint_every=20)
+    dev = "cuda"
+    walls = torch.tensor([0.5, 0.0, 0.0, 0.0], device=dev)
+    with torch.no_grad():
+        target = series(torch.from_numpy(tgt).to(dev), torch.from_numpy(T0).to(dev), walls)
+
+    def probes_of(m, t, w):
+        with torch.no_grad():
+            return series(m, t, w).double()
+
+    m = torch.from_numpy(mfp).to(dev).requires_grad_(True)
+    t = torch.from_numpy(T0).to(dev).requires_grad_(True)
+    w = walls.clone().requires_grad_(True)
+    out = series(m, t, w)
+    loss = ((out - target) ** 2).sum()
+    assert float(loss.detach()) > 0
+    loss.backward()
+    resid = 2.0 * (out.detach().double() - target.double())
+    v = torch.from_numpy(inputs.smooth_lognormal_field(n, n, 7, 64.0, 1.0, 1.0, 0.1, 10.0)
+                         .astype(np.float32)).to(dev)
+    v = v / v.abs().max()
+    e0 = torch.zeros(4, device=dev)
+    e0[0] = 1.0
+    checks = [("mfp", 0, m.grad, v * torch.from_numpy(mfp).to(dev), 1e-3),
+              ("T0", 1, t.grad, v, 1e-2),
+              ("wall 0", 2, w.grad, e0, 1e-2)]
+    for name, k, g, d, h in checks:
+        args_p = [x.detach() for x in (m, t, w)]
+        args_m = [x.detach() for x in (m, t, w)]
+        args_p[k] = args_p[k] + h * d
+        args_m[k] = args_m[k] - h * d
+        dout = (probes_of(*args_p) - probes_of(*args_m)) / (2 * h)
+        fd = float((resid * dout).sum())
+        scale = float((resid * dout).abs().sum())
+        an = float((g.double() * d.double()).sum())
+        print(f"{name}: adjoint {an:.6e}  central difference {fd:.6e}  scale {scale:.6e}")
+        assert scale > 0
+        assert abs(an - fd) <= 2e-3 * scale
+    lat.close()
+    del series, out, loss
+    torch.cuda.empty_cache()

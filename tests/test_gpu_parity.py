@@ -268,6 +268,57 @@ def test_full_size_1024_energy_and_sampled_cells():
         assert abs(T[sy, sx] - want) <= RTOL * max(T0.max(), 1e-30), (sx, sy)
 
 
+def _window(s, half, n, walled):
+    """Cells of the oracle window around coordinate s on an axis of n cells,
+    and that window's edge type: a periodic window when no wall is within
+    reach, else one that starts or ends at the lattice's own wall (its other
+    edge lies outside the region that can influence the sample)."""
+    if walled and s <= half:
+        return np.arange(0, s + half + 1), "lo"
+    if walled and s >= n - 1 - half:
+        return np.arange(s - half, n), "hi"
+    return np.arange(s - half, s + half + 1) % n, None
+
+
+def test_full_size_4096_q256_walls_sampled_cells():
+    """4096 x 4096, Q = 256, Kn = 10 (MFP 40960 cells), blackbody x walls at
+    T = 1 and 0, diffuse y walls, as the large benchmark runs it (single steps,
+    the library's default direction split), from a random initial field:
+    sampled cells after n steps, at the corners, along each wall and inside,
+    equal the oracle run on the window that can influence them.  A window
+    that reaches a wall ends at that wall; its far edge (a wall of the same
+    kind, or a periodic wrap) is more than n cells from the sample."""
+    nx = ny = 4096
+    q, n, mfp = 256, 40, 40960.0
+    walls = dict(x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0, t_x_hi=0.0)
+    T0 = inputs.random_temperature(11, ny, nx)
+    lat = _lattice(nx=nx, ny=ny, q=q, mfp=mfp, **walls)
+    lat.set_temperature(torch.from_numpy(T0))
+    lat.step(n)
+    T = lat.temperature().cpu().numpy()
+    lat.close()
+    assert np.isfinite(T).all()
+    half = n + 2
+    rng = np.random.default_rng(12)
+    samples = [(0, 0), (1, 2), (nx - 1, ny - 1), (nx - 3, ny - 2), (2000, 0), (1500, ny - 1),
+               (0, 2222), (nx - 1, 77), (5, 3000), (nx - 8, 1234), (30, 20)]
+    samples += [tuple(int(v) for v in rng.integers(0, nx, 2)) for _ in range(2)]
+    for (sx, sy) in samples:
+        xs, wx = _window(sx, half, nx, True)
+        ys, wy = _window(sy, half, ny, True)
+        win = T0[np.ix_(ys, xs)].astype(np.float64)
+        kw = dict(x_edge="blackbody" if wx else "periodic",
+                  y_edge="diffuse" if wy else "periodic",
+                  t_x_lo=1.0, t_x_hi=0.0)
+        ora = _oracle(xs.size, ys.size, q, mfp, **kw)
+        ora.set_temperature(win)
+        ora.run(n)
+        cx = int(np.nonzero(xs == sx)[0][0])
+        cy = int(np.nonzero(ys == sy)[0][0])
+        want = ora.temperature()[cy, cx]
+        assert abs(T[sy, sx] - want) <= RTOL * 1.0, (sx, sy, T[sy, sx], want)
+
+
 @pytest.mark.parametrize("kn", [0.1, 10.0])
 def test_crop_256_q64_4000_steps(kn):
     """The 256 x 256 periodic crop of the benchmarked workload (Q = 64 evenly
