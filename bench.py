@@ -73,7 +73,7 @@ def recorded_traffic(path=TRAFFIC_FILE, sources=STEP_SOURCES):
         return None
 
 
-def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1):
+def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1, block_rows=None):
     import numpy as np
     import torch
 
@@ -85,6 +85,8 @@ def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1):
     lat = Lattice(nx, ny, q, mfp=mfp, device="cuda:0", dir_split=split, step_fusion=fusion,
                   **edges)
     lat.set_temperature(torch.from_numpy(T0))
+    for k, rows in (block_rows or {}).items():
+        lat.set_block_rows(k, rows)
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -299,6 +301,9 @@ def main():
                     help="same as --steps-per-launch 1")
     ap.add_argument("--film-steps", type=int, default=10000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--block-rows", default="",
+                    help="fixed block heights of the multi-step kernels instead of the "
+                         "library's timing, as K:R pairs, e.g. 4:9,3:8 (for profiling runs)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="only run a device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -333,8 +338,12 @@ def main():
     if args.steps % 240 % spl or args.steps % spl:
         sys.exit(f"bench.py: --steps must split into launches of {spl} steps "
                  "within 240-step schedule chunks")
+    fixed_rows = {}
+    for item in filter(None, args.block_rows.split(",")):
+        k, rows = (int(v) for v in item.split(":"))
+        fixed_rows[k] = rows
     ms, wall, energy = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.split,
-                               fusion=spl if spl > 1 else 0)
+                               fusion=spl if spl > 1 else 0, block_rows=fixed_rows)
     updates = nx * ny * q * args.steps
     gups = updates / (ms * 1e-3) / 1e9
     ms_step = ms / args.steps
@@ -394,7 +403,7 @@ def main():
     out["fewer_steps_per_launch"] = {}
     for k in range(1, spl):
         msk, _, _ = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.split,
-                            fusion=k if k > 1 else 0)
+                            fusion=k if k > 1 else 0, block_rows=fixed_rows)
         stk = msk / args.steps
         ak = alg_bytes_launch / (stk * k * 1e-3) / 1e9
         out["fewer_steps_per_launch"][str(k)] = {

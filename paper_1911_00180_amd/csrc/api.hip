@@ -52,9 +52,15 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Byte offsets of the workspace regions.
 struct Carve {
-  size_t e[2], E[2], Wf, Wraw, qsx, qsy, partials, totals, flag, sched, wtab, sxtab, sytab, mtab,
-      total;
+  size_t e[2], E[2], Wf, Wraw, qsx, qsy, partials, totals, flag, sched, pulls, wtab, sxtab, sytab,
+      mtab, total;
 };
+
+// Lattices that the multi-step kernels can advance (both edges periodic).
+bool fusable(const wlbm_params& p) {
+  return p.x_edge == WLBM_EDGE_PERIODIC && p.y_edge == WLBM_EDGE_PERIODIC &&
+         fused_supported(p.q, p.nx, p.ny);
+}
 
 int chunk_steps(const wlbm_params& p) { return p.sched_chunk ? p.sched_chunk : kDefaultChunk; }
 
@@ -80,6 +86,9 @@ Carve carve(const wlbm_params& p) {
   c.totals = take(4 * sizeof(double));
   c.flag = take(sizeof(int));
   c.sched = take(size_t(2) * chunk_steps(p) * size_t(p.q));
+  // per step, the multi-step kernels' pull offsets and selection-table
+  // offsets of every direction (FusedArgs::pulls, FusedArgs::sels)
+  c.pulls = take(fusable(p) ? size_t(4) * chunk_steps(p) * size_t(p.q) * sizeof(uint32_t) : 0);
   c.wtab = take(size_t(p.q) * sizeof(float));
   c.sxtab = take(size_t(p.q) * sizeof(float));
   c.sytab = take(size_t(p.q) * sizeof(float));
@@ -211,6 +220,7 @@ struct wlbm_lattice {
   RowTuner tuner[2][5];
   hipEvent_t tev[2] = {nullptr, nullptr};   // timing events of those launches
   uint8_t* pinned[2] = {nullptr, nullptr};
+  uint32_t* pinned_pulls[2] = {nullptr, nullptr};   // staging of the pull offsets
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_pending[2] = {false, false};
   int64_t chunk_counter = 0;
@@ -465,6 +475,7 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
   auto cleanup = [&](wlbm_status s) {
     for (int k = 0; k < 2; ++k) {
       if (l->pinned[k]) (void)hipHostFree(l->pinned[k]);
+      if (l->pinned_pulls[k]) (void)hipHostFree(l->pinned_pulls[k]);
       if (l->ev[k]) (void)hipEventDestroy(l->ev[k]);
       if (l->tev[k]) (void)hipEventDestroy(l->tev[k]);
     }
@@ -474,6 +485,9 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
   const size_t stage = std::max<size_t>(size_t(l->chunk) * p->q, 4 * size_t(p->q) * sizeof(float));
   for (int k = 0; k < 2; ++k) {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&l->pinned[k]), stage, hipHostMallocDefault);
+    if (e == hipSuccess && fusable(*p))
+      e = hipHostMalloc(reinterpret_cast<void**>(&l->pinned_pulls[k]),
+                        size_t(2) * l->chunk * p->q * sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
       wlbm_status s = fail(WLBM_ENOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
       return cleanup(s);
@@ -726,6 +740,9 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
     // Build the schedule rows of this chunk (Sec. 2.3, Sec. 2.5) and the
     // per-step sums of inward weights used by diffuse walls.
     uint8_t* rows = l->pinned[slot];
+    // with it, the multi-step kernels' first-step pull offsets (FusedArgs::pulls)
+    uint32_t* pw = fuse ? l->pinned_pulls[slot] : nullptr;
+    const uint32_t pitch4 = uint32_t(l->g.pitch) * 4u, plane4 = uint32_t(l->g.plane) * 4u;
     insums.assign(size_t(cnt) * 4, 0.f);
     for (int j = 0; j < cnt; ++j) {
       tas_advance(l->dirs, l->tas, dx.data(), dy.data(), hop.data());
@@ -733,6 +750,12 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
       double lo_h = 0, lo_a = 0, hi_h = 0, hi_a = 0;
       for (int i = 0; i < q; ++i) {
         rows[size_t(j) * q + i] = pack_code(dx[i], dy[i], hop[i]);
+        if (pw) {
+          const int hx = hop[i] ? dx[i] : 0, hy = hop[i] ? dy[i] : 0;
+          pw[size_t(2 * j) * q + i] =
+              uint32_t(1 - hy) * pitch4 + uint32_t(4 * (1 - hx)) + uint32_t(i % 8) * plane4;
+          pw[size_t(2 * j + 1) * q + i] = uint32_t(rows[size_t(j) * q + i]) * kSelEntryBytes;
+        }
         if (dy[i] == 1) {
           lo_a += l->dirs.w[i];
           if (hop[i]) lo_h += l->dirs.w[i];
@@ -747,7 +770,12 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
       insums[4 * j + 3] = float(hi_a);
     }
     uint8_t* dev_rows = reinterpret_cast<uint8_t*>(l->ws + l->c.sched) + size_t(slot) * l->chunk * q;
+    uint32_t* dev_pulls =
+        reinterpret_cast<uint32_t*>(l->ws + l->c.pulls) + size_t(2 * slot) * l->chunk * q;
     hipError_t e = hipMemcpyAsync(dev_rows, rows, size_t(cnt) * q, hipMemcpyHostToDevice, l->stream);
+    if (e == hipSuccess && pw)
+      e = hipMemcpyAsync(dev_pulls, pw, size_t(2 * cnt) * q * sizeof(uint32_t),
+                         hipMemcpyHostToDevice, l->stream);
     if (e == hipSuccess) e = hipEventRecord(l->ev[slot], l->stream);
     if (e != hipSuccess) {
       l->broken = true;
@@ -768,8 +796,8 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
         a2.E_in = l->ptr(l->c.E[l->cur]);
         a2.E_out = l->ptr(l->c.E[1 - l->cur]);
         a2.Wf = a.Wf;
-        for (int m = 0; m < K; ++m)
-          a2.codes[m] = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j + m) * q);
+        a2.pulls = dev_pulls + size_t(2 * j) * q;
+        for (int m = 0; m < K; ++m) a2.sels[m] = dev_pulls + size_t(2 * (j + m) + 1) * q;
         a2.wtab = a.wtab;
         a2.W = a.W;
         a2.nx = a.nx;
@@ -1564,6 +1592,7 @@ wlbm_status wlbm_destroy(wlbm_lattice* l) {
   hipError_t e = hipStreamSynchronize(l->stream);
   for (int k = 0; k < 2; ++k) {
     if (l->pinned[k]) (void)hipHostFree(l->pinned[k]);
+    if (l->pinned_pulls[k]) (void)hipHostFree(l->pinned_pulls[k]);
     if (l->ev[k]) (void)hipEventDestroy(l->ev[k]);
     if (l->tev[k]) (void)hipEventDestroy(l->tev[k]);
   }

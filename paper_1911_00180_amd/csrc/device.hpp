@@ -89,13 +89,22 @@ size_t step_batch_lds_bytes(int q, int split);
 // K = 2, 3 or 4 time steps (n+1 .. n+K) of a lattice with periodic x and y
 // edges in one launch; codes[k] is the schedule row of step n+1+k.  Same
 // results as K launch_step calls.
+// Bytes per schedule code in the multi-step kernels' selection table.
+constexpr uint32_t kSelEntryBytes = 32;
 struct FusedArgs {
   const float* e_in;
   float* e_out;
   const float* E_in;
   float* E_out;
   const float* Wf;
-  const uint32_t* codes[4];
+  // Byte offset of the population that direction i pulls on the launch's
+  // first step, from a cell's row and column, one row and one float up:
+  // (1 - hy) pitch 4 + 4 (1 - hx) + (i mod 8) plane 4, with (hx, hy) the
+  // move on a hop and (0, 0) on a pause.
+  const uint32_t* pulls;
+  // Per step of the launch: direction i's byte offset into the selection
+  // table of the kernel (its schedule code times the table's entry size).
+  const uint32_t* sels[4];
   const float* wtab;
   float W;
   int nx, ny, q, pitch;

@@ -13,14 +13,23 @@
 // step-n populations in HBM, then level l of row r-(l-1) for l = 2 .. K from
 // level l-1, whose rows r-l .. r-l+2 are held in registers, a ring of three
 // rows per level; level K is the output.  The one-cell shifts in x of the
-// pull are lane shifts of a whole wave (DPP wave_shr / wave_shl), so level l
-// is valid on lanes l .. 63-l.  Rows wrap by index arithmetic; columns read
-// the ghost frame of periodic x edges (kGhost columns deep), which must be
-// valid on entry (the caller refreshes it with k_fill_ghosts after other
+// pulled populations are lane shifts of a whole wave (DPP wave_shr /
+// wave_shl), so level l is valid on lanes l .. 63-l; E, which every
+// direction reads at its own move, is read from the wave's own LDS copy of
+// the three E rows at a shifted address.  Step-n rows wrap by comparison as
+// they advance (the pulls of a wrapped row reach the ghost rows); columns
+// read the ghost frame of periodic x edges (kGhost columns deep), which must
+// be valid on entry (the caller refreshes it with k_fill_ghosts after other
 // producers) and which the kernel writes for its output.  E of each row of
 // each level is summed over the waves in LDS in k_step's order (8-direction
 // batch sums in batch order), and every update uses k_step's arithmetic, so
 // one launch gives the same bits as K k_step launches.
+//
+// Scalar work per direction is kept to loads: the host writes, per step and
+// direction, the byte offset of the direction's entry in the selection table
+// and, for the first step, the offset of its pulled population, so the kernel
+// decodes no schedule codes (scalar instruction issue limits this kernel as
+// much as vector issue does).
 #include "device.hpp"
 #include "kernel_common.hpp"
 
@@ -56,17 +65,18 @@ __device__ __forceinline__ float from_upper_lane(float v) {
 }
 // Selections by a direction's move are wave-uniform.  Rather than comparing
 // and selecting on the decoded move in scalar code for every direction and
-// row, the kernel loads the lane masks of the move's code from this table
-// (one scalar load per direction) and selects with bitwise operations.
-// Entry c: the masks for dy, dx (the move) and hy, hx (the move if the code
-// hops, else no move) of code c (dx + 1 | (dy + 1) << 2 | hop << 4), and the
-// byte shift 4 (1 - hx) of a pull's column.
-// Words 0..7 serve the relaxation and the second step, 8..11 the pulls of the
-// first step, so that each use site loads one contiguous run.
-enum SelWord : int {
-  kDyLo, kDyMid, kDxPos, kDxNeg, kHyLo, kHyMid, kHxPos, kHxNeg,
-  kPullHyLo, kPullHyMid, kPullHyHi, kCol4, kSelWords = 16
-};
+// row, the kernel loads the entry of the move's code from this table (one
+// scalar load per direction, at a byte offset the host writes per step and
+// direction) and selects with bitwise operations.  Entry c, for code
+// c = dx + 1 | (dy + 1) << 2 | hop << 4 with (hx, hy) the move on a hop and
+// (0, 0) on a pause: the lane masks of hy = -1, hy = 0, hx > 0 and hx < 0,
+// then, for each iteration slot S, the byte offset of E at (x - dx, rho - dy)
+// in a wave's LDS copy of an E ring, from the lane's own entry in slot 0
+// (rows rho - 1, rho, rho + 1 are in slots S, S + 2, S + 1 mod 3).
+enum SelWord : int { kHyLo, kHyMid, kHxPos, kHxNeg, kEOff0, kEOff1, kEOff2, kSelWords = 8 };
+// Row length (floats) of a wave's private LDS copy of one E row: 64 lanes
+// and one pad either side for the lane shifts.
+constexpr int kERow = 66;
 struct CodeSel {
   uint32_t m[32][kSelWords];
 };
@@ -77,25 +87,27 @@ constexpr CodeSel make_code_sel() {
     const bool hop = (c >> 4) & 1;
     const int hx = hop ? dx : 0, hy = hop ? dy : 0;
     auto m = [](bool b) { return b ? 0xffffffffu : 0u; };
-    t.m[c][kDyLo] = m(dy == -1);
-    t.m[c][kDyMid] = m(dy == 0);
-    t.m[c][kDxPos] = m(dx > 0);
-    t.m[c][kDxNeg] = m(dx < 0);
-    t.m[c][kHyLo] = t.m[c][kPullHyLo] = m(hy == -1);
-    t.m[c][kHyMid] = t.m[c][kPullHyMid] = m(hy == 0);
-    t.m[c][kPullHyHi] = m(hy == 1);
+    t.m[c][kHyLo] = m(hy == -1);
+    t.m[c][kHyMid] = m(hy == 0);
     t.m[c][kHxPos] = m(hx > 0);
     t.m[c][kHxNeg] = m(hx < 0);
-    t.m[c][kCol4] = uint32_t(4 * (1 - hx));
+    for (int S = 0; S < 3; ++S) {
+      const int slot = dy == -1 ? S : (dy == 0 ? (S + 2) % 3 : (S + 1) % 3);
+      t.m[c][kEOff0 + S] = uint32_t(4 * (slot * kERow - dx));
+    }
   }
   return t;
 }
 __constant__ CodeSel kCodeSel = make_code_sel();
+static_assert(kSelWords * 4 == kSelEntryBytes, "selection entry size");
 
-// The selection masks of direction d of a batch whose codes are `words`.
-__device__ __forceinline__ const WLBM_CONST uint32_t* sel_of(const WLBM_CONST uint32_t* tab,
-                                                             const uint32_t* words, int d) {
-  return tab + ((words[d >> 2] >> (8 * (d & 3))) & 31u) * kSelWords;
+// The selection masks of a direction whose entry in the launch's table of
+// selection offsets is `off` (bytes into the table: its code times the
+// entry size).
+__device__ __forceinline__ const WLBM_CONST uint32_t* sel_at(const WLBM_CONST uint32_t* tab,
+                                                             uint32_t off) {
+  return reinterpret_cast<const WLBM_CONST uint32_t*>(reinterpret_cast<const WLBM_CONST char*>(tab) +
+                                                      off);
 }
 __device__ __forceinline__ float bsel(uint32_t m, float a, float b) {
   return __builtin_bit_cast(float, (__builtin_bit_cast(uint32_t, a) & m) |
@@ -129,20 +141,23 @@ struct Ring {
   float En[3];             // step n E (per-cell mode: W E), rows by slot
   float Wn[3];             // step n W (per-cell mode)
   float V[SH];             // step n populations pulled into the next level-1 row
+  uint32_t rb[3];          // byte offsets of the step-n rows, by slot
+  int wn;                  // wrapped index of the newest step-n row loaded
 };
 
 // Issue the loads of level-1 row r: the step-n populations each of this
 // wave's directions pulls (row r - hy, column x - hx) into g.V, and step-n E
 // (and W) of row r + 1 into ring slot SN.  Nothing waits for them here.
 template <int SH, int K, bool WF, int SN>
-__device__ __forceinline__ void issue_row(const FusedArgs& a, Ring<SH, K>& g, int r, int i_begin,
+__device__ __forceinline__ void issue_row(const FusedArgs& a, Ring<SH, K>& g, int i_begin,
                                           uint32_t lcol) {
-  const WLBM_CONST uint32_t* codes1 = row_ptr(a.codes[0]);
-  const WLBM_CONST uint32_t* tab = row_ptr(&kCodeSel.m[0][0]);
+  const WLBM_CONST uint32_t* pulls = row_ptr(a.pulls);
   const long long plane = a.plane;
   const uint32_t plane_bytes = uint32_t(plane * 4);
-  auto row_bytes = [&](int rr) { return uint32_t((wrap_index(rr, a.ny) + 1) * a.pitch * 4); };
-  const uint32_t rb_m = row_bytes(r + 1), rb_0 = row_bytes(r), rb_p = row_bytes(r - 1);
+  // the rows advance by one per call: wrap the newest index by comparison
+  g.wn = g.wn + 1 == a.ny ? 0 : g.wn + 1;
+  g.rb[SN] = uint32_t((g.wn + 1) * a.pitch * 4);
+  const uint32_t rb_m = g.rb[SN], rb_0 = g.rb[(SN + 2) % 3];
   {
     const float Ev = buf_load(make_rsrc(a.E_in, plane_bytes), lcol, rb_m);
     if constexpr (WF) {
@@ -156,18 +171,14 @@ __device__ __forceinline__ void issue_row(const FusedArgs& a, Ring<SH, K>& g, in
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
-    uint32_t words[kMaxGroupPlanes / 4];
+    // one row and one float before the batch: a pull's row r - hy and
+    // column x - hx then sit at the non-negative offset in its table entry
+    // (wrapped row r; rows -1 and ny are the ghost rows)
+    const rsrc_t rs = make_rsrc(a.e_in + (long long)i0 * plane - 1 - a.pitch,
+                                uint32_t((kMaxGroupPlanes * plane + a.pitch + 2) * 4));
 #pragma unroll
-    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes1[(i0 >> 2) + k];
-    // one float before the batch, so that the column shift 4 (1 - hx) >= 0
-    const rsrc_t rs = make_rsrc(a.e_in + (long long)i0 * plane - 1,
-                                uint32_t((kMaxGroupPlanes * plane + 2) * 4));
-#pragma unroll
-    for (int d = 0; d < kMaxGroupPlanes; ++d) {
-      const WLBM_CONST uint32_t* m = sel_of(tab, words, d);
-      const uint32_t rowb = (rb_m & m[kPullHyLo]) | (rb_0 & m[kPullHyMid]) | (rb_p & m[kPullHyHi]);
-      g.V[b0 + d] = buf_load(rs, lcol, uint32_t(d) * plane_bytes + rowb + m[kCol4]);
-    }
+    for (int d = 0; d < kMaxGroupPlanes; ++d)
+      g.V[b0 + d] = buf_load(rs, lcol, rb_0 + pulls[i0 + d]);
   }
 }
 
@@ -192,31 +203,32 @@ __device__ __forceinline__ RowCtx row_ctx(const FusedArgs& a) {
 // from the step-n loads; then the loads of the next row are issued, and E of
 // row r is summed.  Step-n slots: rows r-1, r, r+1 are S, S+1, S+2 (mod 3).
 template <int NW, int SH, int K, bool WF, int S>
-__device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float* sP, int t,
-                                       int y0, int lane, int part, uint32_t lcol) {
+__device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float* sP, float* eR,
+                                       int t, int y0, int lane, int part, uint32_t lcol) {
   constexpr int S1 = (S + 1) % 3, S2 = (S + 2) % 3;
   constexpr int NB = NW * SH / kMaxGroupPlanes;   // batches of 8 directions
   const RowCtx c = row_ctx(a);
-  const WLBM_CONST uint32_t* codes = row_ptr(a.codes[0]);
-  const int r = y0 - (K - 1) + t;
+  const WLBM_CONST uint32_t* sels = row_ptr(a.sels[0]);
   const int i_begin = part * SH;
   float* p1 = sP + (t & 1) * NB * 64;
+  // step-n E of row r + 1 (loaded during the previous iteration) into this
+  // wave's LDS copy; rows r - 1 and r are there already
+  eR[S2 * kERow + 1 + lane] = g.En[S2];
+  __builtin_amdgcn_wave_barrier();
+  const float* eLane0 = eR + 1 + lane;
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
     float bsum = 0.f;
-    uint32_t words[kMaxGroupPlanes / 4];
-#pragma unroll
-    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes[(i0 >> 2) + k];
 #pragma unroll
     for (int d = 0; d < kMaxGroupPlanes; ++d) {
       const int i = i0 + d;
-      const WLBM_CONST uint32_t* m = sel_of(c.tab, words, d);
+      const WLBM_CONST uint32_t* m = sel_at(c.tab, sels[i0 + d]);
       const float wi = c.wtab[i];
       const float e = g.V[b0 + d];
       // source rows r - dy: dy = -1 -> slot S2, 0 -> S1, 1 -> S
-      const float Es = at_minus(pick3m(g.En[S2], g.En[S1], g.En[S], m[kDyLo], m[kDyMid]),
-                                m[kDxPos], m[kDxNeg]);
+      const float Es = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(eLane0) +
+                                                       int(m[kEOff0 + S2]));
       float out;
       if constexpr (!WF) {
         out = fmaf(a.W, fmaf(wi, Es, -e), e);
@@ -235,13 +247,16 @@ __device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float
   if constexpr (WF) g.W[0][S] = g.Wn[S1];
   const float Wrow = WF ? g.Wn[S1] : 1.f;
   // loads of the next level-1 row (its step-n row r + 2 goes to slot S)
-  if (t + 1 < a.rows + 2 * (K - 1)) issue_row<SH, K, WF, S>(a, g, r + 1, i_begin, lcol);
+  if (t + 1 < a.rows + 2 * (K - 1)) issue_row<SH, K, WF, S>(a, g, i_begin, lcol);
   // E of row r: the batch sums in batch order, as k_step adds them
   lds_barrier();
   float E = 0.f;
 #pragma unroll
   for (int k = 0; k < NB; ++k) E += p1[k * 64 + lane];
   g.E[0][S] = WF ? E * Wrow : E;
+  // this wave's LDS copy of the row, read with lane shifts by the next level
+  eR[(3 + S) * kERow + 1 + lane] = g.E[0][S];
+  __builtin_amdgcn_wave_barrier();
 }
 
 // The relaxation of level L (2 .. K) at one cell from level L-1: rows
@@ -249,15 +264,16 @@ __device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float
 // t-2, t-1, t).
 template <int SH, int K, bool WF, int L, int S>
 __device__ __forceinline__ float relax_up(const FusedArgs& a, const Ring<SH, K>& g,
-                                          const WLBM_CONST uint32_t* m, float wi, int j) {
+                                          const WLBM_CONST uint32_t* m, float wi, int j,
+                                          const float* eLane) {
   constexpr int S1 = (S + 1) % 3, S2 = (S + 2) % 3;
   constexpr int P = L - 2;   // ring index of level L-1
   // source rows rho - dy: dy = -1 -> slot S, 0 -> S2, 1 -> S1
   const float e = at_minus(pick3m(g.X[P][S][j], g.X[P][S2][j], g.X[P][S1][j], m[kHyLo],
                                   m[kHyMid]),
                            m[kHxPos], m[kHxNeg]);
-  const float Es = at_minus(pick3m(g.E[P][S], g.E[P][S2], g.E[P][S1], m[kDyLo], m[kDyMid]),
-                            m[kDxPos], m[kDxNeg]);
+  const float Es = *reinterpret_cast<const float*>(reinterpret_cast<const char*>(eLane) +
+                                                   int(m[kEOff0 + S]));
   if constexpr (!WF) {
     return fmaf(a.W, fmaf(wi, Es, -e), e);
   } else {
@@ -270,25 +286,22 @@ __device__ __forceinline__ float relax_up(const FusedArgs& a, const Ring<SH, K>&
 // An intermediate level L (2 .. K-1) at iteration t: row r - (L-1) into ring
 // slot S of level L, and its E.
 template <int NW, int SH, int K, bool WF, int L, int S>
-__device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, float* sP, int t,
-                                          int lane, int part) {
+__device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, float* sP,
+                                          float* eR, int t, int lane, int part) {
   constexpr int S2 = (S + 2) % 3;
   constexpr int NB = NW * SH / kMaxGroupPlanes;
   const RowCtx c = row_ctx(a);
-  const WLBM_CONST uint32_t* codes = row_ptr(a.codes[L - 1]);
+  const WLBM_CONST uint32_t* sels = row_ptr(a.sels[L - 1]);
   const int i_begin = part * SH;
   float* pl = sP + (2 * (L - 1) + (t & 1)) * NB * 64;
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
     float bsum = 0.f;
-    uint32_t words[kMaxGroupPlanes / 4];
-#pragma unroll
-    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes[(i0 >> 2) + k];
 #pragma unroll
     for (int d = 0; d < kMaxGroupPlanes; ++d) {
-      const float out = relax_up<SH, K, WF, L, S>(a, g, sel_of(c.tab, words, d), c.wtab[i0 + d],
-                                                  b0 + d);
+      const float out = relax_up<SH, K, WF, L, S>(a, g, sel_at(c.tab, sels[i0 + d]), c.wtab[i0 + d],
+                                                  b0 + d, eR + (L - 1) * 3 * kERow + 1 + lane);
       g.X[L - 1][S][b0 + d] = out;
       bsum += out;
     }
@@ -301,16 +314,19 @@ __device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, fl
 #pragma unroll
   for (int k = 0; k < NB; ++k) E += pl[k * 64 + lane];
   g.E[L - 1][S] = WF ? E * g.W[L - 1][S] : E;
+  eR[(L * 3 + S) * kERow + 1 + lane] = g.E[L - 1][S];
+  __builtin_amdgcn_wave_barrier();
 }
 
 // The output level K at iteration t: row ro = r - (K-1), stored with its
 // ghost copies.
 template <int NW, int SH, int K, bool WF, int S>
-__device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, float* sP, int t,
-                                          int x0, int y0, int lane, int part, bool out_lane) {
+__device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, float* sP,
+                                          const float* eR, int t, int x0, int y0, int lane,
+                                          int part, bool out_lane) {
   constexpr int NB = NW * SH / kMaxGroupPlanes;
   const RowCtx c = row_ctx(a);
-  const WLBM_CONST uint32_t* codes = row_ptr(a.codes[K - 1]);
+  const WLBM_CONST uint32_t* sels = row_ptr(a.sels[K - 1]);
   const int ny = a.ny, pitch = a.pitch, nx = a.nx;
   const long long plane = a.plane;
   const int i_begin = part * SH;
@@ -339,16 +355,13 @@ __device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, fl
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
     float bsum = 0.f;
-    uint32_t words[kMaxGroupPlanes / 4];
-#pragma unroll
-    for (int k = 0; k < kMaxGroupPlanes / 4; ++k) words[k] = codes[(i0 >> 2) + k];
     const rsrc_t ro_rs = make_rsrc(a.e_out + (long long)i0 * plane,
                                    uint32_t(kMaxGroupPlanes * plane * 4));
     float o[kMaxGroupPlanes];
 #pragma unroll
     for (int d = 0; d < kMaxGroupPlanes; ++d) {
-      const float out = relax_up<SH, K, WF, K, S>(a, g, sel_of(c.tab, words, d), c.wtab[i0 + d],
-                                                  b0 + d);
+      const float out = relax_up<SH, K, WF, K, S>(a, g, sel_at(c.tab, sels[i0 + d]), c.wtab[i0 + d],
+                                                  b0 + d, eR + (K - 1) * 3 * kERow + 1 + lane);
       bsum += out;
       o[d] = out;
     }
@@ -384,20 +397,20 @@ __device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, fl
 // Iteration t (ring slot S = t mod 3): level 1, then each higher level once
 // the three rows it reads exist.
 template <int NW, int SH, int K, bool WF, int S>
-__device__ __forceinline__ void iteration(const FusedArgs& a, Ring<SH, K>& g, float* sP, int t,
-                                          int x0, int y0, int lane, int part, uint32_t lcol,
-                                          bool out_lane) {
-  level1<NW, SH, K, WF, S>(a, g, sP, t, y0, lane, part, lcol);
+__device__ __forceinline__ void iteration(const FusedArgs& a, Ring<SH, K>& g, float* sP,
+                                          float* eR, int t, int x0, int y0, int lane, int part,
+                                          uint32_t lcol, bool out_lane) {
+  level1<NW, SH, K, WF, S>(a, g, sP, eR, t, y0, lane, part, lcol);
   if constexpr (K >= 3) {
     if (t < 2) return;
-    level_mid<NW, SH, K, WF, 2, S>(a, g, sP, t, lane, part);
+    level_mid<NW, SH, K, WF, 2, S>(a, g, sP, eR, t, lane, part);
   }
   if constexpr (K >= 4) {
     if (t < 4) return;
-    level_mid<NW, SH, K, WF, 3, S>(a, g, sP, t, lane, part);
+    level_mid<NW, SH, K, WF, 3, S>(a, g, sP, eR, t, lane, part);
   }
   if (t < 2 * (K - 1)) return;
-  level_out<NW, SH, K, WF, S>(a, g, sP, t, x0, y0, lane, part, out_lane);
+  level_out<NW, SH, K, WF, S>(a, g, sP, eR, t, x0, y0, lane, part, out_lane);
 }
 
 // Ghost frame of a periodic lattice written by another producer (k_step
@@ -432,6 +445,8 @@ template <int NW, int SH, bool WF, int K>
 __global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
   // E batch sums: [level 1 .. K][row parity][batch of 8 directions][lane]
   __shared__ float sP[2 * K * (NW * SH / kMaxGroupPlanes) * 64];
+  // each wave's own copy of the E rings: step n, then levels 1 .. K-1
+  __shared__ float sEr[NW][K * 3 * kERow];
   const int lane = threadIdx.x & 63;
   const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int b = xcd_tile(blockIdx.x, gridDim.x);
@@ -453,6 +468,7 @@ __global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
 #pragma unroll
   for (int k = 0; k < 2; ++k) {
     const uint32_t rb = uint32_t((wrap_index(r0 - 1 + k, a.ny) + 1) * a.pitch * 4);
+    g.rb[k] = rb;
     const float Ev = buf_load(make_rsrc(a.E_in, plane_bytes), lcol, rb);
     if constexpr (WF) {
       const float Wv = buf_load(make_rsrc(a.Wf, plane_bytes), lcol, rb);
@@ -462,13 +478,20 @@ __global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
       g.En[k] = Ev;
     }
   }
-  issue_row<SH, K, WF, 2>(a, g, r0, part * SH, lcol);
+  float* eR = sEr[part];
+  // the pads either side of each row (read only by lanes whose results are
+  // never used) hold zero
+  if (lane < 3 * K) eR[lane * kERow] = eR[lane * kERow + kERow - 1] = 0.f;
+  eR[1 + lane] = g.En[0];
+  eR[kERow + 1 + lane] = g.En[1];
+  g.wn = wrap_index(r0, a.ny);
+  issue_row<SH, K, WF, 2>(a, g, part * SH, lcol);
   // a.rows + 2 (K - 1) is a multiple of 3 (the loop is unrolled by three)
   const int T = a.rows + 2 * (K - 1);
   for (int t = 0; t < T; t += 3) {
-    iteration<NW, SH, K, WF, 0>(a, g, sP, t, x0, y0, lane, part, lcol, out_lane);
-    iteration<NW, SH, K, WF, 1>(a, g, sP, t + 1, x0, y0, lane, part, lcol, out_lane);
-    iteration<NW, SH, K, WF, 2>(a, g, sP, t + 2, x0, y0, lane, part, lcol, out_lane);
+    iteration<NW, SH, K, WF, 0>(a, g, sP, eR, t, x0, y0, lane, part, lcol, out_lane);
+    iteration<NW, SH, K, WF, 1>(a, g, sP, eR, t + 1, x0, y0, lane, part, lcol, out_lane);
+    iteration<NW, SH, K, WF, 2>(a, g, sP, eR, t + 2, x0, y0, lane, part, lcol, out_lane);
   }
 }
 
