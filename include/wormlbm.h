@@ -93,7 +93,10 @@ typedef struct wlbm_params {
   double t_y_lo, t_y_hi;     /* blackbody temperatures at y = 0 and y = ny-1     */
   int32_t dir_split;         /* waves sharing one cell's directions: 0 (auto),   */
                              /* 1, 2 or 4; q must be a multiple of 8*dir_split   */
-  int32_t sched_chunk;       /* steps per schedule upload: 0 (auto) or 16..65536 */
+  int32_t sched_chunk;       /* steps per schedule upload: 0 (auto) or 16..65536; */
+                             /* the workspace holds two chunks of q bytes per    */
+                             /* step, and of 2 q 32-bit words per step when the  */
+                             /* multi-step kernels apply (both edges periodic)   */
   double y_specularity;      /* diffuse y walls: fraction p in [0, 1] of what    */
                              /* crosses them that is reflected specularly        */
                              /* (Eq. adiabatic-specular); 1 - p is scattered     */
