@@ -172,3 +172,34 @@ def test_fixed_block_heights():
     with pytest.raises(W.WormLBMError):
         b.set_block_rows(5, 3)
     b.close()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_fused_random_shapes(seed):
+    """Seeded random lattices (nx 8 .. 300, ny 2 .. 90, Q from 8 to 128,
+    either direction set, uniform or per-cell MFP, random schedule chunk and
+    step counts): any number of steps per launch gives the bits of single
+    steps."""
+    rng = np.random.default_rng(1000 + seed)
+    nx = int(rng.integers(8, 301))
+    ny = int(rng.integers(2, 91))
+    q = int(rng.choice([8, 16, 24, 32, 48, 64, 80, 96, 112, 128]))
+    kind = "ring" if rng.random() < 0.3 else "uniform"
+    fusion = int(rng.integers(1, 5))
+    chunk = int(rng.integers(16, 64))
+    a, b = _pair(nx, ny, q, fusion=fusion, mfp=float(rng.uniform(2.0, 50.0)), dirs=kind,
+                 sched_chunk=chunk)
+    if rng.random() < 0.4:
+        mfp = torch.from_numpy(inputs.smooth_lognormal_field(nx, ny, seed, 4.0, 8.0, 0.5, 2.0,
+                                                             40.0).astype(np.float32))
+        a.set_mfp_field(mfp)
+        b.set_mfp_field(mfp)
+    e0 = torch.from_numpy(inputs.random_populations(50 + seed, q, ny, nx))
+    for lat in (a, b):
+        lat.set_populations(e0)
+    for n in rng.integers(1, 40, 3):
+        a.step(int(n))
+        b.step(int(n))
+        assert torch.equal(a.populations(), b.populations()), (nx, ny, q, kind, fusion, chunk, n)
+    a.close()
+    b.close()
