@@ -37,17 +37,14 @@ namespace wlbm {
 namespace {
 
 // Output columns per block (lanes K .. K + kStrip - 1) for K steps per
-// launch.  With two or three steps, 48, a multiple of 16, so that every
-// block's output rows are whole 64-byte write segments (x = 0 starts a
-// 128-byte line): with 60 or 56 columns most rows end in partial segments on
-// both sides, and those partial writes cost more than the idle lanes (two
-// steps at 1024 x 1024, Q = 64: 60 columns 788, 56 columns 851, 48 columns
-// 928, 32 columns 723 G updates/s, 4-row blocks).  With four steps a launch
-// writes half as often per step and does more arithmetic per byte, and the
-// 56 columns the halo leaves are faster (1256 against 1195; with two steps
-// 56 columns cost 10 %).
+// launch: 48, a multiple of 16, so that every block's output rows are whole
+// 64-byte write segments (x = 0 starts a 128-byte line).  With 60 or 56
+// columns most rows end in partial segments on both sides, and those partial
+// writes cost more than the idle lanes (1024 x 1024, Q = 64: four steps per
+// launch 1627 G updates/s with 48 columns against 1490 with 56; three steps
+// 1333 against 1209; two steps 998 against 846).
 template <int K>
-constexpr int kStrip = K == 4 ? 56 : 48;
+constexpr int kStrip = 48;
 // Ghost columns written on each side by every multi-step launch (the most
 // any K reads), so that launches of different K can follow each other.
 constexpr int kGhost = 4;
