@@ -220,9 +220,11 @@ def run_films(steps=10000):
     out = {"workload": "24 films, Nx=512, Q=128, Ny from {32,64,128,256}, Kn 0.01..100, "
                        f"blackbody x 1/0, diffuse y, {steps} steps"}
     stream = torch.cuda.current_stream()
-    for mode in ("batched", "one_by_one"):
+    for mode in ("batched", "batched_no_graphs", "one_by_one"):
         sw = FilmSweep(films)
-        go = sw.step_batched if mode == "batched" else sw.step_each
+        if mode == "batched_no_graphs":
+            sw.batch.set_graphs(False)
+        go = sw.step_each if mode == "one_by_one" else sw.step_batched
         go(20)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -235,6 +237,43 @@ def run_films(steps=10000):
         out[mode + "_gups"] = round(sw.updates_per_step * steps / (ms * 1e-3) / 1e9, 2)
         sw.close()
     out["speedup"] = round(out["one_by_one_ms_per_step"] / out["batched_ms_per_step"], 3)
+    out["graph_speedup"] = round(out["batched_no_graphs_ms_per_step"] / out["batched_ms_per_step"], 3)
+    out.update(run_small_batch())
+    return out
+
+
+def run_small_batch(steps=4800):
+    """A small batch, where per-step launch costs would show most: 24
+    lattices of 64 x 64, Q = 16, blackbody x and diffuse y walls, MFP 4 .. 64
+    cells; graph launches of whole schedule chunks against one launch per
+    step."""
+    import torch
+
+    from paper_1911_00180_amd.lattice import Batch, Lattice
+
+    out = {}
+    stream = torch.cuda.current_stream()
+    for graphs in (True, False):
+        lats = [Lattice(64, 64, 16, mfp=4.0 * 16 ** (j / 23), x_edge="blackbody",
+                        y_edge="diffuse", t_x_lo=1.0, device="cuda:0") for j in range(24)]
+        batch = Batch(lats)
+        batch.set_graphs(graphs)
+        batch.step(480)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        batch.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        key = "small_batch_graphs_us_per_step" if graphs else "small_batch_no_graphs_us_per_step"
+        out[key] = round(e0.elapsed_time(e1) * 1e3 / steps, 3)
+        batch.close()
+        for lat in lats:
+            lat.close()
+    out["small_batch_workload"] = ("24 lattices 64x64, Q=16, blackbody x, diffuse y, "
+                                   f"MFP 4..64, {steps} steps")
+    out["small_batch_graph_speedup"] = round(out["small_batch_no_graphs_us_per_step"] /
+                                             out["small_batch_graphs_us_per_step"], 3)
     return out
 
 

@@ -393,8 +393,17 @@ wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, 
 
 /* Advance every lattice of the batch nsteps steps, as wlbm_step would (their
  * step counts, buffers and flux windows are updated).  Wall temperatures and
- * fields are read from the lattices at each call. */
+ * fields are read from the lattices at each call.  Each whole schedule chunk
+ * (sched_chunk steps, when that is even) with no flux-window step and no
+ * sources runs as one launch of a HIP graph of its per-step launches,
+ * captured on first use for each of the two schedule-ring slots (and again
+ * after a change of split or per-cell field use); the kernels, and the bits,
+ * are those of step-by-step launches. */
 wlbm_status wlbm_batch_step(wlbm_batch* batch, int64_t nsteps);
+
+/* on = 1 (the default): whole chunks run as graph launches as above; on = 0:
+ * one launch per step.  Other values are rejected (WLBM_EINVAL). */
+wlbm_status wlbm_batch_set_graphs(wlbm_batch* batch, int32_t on);
 
 /* Release the batch after waiting for its stream.  NULL is accepted. */
 wlbm_status wlbm_batch_destroy(wlbm_batch* batch);

@@ -270,21 +270,28 @@ struct wlbm_batch {
   std::vector<wlbm_lattice*> lats;
   hipStream_t stream = nullptr;
   char* ws = nullptr;
-  size_t off_args = 0, off_first = 0, off_sched = 0;
+  size_t off_args = 0, off_first = 0, off_sched = 0, off_ins = 0;
   int chunk = 0;
   uint8_t* pinned[2] = {nullptr, nullptr};
+  float* pinned_ins[2] = {nullptr, nullptr};   // staging of the per-step wall sums
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_pending[2] = {false, false};
   int64_t chunk_counter = 0;
   char* table = nullptr;        // pinned staging of the argument table
   hipEvent_t table_ev = nullptr;
   bool table_pending = false;
+  // Full schedule chunks run as one launch of a captured HIP graph per
+  // schedule-ring slot; key: what the graph was captured for.
+  bool use_graphs = true;
+  hipStream_t cap = nullptr;    // private stream the graphs are captured on
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int64_t gkey[2] = {-1, -1};
 };
 
 namespace {
 
 struct BatchCarve {
-  size_t args, first, sched, total;
+  size_t args, first, sched, ins, total;
 };
 
 BatchCarve batch_carve(int n, int q, int chunk) {
@@ -298,6 +305,7 @@ BatchCarve batch_carve(int n, int q, int chunk) {
   c.args = take(size_t(2) * n * sizeof(StepArgs));
   c.first = take(size_t(n + 1) * sizeof(int));
   c.sched = take(size_t(2) * chunk * q);
+  c.ins = take(size_t(2) * chunk * 4 * sizeof(float));
   c.total = off;
   return c;
 }
@@ -1314,13 +1322,18 @@ wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, 
   b->off_args = bc.args;
   b->off_first = bc.first;
   b->off_sched = bc.sched;
+  b->off_ins = bc.ins;
   b->chunk = lats[0]->chunk;
   const size_t stage = size_t(b->chunk) * lats[0]->p.q;
   hipError_t e = hipSuccess;
   for (int k = 0; k < 2 && e == hipSuccess; ++k) {
     e = hipHostMalloc(reinterpret_cast<void**>(&b->pinned[k]), stage, hipHostMallocDefault);
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void**>(&b->pinned_ins[k]),
+                        size_t(b->chunk) * 4 * sizeof(float), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming);
   }
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e == hipSuccess)
     e = hipHostMalloc(reinterpret_cast<void**>(&b->table), bc.first + size_t(n + 1) * sizeof(int),
                       hipHostMallocDefault);
@@ -1402,10 +1415,11 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
   ba.nblocks = first[size_t(n)];
   ba.q = q;
   const int64_t flux_from = l0->flux_window > 0 ? nsteps - l0->flux_window : nsteps;
+  bool has_sources = false;
+  for (wlbm_lattice* l : b->lats) has_sources = has_sources || l->nsrc > 0;
   TasState tas = l0->tas;
   std::vector<int8_t> dx(q), dy(q);
   std::vector<uint8_t> hop(q);
-  std::vector<float> insums;
   int64_t done = 0;
   while (done < nsteps) {
     const int cnt = int(std::min<int64_t>(b->chunk, nsteps - done));
@@ -1417,7 +1431,7 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
       b->ev_pending[slot] = false;
     }
     uint8_t* rows = b->pinned[slot];
-    insums.assign(size_t(cnt) * 4, 0.f);
+    float* insums = b->pinned_ins[slot];
     for (int j = 0; j < cnt; ++j) {
       tas_advance(l0->dirs, tas, dx.data(), dy.data(), hop.data());
       for (wlbm_lattice* l : b->lats) l->book.note(tas);
@@ -1438,19 +1452,68 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
       insums[4 * j + 3] = float(hi_a);
     }
     uint8_t* dev_rows = reinterpret_cast<uint8_t*>(b->ws + b->off_sched) + size_t(slot) * b->chunk * q;
+    float* dev_ins = reinterpret_cast<float*>(b->ws + b->off_ins) + size_t(slot) * b->chunk * 4;
     hipError_t e = hipMemcpyAsync(dev_rows, rows, size_t(cnt) * q, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(dev_ins, insums, size_t(cnt) * 4 * sizeof(float), hipMemcpyHostToDevice,
+                         b->stream);
     if (e == hipSuccess) e = hipEventRecord(b->ev[slot], b->stream);
     if (e != hipSuccess) return fail(WLBM_EHIP, "schedule upload failed: %s", hipGetErrorString(e));
     b->ev_pending[slot] = true;
     ++b->chunk_counter;
+    // A whole chunk with no flux-window step and no sources, starting on an
+    // even step of this call, is one launch of the slot's captured graph:
+    // its kernels read the schedule rows and sums just uploaded, and the
+    // argument table of this call.
+    const bool graph = b->use_graphs && cnt == b->chunk && b->chunk % 2 == 0 &&
+                       done % 2 == 0 && done + cnt <= flux_from && !has_sources;
+    if (graph) {
+      const int64_t key = (int64_t(ba.nblocks) << 8) | (int64_t(l0->split) << 1) |
+                          int64_t(l0->per_cell ? 1 : 0);
+      if (!b->gexec[slot] || b->gkey[slot] != key) {
+        if (b->gexec[slot]) {
+          // the old graph may still be running: let it finish first
+          e = hipStreamSynchronize(b->stream);
+          if (e == hipSuccess) e = hipGraphExecDestroy(b->gexec[slot]);
+          b->gexec[slot] = nullptr;
+          b->gkey[slot] = -1;
+        }
+        hipGraph_t gr = nullptr;
+        if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
+        if (e == hipSuccess) {
+          hipError_t el = hipSuccess;
+          for (int j = 0; j < cnt && el == hipSuccess; ++j) {
+            BatchStepArgs bj = ba;
+            bj.codes = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j) * q);
+            bj.ins = dev_ins + size_t(4) * j;
+            bj.parity = j & 1;
+            bj.q_first = 0;
+            el = launch_step_batch(bj, l0->split, l0->per_cell, false, b->cap);
+          }
+          e = hipStreamEndCapture(b->cap, &gr);
+          if (el != hipSuccess) e = el;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec[slot], gr, nullptr, nullptr, 0);
+        if (gr) (void)hipGraphDestroy(gr);
+        if (e != hipSuccess) {
+          for (wlbm_lattice* l : b->lats) l->broken = true;
+          return fail(WLBM_EHIP, "batch graph capture failed: %s", hipGetErrorString(e));
+        }
+        b->gkey[slot] = key;
+      }
+      e = hipGraphLaunch(b->gexec[slot], b->stream);
+      if (e != hipSuccess) {
+        for (wlbm_lattice* l : b->lats) l->broken = true;
+        return fail(WLBM_EHIP, "batch graph launch failed: %s", hipGetErrorString(e));
+      }
+      done += cnt;
+      continue;
+    }
     for (int j = 0; j < cnt; ++j) {
       const int64_t k = done + j;
       const bool flux = k >= flux_from;
       ba.codes = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j) * q);
-      ba.in_lo_hop = insums[4 * j];
-      ba.in_lo_all = insums[4 * j + 1];
-      ba.in_hi_hop = insums[4 * j + 2];
-      ba.in_hi_all = insums[4 * j + 3];
+      ba.ins = dev_ins + size_t(4) * j;
       ba.parity = int(k & 1);
       ba.q_first = (flux && k == flux_from) ? 1 : 0;
       e = launch_step_batch(ba, l0->split, l0->per_cell, flux, b->stream);
@@ -1476,13 +1539,23 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
   return WLBM_OK;
 }
 
+wlbm_status wlbm_batch_set_graphs(wlbm_batch* b, int32_t on) {
+  if (!b) return fail(WLBM_EINVAL, "batch is NULL");
+  if (on != 0 && on != 1) return fail(WLBM_EINVAL, "on must be 0 or 1");
+  b->use_graphs = on != 0;
+  return WLBM_OK;
+}
+
 wlbm_status wlbm_batch_destroy(wlbm_batch* b) {
   if (!b) return WLBM_OK;
   hipError_t e = hipStreamSynchronize(b->stream);
   for (int k = 0; k < 2; ++k) {
+    if (b->gexec[k]) (void)hipGraphExecDestroy(b->gexec[k]);
     if (b->pinned[k]) (void)hipHostFree(b->pinned[k]);
+    if (b->pinned_ins[k]) (void)hipHostFree(b->pinned_ins[k]);
     if (b->ev[k]) (void)hipEventDestroy(b->ev[k]);
   }
+  if (b->cap) (void)hipStreamDestroy(b->cap);
   if (b->table) (void)hipHostFree(b->table);
   if (b->table_ev) (void)hipEventDestroy(b->table_ev);
   delete b;

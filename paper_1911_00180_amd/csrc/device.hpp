@@ -134,7 +134,10 @@ struct BatchStepArgs {
   const StepArgs* lats;
   const int* first;
   const uint32_t* codes;
-  float in_lo_hop, in_lo_all, in_hi_hop, in_hi_all;
+  // the step's sums of inward weights of diffuse walls: in_lo_hop,
+  // in_lo_all, in_hi_hop, in_hi_all (device memory, uploaded with the
+  // schedule, so that a captured launch reads the values of its step)
+  const float* ins;
   int n, nblocks, parity, q_first;
   int q;
 };

@@ -357,11 +357,12 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
   while (j + 1 < b.n && g >= first[j + 1]) ++j;
   j = __builtin_amdgcn_readfirstlane(j);
   StepArgs a = b.lats[2 * j + b.parity];
+  const WLBM_CONST float* ins = scalar_ptr(b.ins);
   a.codes = b.codes;
-  a.in_lo_hop = b.in_lo_hop;
-  a.in_lo_all = b.in_lo_all;
-  a.in_hi_hop = b.in_hi_hop;
-  a.in_hi_all = b.in_hi_all;
+  a.in_lo_hop = ins[0];
+  a.in_lo_all = ins[1];
+  a.in_hi_hop = ins[2];
+  a.in_hi_all = ins[3];
   a.q_first = b.q_first;
   step_tile<NW, WF, FLUX>(a, g - first[j], sh);
 }

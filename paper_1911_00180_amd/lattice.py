@@ -197,7 +197,8 @@ class Lattice:
 
 class Batch:
     """Lattices advanced together, one kernel launch per step (same q,
-    direction set, step count, split and flux window)."""
+    direction set, step count, split and flux window); whole schedule chunks
+    run as one HIP graph launch unless ``set_graphs(False)``."""
 
     def __init__(self, lattices):
         self.lattices = list(lattices)
@@ -212,6 +213,9 @@ class Batch:
         for lat in self.lattices:
             lat._sync_stream()
         W.wlbm_batch_step(self.handle, n)
+
+    def set_graphs(self, on: bool) -> None:
+        W.wlbm_batch_set_graphs(self.handle, 1 if on else 0)
 
     def close(self) -> None:
         if getattr(self, "handle", None):

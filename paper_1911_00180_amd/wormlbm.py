@@ -42,7 +42,8 @@ EXPORTS = (
     "wlbm_read_probes", "wlbm_adjoint_bytes", "wlbm_adjoint_begin", "wlbm_adjoint_seed",
     "wlbm_adjoint_steps", "wlbm_adjoint_read", "wlbm_adjoint_step_index",
     "wlbm_set_dir_split", "wlbm_get_dir_split", "wlbm_autotune", "wlbm_batch_bytes",
-    "wlbm_batch_create", "wlbm_batch_step", "wlbm_batch_destroy", "wlbm_read_flux_mean",
+    "wlbm_batch_create", "wlbm_batch_step", "wlbm_batch_set_graphs", "wlbm_batch_destroy",
+    "wlbm_read_flux_mean",
     "wlbm_set_sources", "wlbm_flux_distribution", "wlbm_set_speeds",
     "wlbm_accumulate_temperature", "wlbm_get_block_rows", "wlbm_set_block_rows",
 )
@@ -128,6 +129,7 @@ def lib() -> ctypes.CDLL:
         "wlbm_batch_create": (c_int, [POINTER(c_void_p), c_int32, c_void_p, c_size_t, c_void_p,
                                       POINTER(c_void_p)]),
         "wlbm_batch_step": (c_int, [c_void_p, c_int64]),
+        "wlbm_batch_set_graphs": (c_int, [c_void_p, c_int32]),
         "wlbm_batch_destroy": (c_int, [c_void_p]),
         "wlbm_read_flux_mean": (c_int, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double),
                                         POINTER(c_double)]),
@@ -380,6 +382,10 @@ def wlbm_batch_create(handles, d_ws, nbytes: int, stream) -> int:
 
 def wlbm_batch_step(b: int, nsteps: int) -> None:
     _check(lib().wlbm_batch_step(c_void_p(b), nsteps))
+
+
+def wlbm_batch_set_graphs(b: int, on: int) -> None:
+    _check(lib().wlbm_batch_set_graphs(c_void_p(b), on))
 
 
 def wlbm_batch_destroy(b: int) -> None:

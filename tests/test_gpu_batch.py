@@ -134,3 +134,47 @@ def test_film_sweep_full_size_batched_equals_one_by_one():
     assert all(np.isfinite(ka))
     a.close()
     b.close()
+
+
+def test_batch_graph_replays_equal_step_by_step():
+    """Whole schedule chunks replayed as captured HIP graphs give the bits of
+    step-by-step launches and of one-by-one lattices, over repeated replays
+    of both ring slots with eager work between them (reads, new wall
+    temperatures, a per-cell field that makes the batch capture again), and
+    with chunk remainders that shift the buffer parity between calls."""
+    from paper_1911_00180_amd import wormlbm as W
+    from paper_1911_00180_amd.lattice import Batch
+    q = 16
+    kw = dict(sched_chunk=16)
+    sets = [[_make(q, c, 30 + k, **kw) for k, c in enumerate(MIXED)] for _ in range(3)]
+    graphed, eager, single = sets
+    bg, be = Batch(graphed), Batch(eager)
+    be.set_graphs(False)
+    with pytest.raises(W.WormLBMError):
+        W.wlbm_batch_set_graphs(bg.handle, 2)
+    mfp = {id(c): torch.from_numpy(inputs.smooth_lognormal_field(c["nx"], c["ny"], 5, 4.0, 6.0,
+                                                                 0.5, 2.0, 30.0)
+                                   .astype(np.float32)) for c in MIXED}
+    for call, n in enumerate((32, 16, 7, 48, 16, 33, 32)):
+        if call == 3:
+            for lats in sets:
+                for lat, c in zip(lats, MIXED):
+                    lat.set_mfp_field(mfp[id(c)])
+        if call == 5:
+            for lats in sets:
+                for lat in lats:
+                    lat.set_wall_temperatures(0.75, 0.125, 0.5, 0.25)
+        bg.step(n)
+        be.step(n)
+        for lat in single:
+            lat.step(n)
+        for x, y, z in zip(graphed, eager, single):
+            assert x.step_count == y.step_count == z.step_count
+            assert torch.equal(x.populations(), y.populations()), (call, n)
+            assert torch.equal(x.populations(), z.populations()), (call, n)
+            assert torch.equal(x.temperature(), z.temperature()), (call, n)
+    bg.close()
+    be.close()
+    for lats in sets:
+        for lat in lats:
+            lat.close()
