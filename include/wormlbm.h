@@ -374,12 +374,14 @@ wlbm_status wlbm_autotune(wlbm_lattice* lat, void* d_state, size_t bytes, int32_
                           float* ms_by_split, int32_t* chosen);
 
 /* ---- Batches ----------------------------------------------------------------
- * Several lattices with the same q and direction set, at the same step, with
- * the same split, per-cell field use, schedule chunk and flux window, are
- * advanced together: one kernel launch per time step covers the tiles of all
- * of them (the schedule row is shared: it depends only on the directions and
- * the step).  Sizes, edges, wall temperatures and relaxation weights may
- * differ.  Each step gives the same result as wlbm_step on each lattice. */
+ * Several lattices at the same step, with the same split, per-cell field use,
+ * schedule chunk and flux window, are advanced together: one kernel launch
+ * per time step covers the tiles of all of them.  Sizes, edges, wall
+ * temperatures, relaxation weights, q, direction sets and grid speeds may
+ * differ: lattices with the same q, set and speeds share one schedule (it
+ * depends only on the directions and the step), each such group has its own
+ * schedule ring in the batch workspace.  Each step gives the same result as
+ * wlbm_step on each lattice. */
 
 /* Bytes of device workspace for a batch of these n lattices (1 .. 4096). */
 wlbm_status wlbm_batch_bytes(wlbm_lattice* const* lats, int32_t n, size_t* bytes);
@@ -393,7 +395,9 @@ wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, 
 
 /* Advance every lattice of the batch nsteps steps, as wlbm_step would (their
  * step counts, buffers and flux windows are updated).  Wall temperatures and
- * fields are read from the lattices at each call.  Each whole schedule chunk
+ * fields are read from the lattices at each call; a member whose q,
+ * direction set or grid speeds no longer match its group's is refused
+ * (WLBM_EINVAL: create the batch again).  Each whole schedule chunk
  * (sched_chunk steps, when that is even) with no flux-window step and no
  * sources runs as one launch of a HIP graph of its per-step launches,
  * captured on first use for each of the two schedule-ring slots (and again

@@ -133,16 +133,22 @@ bool fused_supported(int q, int nx, int ny);
 struct BatchStepArgs {
   const StepArgs* lats;
   const int* first;
+  // This step's schedule row and sums of inward weights of diffuse walls
+  // (in_lo_hop, in_lo_all, in_hi_hop, in_hi_all), in device memory uploaded
+  // with the schedule, so that a captured launch reads the values of its
+  // step.  With one direction set in the batch: codes and ins.  With several
+  // (grouped launch): lattice j's rings start at ring_codes[j] and
+  // ring_ins[j], and the step is their row `row`.
   const uint32_t* codes;
-  // the step's sums of inward weights of diffuse walls: in_lo_hop,
-  // in_lo_all, in_hi_hop, in_hi_all (device memory, uploaded with the
-  // schedule, so that a captured launch reads the values of its step)
   const float* ins;
+  const uint32_t* const* ring_codes;
+  const float* const* ring_ins;
+  int row;
   int n, nblocks, parity, q_first;
-  int q;
+  int q;   // largest q of the batch (sizes the dynamic LDS)
 };
 hipError_t launch_step_batch(const BatchStepArgs& b, int split, bool per_cell, bool flux,
-                             hipStream_t s);
+                             bool grouped, hipStream_t s);
 
 // e_i = w_i T0 (T0 unpadded [ny][nx]), blackbody walls, E, ghosts.
 hipError_t launch_init_temperature(const Geometry& g, const float* T0, float* e, float* E,

@@ -346,8 +346,10 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 // One time step of several lattices in one launch.  The tiles of lattice j
 // are blocks first[j] .. first[j+1]-1 of the (XCD-remapped) grid; each block
 // reads its lattice's arguments for the current buffer parity from the table
-// through the scalar cache and runs the same tile code as k_step.
-template <int NW, bool WF, bool FLUX>
+// through the scalar cache and runs the same tile code as k_step.  GROUPED:
+// the lattices have several direction sets, each block takes the schedule
+// row of its lattice's ring.
+template <int NW, bool WF, bool FLUX, bool GROUPED>
 __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_step_batch(
     const BatchStepArgs b) {
   __shared__ StepShared<NW, WF, FLUX> sh;
@@ -357,8 +359,14 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
   while (j + 1 < b.n && g >= first[j + 1]) ++j;
   j = __builtin_amdgcn_readfirstlane(j);
   StepArgs a = b.lats[2 * j + b.parity];
-  const WLBM_CONST float* ins = scalar_ptr(b.ins);
-  a.codes = b.codes;
+  const WLBM_CONST float* ins;
+  if constexpr (GROUPED) {
+    a.codes = scalar_ptr(b.ring_codes)[j] + size_t(b.row) * size_t(a.q >> 2);
+    ins = scalar_ptr(scalar_ptr(b.ring_ins)[j]) + 4 * b.row;
+  } else {
+    a.codes = b.codes;
+    ins = scalar_ptr(b.ins);
+  }
   a.in_lo_hop = ins[0];
   a.in_lo_all = ins[1];
   a.in_hi_hop = ins[2];
@@ -631,18 +639,26 @@ int tiles_y_for(int ny, int split) {
   return (ny + ty - 1) / ty;
 }
 
-template <int NW, bool WF, bool FLUX>
+template <int NW, bool WF, bool FLUX, bool GROUPED>
 hipError_t launch_batch_tmpl(const BatchStepArgs& b, hipStream_t s) {
-  hipLaunchKernelGGL((k_step_batch<NW, WF, FLUX>), dim3(b.nblocks), dim3(kBlock),
+  hipLaunchKernelGGL((k_step_batch<NW, WF, FLUX, GROUPED>), dim3(b.nblocks), dim3(kBlock),
                      step_batch_lds_bytes(b.q, NW), s, b);
   return hipGetLastError();
 }
 
-template <int NW>
-hipError_t launch_batch_nw(const BatchStepArgs& b, bool wf, bool fl, hipStream_t s) {
+template <int NW, bool GROUPED>
+hipError_t launch_batch_wf(const BatchStepArgs& b, bool wf, bool fl, hipStream_t s) {
   if (wf)
-    return fl ? launch_batch_tmpl<NW, true, true>(b, s) : launch_batch_tmpl<NW, true, false>(b, s);
-  return fl ? launch_batch_tmpl<NW, false, true>(b, s) : launch_batch_tmpl<NW, false, false>(b, s);
+    return fl ? launch_batch_tmpl<NW, true, true, GROUPED>(b, s)
+              : launch_batch_tmpl<NW, true, false, GROUPED>(b, s);
+  return fl ? launch_batch_tmpl<NW, false, true, GROUPED>(b, s)
+            : launch_batch_tmpl<NW, false, false, GROUPED>(b, s);
+}
+
+template <int NW>
+hipError_t launch_batch_nw(const BatchStepArgs& b, bool wf, bool fl, bool grouped,
+                           hipStream_t s) {
+  return grouped ? launch_batch_wf<NW, true>(b, wf, fl, s) : launch_batch_wf<NW, false>(b, wf, fl, s);
 }
 
 hipError_t launch_step(const StepArgs& a, int split, bool per_cell, bool flux, hipStream_t s) {
@@ -655,11 +671,11 @@ hipError_t launch_step(const StepArgs& a, int split, bool per_cell, bool flux, h
 }
 
 hipError_t launch_step_batch(const BatchStepArgs& b, int split, bool per_cell, bool flux,
-                             hipStream_t s) {
+                             bool grouped, hipStream_t s) {
   switch (split) {
-    case 1: return launch_batch_nw<1>(b, per_cell, flux, s);
-    case 2: return launch_batch_nw<2>(b, per_cell, flux, s);
-    case 4: return launch_batch_nw<4>(b, per_cell, flux, s);
+    case 1: return launch_batch_nw<1>(b, per_cell, flux, grouped, s);
+    case 2: return launch_batch_nw<2>(b, per_cell, flux, grouped, s);
+    case 4: return launch_batch_nw<4>(b, per_cell, flux, grouped, s);
     default: return hipErrorInvalidValue;
   }
 }

@@ -196,9 +196,10 @@ class Lattice:
 
 
 class Batch:
-    """Lattices advanced together, one kernel launch per step (same q,
-    direction set, step count, split and flux window); whole schedule chunks
-    run as one HIP graph launch unless ``set_graphs(False)``."""
+    """Lattices advanced together, one kernel launch per step (same step
+    count, split, per-cell field use and flux window; q, direction sets and
+    grid speeds may differ); whole schedule chunks run as one HIP graph
+    launch unless ``set_graphs(False)``."""
 
     def __init__(self, lattices):
         self.lattices = list(lattices)

@@ -9,8 +9,10 @@ schedule imposes by pausing (Sec. 2.3).  With the linearised gray model each
 band holds the energy c_b T, relaxes towards its own equilibrium, and the
 temperature of the superposition is T = sum_b E_b / sum_b c_b.
 
-Bands with equal grid speeds share the schedule and advance together in one
-batched launch per step; otherwise each band advances on its own.
+With walls, the bands advance together in one batched launch per step
+(bands with equal grid speeds share one schedule, the others have their
+own); on a periodic lattice each band advances on its own, several steps
+per launch.
 """
 from __future__ import annotations
 
@@ -41,8 +43,9 @@ class Multigray:
             if v != 1.0:
                 lat.set_speeds(np.full(q, v))
             self.lattices.append(lat)
-        same = len({v for _, v, _ in self.bands}) == 1
-        self.batch = Batch(self.lattices) if same and len(self.lattices) > 1 else None
+        p = self.lattices[0].params
+        periodic = p.x_edge == 0 and p.y_edge == 0
+        self.batch = Batch(self.lattices) if len(self.lattices) > 1 and not periodic else None
 
     def set_temperature(self, T0) -> None:
         T0 = torch.as_tensor(T0, dtype=torch.float32, device=self.device)

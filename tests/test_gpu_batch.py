@@ -75,11 +75,16 @@ def test_batch_equals_one_by_one(q, split):
 def test_batch_rejects_mismatched_lattices():
     from paper_1911_00180_amd import wormlbm as W
     from paper_1911_00180_amd.lattice import Batch
-    a = _make(16, MIXED[0], 1)
-    b = _make(32, MIXED[1], 2)
+    a = _make(16, MIXED[0], 1, dir_split=1)
+    b = _make(32, MIXED[1], 2, dir_split=2)
     with pytest.raises(W.WormLBMError):
-        Batch([a, b])
-    c = _make(16, MIXED[1], 3)
+        Batch([a, b])          # splits differ
+    b.close()
+    b = _make(16, MIXED[1], 2, dir_split=1)
+    b.set_mfp_field(torch.full((MIXED[1]["ny"], MIXED[1]["nx"]), 7.0))
+    with pytest.raises(W.WormLBMError):
+        Batch([a, b])          # per-cell field use differs
+    c = _make(16, MIXED[1], 3, dir_split=1)
     c.step(1)
     with pytest.raises(W.WormLBMError):
         Batch([a, c])
@@ -178,3 +183,46 @@ def test_batch_graph_replays_equal_step_by_step():
     for lats in sets:
         for lat in lats:
             lat.close()
+
+
+def test_batch_of_different_direction_sets_equals_one_by_one():
+    """Lattices with different Q, direction sets and grid speeds in one
+    batch (each direction set has its own schedule ring; one launch per step
+    covers all of them) give the bits of stepping each lattice alone; a
+    member whose grid speeds change after the batch was made is refused."""
+    from paper_1911_00180_amd import wormlbm as W
+    from paper_1911_00180_amd.lattice import Batch
+    specs = [(16, "uniform", False), (32, "ring", False), (24, "uniform", False),
+             (16, "uniform", True), (48, "ring", False), (16, "uniform", False)]
+    kw = dict(dir_split=1, sched_chunk=16)
+
+    def build(seed0):
+        lats = []
+        for k, (q, kind, slow) in enumerate(specs):
+            lat = _make(q, MIXED[k % len(MIXED)], seed0 + k, dirs=kind, **kw)
+            if slow:
+                lat.set_speeds(np.linspace(0.55, 1.0, q))
+            lats.append(lat)
+        return lats
+
+    a, b = build(60), build(60)
+    batch = Batch(a)
+    for n in (37, 16, 5, 32):
+        batch.step(n)
+        for lat in b:
+            lat.step(n)
+        for x, y in zip(a, b):
+            assert x.step_count == y.step_count
+            assert torch.equal(x.populations(), y.populations()), (x.q, n)
+            assert torch.equal(x.temperature(), y.temperature()), (x.q, n)
+    batch.close()
+    for lat in a + b:
+        lat.close()
+    c = build(70)
+    batch = Batch(c)
+    c[0].set_speeds(np.full(16, 0.8))
+    with pytest.raises(W.WormLBMError):
+        batch.step(1)
+    batch.close()
+    for lat in c:
+        lat.close()

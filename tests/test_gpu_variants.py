@@ -49,33 +49,48 @@ def test_angle_dependent_speeds(q, kind, edges):
     lat.close()
 
 
-def test_speeds_only_at_step_zero_and_batches_need_equal_speeds():
+def test_speeds_only_at_step_zero_and_batches_take_unequal_speeds():
     from paper_1911_00180_amd import wormlbm as W
     from paper_1911_00180_amd.lattice import Batch, Lattice
     a = Lattice(40, 30, 16, mfp=5.0)
     b = Lattice(40, 30, 16, mfp=5.0)
     b.set_speeds(np.full(16, 0.5))
+    a2 = Lattice(40, 30, 16, mfp=5.0)
+    b2 = Lattice(40, 30, 16, mfp=5.0)
+    b2.set_speeds(np.full(16, 0.5))
+    T0 = torch.from_numpy(inputs.random_temperature(3, 30, 40))
+    for lat in (a, b, a2, b2):
+        lat.set_temperature(T0)
+    batch = Batch([a, b])          # two schedules in one launch per step
+    batch.step(21)
+    a2.step(21)
+    b2.step(21)
+    assert torch.equal(a.populations(), a2.populations())
+    assert torch.equal(b.populations(), b2.populations())
+    assert not torch.equal(a.populations(), b.populations())
+    batch.close()
+    for lat in (a, b, a2, b2):
+        lat.close()
+    c = Lattice(40, 30, 16, mfp=5.0)
     with pytest.raises(W.WormLBMError):
-        Batch([a, b])
+        c.set_speeds(np.full(16, 1.5))     # above one cell per step
+    c.step(1)
     with pytest.raises(W.WormLBMError):
-        a.set_speeds(np.full(16, 1.5))
-    a.step(1)
-    with pytest.raises(W.WormLBMError):
-        a.set_speeds(np.full(16, 0.5))
-    a.close()
-    b.close()
+        c.set_speeds(np.full(16, 0.5))     # only at step 0
+    c.close()
 
 
 @pytest.mark.parametrize("speeds", [(1.0, 0.7, 0.4), (1.0, 1.0, 1.0)])
 def test_multigray_superposition(speeds):
     """Three uncoupled bands (heat-capacity shares 0.5 / 0.3 / 0.2, MFPs 4 / 20
-    / 200 cells) against the superposed oracle bands; equal speeds take the
-    batched path."""
+    / 200 cells) against the superposed oracle bands; with the blackbody wall
+    both speed sets take the batched path (unequal speeds as separate
+    schedules in one launch per step)."""
     from paper_1911_00180_amd.multigray import Multigray
     nx, ny, q = 66, 40, 16
     bands = [(0.5, speeds[0], 4.0), (0.3, speeds[1], 20.0), (0.2, speeds[2], 200.0)]
     mg = Multigray(nx, ny, q, bands, x_edge="blackbody", t_x_lo=1.0)
-    assert (mg.batch is not None) == (len(set(speeds)) == 1)
+    assert mg.batch is not None
     T0 = inputs.gaussian_pulse(nx, ny, 6.0, 33, 20).astype(np.float32)
     mg.set_temperature(torch.from_numpy(T0))
     mg.step(45)
