@@ -125,8 +125,9 @@ int fused_row_candidates(int ny, int k, int* cand, int max_cand);
 // 64 or of 16 up to 128, nx >= 8, ny >= 2.
 bool fused_supported(int q, int nx, int ny);
 
-// One time step of n lattices in one launch (same q, direction set and
-// schedule row).  lats holds, for each lattice j, its arguments for buffer
+// One time step of n lattices in one launch (same split, per-cell field use
+// and step; lattices with the same q, direction set and grid speeds share a
+// schedule ring).  lats holds, for each lattice j, its arguments for buffer
 // parity 0 and 1 ([2n], on the device); first[j] is the first block of
 // lattice j, first[n] = nblocks.  The per-step fields of StepArgs (codes,
 // wall sums, q_first) come from here.
