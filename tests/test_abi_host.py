@@ -185,3 +185,11 @@ def test_specularity_validated():
     assert ei.value.status == W.WLBM_EINVAL
     p = W.make_params(16, 16, 16, mfp=8.0, y_edge="diffuse", y_specularity=0.25)
     assert W.wlbm_workspace_bytes(p) > 0
+
+
+def test_batch_entry_points_reject_null_handles_without_the_gpu():
+    for call in (lambda: W.wlbm_batch_step(0, 1), lambda: W.wlbm_batch_set_graphs(0, 1)):
+        with pytest.raises(W.WormLBMError) as ei:
+            call()
+        assert ei.value.status == W.WLBM_EINVAL
+    W.wlbm_batch_destroy(0)     # NULL is accepted
