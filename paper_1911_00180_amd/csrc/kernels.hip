@@ -99,7 +99,9 @@ __device__ __forceinline__ void load_batch(const StepArgs& a, int i0, uint32_t b
 }
 
 // The sweep of one wave over its share of the directions for one cell per
-// lane.  EDGE tiles touch a domain edge or are ragged: they mask cells
+// lane.  XWALL tiles (blackbody x edges) touch only an x edge, hold no
+// ragged lanes and no y-edge rows: they run the interior path plus the
+// blackbody overwrite.  EDGE tiles touch a domain edge or are ragged: they mask cells
 // outside the lattice, apply the wall conditions and write the ghost copies
 // of periodic edges.  Interior tiles need none of that: every source cell of
 // a pull lies inside the padded arrays, with no wrap arithmetic.
@@ -107,7 +109,7 @@ __device__ __forceinline__ void load_batch(const StepArgs& a, int i0, uint32_t b
 // direction split: each batch of D = 8 directions is summed in direction
 // order, then the batch sums are added in batch order (sBat holds them when
 // several waves share a cell).  The multi-step kernels add in the same order.
-template <int NW, bool WF, bool FLUX, bool EDGE>
+template <int NW, bool WF, bool FLUX, bool EDGE, bool XWALL = false>
 __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const float* sW,
                                       const float* sTg, const float* sWTg, float* sRed,
                                       float* sBat, int x0, int y0, uint32_t boff,
@@ -165,7 +167,11 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
         const float Wh = sW[hop ? ls : lc];
         out = e + fmaf(wi, Es, -(Wh * e));
       }
-      if constexpr (EDGE) {
+      if constexpr (XWALL) {
+        out = blackbody(out, wi, x, y, a.nx, a.ny, a.x_edge, a.y_edge, a.t_x_lo, a.t_x_hi,
+                        a.t_y_lo, a.t_y_hi);
+        buf_store_stream(out, ro, boff, d * plane_bytes);
+      } else if constexpr (EDGE) {
         if (!ok) continue;
         if (a.y_edge == kDiffuse) {
           if (y == 0 && dy == 1) out = fmaf(wi, (hop ? sTg : sWTg)[lane + 1 - dx], out);
@@ -317,7 +323,10 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
     if constexpr (WF) sW[k] = wv;
   }
   const bool edge = x0 == 0 || x0 + T::TX >= a.nx || y0 == 0 || y0 + T::TY >= a.ny;
-  if (edge && a.y_edge == kDiffuse) {
+  // only a blackbody x edge, every lane inside and no row on a y edge
+  const bool xwall = edge && a.x_edge == kBlackbody && x0 + T::TX <= a.nx && y0 > 0 &&
+                     y0 + T::TY < a.ny;
+  if (edge && !xwall && a.y_edge == kDiffuse) {
     const bool lo = y0 == 0;
     const bool hi = a.ny - 1 < y0 + T::TY;
     for (int k = threadIdx.x; k < 2 * T::LP; k += kBlock) {
@@ -330,7 +339,9 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
     }
   }
   __syncthreads();
-  if (edge)
+  if (xwall)
+    sweep<NW, WF, FLUX, false, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0);
+  else if (edge)
     sweep<NW, WF, FLUX, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0);
   else
     sweep<NW, WF, FLUX, false>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0);
