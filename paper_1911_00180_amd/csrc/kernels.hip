@@ -26,31 +26,42 @@ namespace {
 // Boundary node of a diffuse wall (Sec. 2.6, Eq. adiabatic-diffuse): the node
 // at column X behind the lo (wall 0, row -1) or hi (wall 1, row ny) wall
 // absorbs the diffuse share 1 - p of what streams into it on this step and
-// re-emits it isotropically, as inward DDEDs w_i T_g.  A direction with an inward pending move delivers
-// w_i T_g on a hop and w_i W_g T_g (its EED part) on a pause; T_g is chosen so
-// that the node emits exactly what it absorbed.  Returns T_g and W_g T_g.
-// The node below/above a blackbody column belongs to the blackbody wall.
+// re-emits it isotropically, as inward DDEDs w_i T_g.  A direction with an
+// inward pending move delivers w_i T_g on a hop and w_i W_g T_g (its EED
+// part) on a pause; T_g is chosen so that the node emits exactly what it
+// absorbed.  The node below/above a blackbody column belongs to the blackbody
+// wall, and nodes outside a blackbody edge emit nothing: for those,
+// node_fixed sets T_g and W_g T_g and returns true; otherwise it wraps X of a
+// periodic edge and returns false.
 template <bool WF>
-__device__ void boundary_node(const StepArgs& a, int wall, int X, float& tg, float& wtg) {
+__device__ __forceinline__ bool node_fixed(const StepArgs& a, int wall, int& X, float& tg,
+                                           float& wtg) {
   const int yrow = wall == 0 ? 0 : a.ny - 1;
-  const int out_dy = wall == 0 ? -1 : 1;
   if (a.x_edge == kBlackbody) {
     if (X < 0 || X >= a.nx) {
       tg = wtg = 0.f;
-      return;
+      return true;
     }
     if (X == 0 || X == a.nx - 1) {
       const float Wg = WF ? a.Wf[cell(X, yrow, a.pitch)] : a.W;
       tg = (1.f - a.spec) * ((X == a.nx - 1) ? a.t_x_hi : a.t_x_lo);
       wtg = Wg * tg;
-      return;
+      return true;
     }
   } else {
     X = ((X % a.nx) + a.nx) % a.nx;
   }
-  const float Wg = WF ? a.Wf[cell(X, yrow, a.pitch)] : a.W;
+  return false;
+}
+
+// What directions i0 .. i1-1 stream into the node at (wrapped) column X on
+// this step, summed in direction order.
+template <bool WF>
+__device__ float node_inflow(const StepArgs& a, int wall, int X, int i0, int i1) {
+  const int yrow = wall == 0 ? 0 : a.ny - 1;
+  const int out_dy = wall == 0 ? -1 : 1;
   float R = 0.f;
-  for (int i = 0; i < a.q; ++i) {
+  for (int i = i0; i < i1; ++i) {
     const uint32_t code = (a.codes[i >> 2] >> (8 * (i & 3))) & 0xffu;
     int dx, dy;
     bool hop;
@@ -64,6 +75,15 @@ __device__ void boundary_node(const StepArgs& a, int wall, int X, float& tg, flo
     if (hop) R += fmaf(-Ws, e, e);
     R = fmaf(Ws * a.wtab[i], a.E_in[o], R);
   }
+  return R;
+}
+
+// T_g and W_g T_g of the node at (wrapped) column X from its inflow R.
+template <bool WF>
+__device__ __forceinline__ void node_emit(const StepArgs& a, int wall, int X, float R, float& tg,
+                                          float& wtg) {
+  const int yrow = wall == 0 ? 0 : a.ny - 1;
+  const float Wg = WF ? a.Wf[cell(X, yrow, a.pitch)] : a.W;
   const float hs = wall == 0 ? a.in_lo_hop : a.in_hi_hop;
   const float as = wall == 0 ? a.in_lo_all : a.in_hi_all;
   const float C = fmaf(Wg, as - hs, hs);
@@ -264,6 +284,9 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
   }
 }
 
+// Threads that share the inflow sum of one diffuse-wall node.
+constexpr int kNodeParts = 3;
+
 // LDS of one block of the step kernel.
 template <int NW, bool WF, bool FLUX>
 struct StepShared {
@@ -272,6 +295,7 @@ struct StepShared {
   float sW[WF ? T::LH * T::LP : 1];
   float sTg[2 * T::LP];
   float sWTg[2 * T::LP];
+  float sInflow[2 * T::LP * kNodeParts];   // partial inflows of diffuse-wall nodes
   float sRed[NW > 1 && FLUX ? 2 * kBlock : 1];
 };
 
@@ -327,13 +351,34 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
   const bool xwall = edge && a.x_edge == kBlackbody && x0 + T::TX <= a.nx && y0 > 0 &&
                      y0 + T::TY < a.ny;
   if (edge && !xwall && a.y_edge == kDiffuse) {
+    // The inflow of each node of the tile's wall rows (and halo) is summed
+    // by kNodeParts threads over consecutive ranges of directions, then the
+    // parts are added in order.
     const bool lo = y0 == 0;
     const bool hi = a.ny - 1 < y0 + T::TY;
+    const int chunk = (a.q + kNodeParts - 1) / kNodeParts;
+    for (int k = threadIdx.x; k < 2 * T::LP * kNodeParts; k += kBlock) {
+      const int node = k / kNodeParts, part = k - node * kNodeParts;
+      const int wall = node / T::LP;
+      if (wall == 0 ? !lo : !hi) continue;
+      int X = x0 - 1 + (node - wall * T::LP);
+      float tg, wtg;
+      if (node_fixed<WF>(a, wall, X, tg, wtg)) continue;
+      const int i0 = part * chunk, i1 = min(a.q, i0 + chunk);
+      sh.sInflow[k] = node_inflow<WF>(a, wall, X, i0, i1);
+    }
+    __syncthreads();
     for (int k = threadIdx.x; k < 2 * T::LP; k += kBlock) {
       const int wall = k / T::LP;
       if (wall == 0 ? !lo : !hi) continue;
+      int X = x0 - 1 + (k - wall * T::LP);
       float tg, wtg;
-      boundary_node<WF>(a, wall, x0 - 1 + (k - wall * T::LP), tg, wtg);
+      if (!node_fixed<WF>(a, wall, X, tg, wtg)) {
+        float R = sh.sInflow[k * kNodeParts];
+#pragma unroll
+        for (int p = 1; p < kNodeParts; ++p) R += sh.sInflow[k * kNodeParts + p];
+        node_emit<WF>(a, wall, X, R, tg, wtg);
+      }
       sTg[k] = tg;
       sWTg[k] = wtg;
     }
