@@ -74,6 +74,10 @@ def recorded_traffic(path=TRAFFIC_FILE, sources=STEP_SOURCES):
 
 
 def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1, block_rows=None):
+    """Time `steps` steps (after `warmup`) of the lattice; with several steps
+    per launch the block height is fixed beforehand (given, or timed by the
+    library's tuner on a saved state that is then restored), so that no
+    tuning happens inside the timed region."""
     import numpy as np
     import torch
 
@@ -87,6 +91,10 @@ def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1, 
     lat.set_temperature(torch.from_numpy(T0))
     for k, rows in (block_rows or {}).items():
         lat.set_block_rows(k, rows)
+    if fusion in (2, 3, 4) and lat.block_rows(fusion) > 0 and fusion not in (block_rows or {}):
+        lat.tune_block_rows(fusion)
+    if fusion in (2, 3, 4) and lat.block_rows(fusion) <= 0:
+        raise SystemExit(f"bench.py: no block height for {fusion} steps per launch")
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -106,6 +114,52 @@ def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1, 
     del lat
     torch.cuda.empty_cache()
     return ms, wall, energy
+
+
+def run_stream_ceiling(sizes, repeats=10):
+    """Read+write stream kernel (libwlbm_probe.so, 16-byte loads and stores)
+    over buffers of the given byte sizes: the best GB/s (bytes read + bytes
+    written per second) over its variants, per size."""
+    import ctypes
+
+    import torch
+
+    path = os.path.join(ROOT, "paper_1911_00180_amd", "libwlbm_probe.so")
+    probe = ctypes.CDLL(path)
+    probe.wlbm_probe_copy.restype = ctypes.c_int
+    probe.wlbm_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+    stream = torch.cuda.current_stream()
+    out = {}
+    for label, nbytes in sizes:
+        nbytes = nbytes // 16 * 16
+        a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        best = None
+        for unroll in (1, 2, 4):
+            for nt in (0, 1):
+                def go():
+                    rc = probe.wlbm_probe_copy(a.data_ptr(), b.data_ptr(), nbytes, unroll, nt,
+                                               stream.cuda_stream)
+                    if rc:
+                        raise RuntimeError(f"stream probe failed: {rc}")
+                go()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(repeats):
+                    go()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                gbs = 2 * nbytes * repeats / (e0.elapsed_time(e1) * 1e-3) / 1e9
+                if best is None or gbs > best[0]:
+                    best = (gbs, unroll, nt)
+        assert torch.equal(a[:1024], b[:1024])
+        out[label] = {"bytes_per_buffer": nbytes, "GBs": round(best[0], 1),
+                      "frac": round(best[0] / HBM_PEAK_GBS, 4),
+                      "unroll": best[1], "nontemporal_stores": bool(best[2])}
+        del a, b
+        torch.cuda.empty_cache()
+    return out
 
 
 def adjoint_bytes_per_update(q: int, per_cell_w: bool = False) -> float:
@@ -220,10 +274,10 @@ def run_films(steps=10000):
     out = {"workload": "24 films, Nx=512, Q=128, Ny from {32,64,128,256}, Kn 0.01..100, "
                        f"blackbody x 1/0, diffuse y, {steps} steps"}
     stream = torch.cuda.current_stream()
-    for mode in ("batched", "batched_no_graphs", "one_by_one"):
+    for mode in ("batched", "batched_graphs", "one_by_one"):
         sw = FilmSweep(films)
-        if mode == "batched_no_graphs":
-            sw.batch.set_graphs(False)
+        if mode == "batched_graphs":
+            sw.batch.set_graphs(True)
         go = sw.step_each if mode == "one_by_one" else sw.step_batched
         go(20)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -237,7 +291,7 @@ def run_films(steps=10000):
         out[mode + "_gups"] = round(sw.updates_per_step * steps / (ms * 1e-3) / 1e9, 2)
         sw.close()
     out["speedup"] = round(out["one_by_one_ms_per_step"] / out["batched_ms_per_step"], 3)
-    out["graph_speedup"] = round(out["batched_no_graphs_ms_per_step"] / out["batched_ms_per_step"], 3)
+    out["graph_speedup"] = round(out["batched_ms_per_step"] / out["batched_graphs_ms_per_step"], 3)
     out.update(run_small_batch())
     return out
 
@@ -328,9 +382,13 @@ def main():
     ap.add_argument("--split", type=int, default=0,
                     help="waves sharing one cell's directions (0 = library default)")
     ap.add_argument("--large", action="store_true",
-                    help="also time the 4096 x 4096, Q = 256 wall-bounded lattice and the "
-                         "2048 x 2048, Q = 128 inverse problem (about 160 GB of checkpoints)")
+                    help="also time the 2048 x 2048, Q = 128 inverse problem (about 160 GB "
+                         "of checkpoints)")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the 4096 x 4096, Q = 256 wall-bounded lattice")
     ap.add_argument("--large-steps", type=int, default=200)
+    ap.add_argument("--no-stream", action="store_true",
+                    help="skip the read+write stream-kernel ceiling")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint measurements")
     ap.add_argument("--no-films", action="store_true", help="skip the batched film sweep")
@@ -387,13 +445,18 @@ def main():
     gups = updates / (ms * 1e-3) / 1e9
     ms_step = ms / args.steps
     bpu = bytes_per_update(q)
-    # Dominant kernel: every population is read once and written once per
-    # launch, so the algorithmic bytes of a launch are those of one time step
-    # however many steps the launch advances.
+    # Dominant kernel: the launch advancing spl steps.  Algorithmic bytes per
+    # launch = the per-update figure (8 + 8/Q B: each population read and
+    # written once per step, E read and written once per cell) times the
+    # updates one launch processes, nx * ny * q * spl.  With several steps per
+    # launch the kernel keeps the intermediate steps on chip, so this rate can
+    # exceed the HBM peak; hbm_frac_one_pass is the share of the peak that
+    # one pass over the arrays per launch (what it actually must move) takes.
     steps_per_launch = spl
     launches = args.steps // steps_per_launch
     ms_launch = ms / launches
-    alg_bytes_launch = bpu * nx * ny * q
+    alg_bytes_launch = bpu * nx * ny * q * steps_per_launch
+    one_pass_bytes = bpu * nx * ny * q
     achieved = alg_bytes_launch / (ms_launch * 1e-3) / 1e9
     traffic = (recorded_traffic(FUSED_TRAFFIC_FILES[spl], FUSED_SOURCES) if spl > 1
                else recorded_traffic())
@@ -430,10 +493,11 @@ def main():
             "launches": launches,
             "ms_per_launch": round(ms_launch, 5),
             "algorithmic_bytes_per_launch": alg_bytes_launch,
-            # bytes a one-step-per-launch path would have to move per step,
-            # per unit time: above the HBM peak when several steps share a
-            # launch's traffic
-            "single_step_equivalent_GBs": round(alg_bytes_launch / (ms_step * 1e-3) / 1e9, 1),
+            "one_pass_bytes_per_launch": one_pass_bytes,
+            "hbm_frac_one_pass": round(one_pass_bytes / (ms_launch * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                       4),
+            "hbm_frac_traffic": (round(traffic / (ms_launch * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                 if traffic else None),
         },
         "wall_s": round(wall, 4),
         "energy_after": energy,
@@ -444,7 +508,7 @@ def main():
         msk, _, _ = run_gpu(nx, ny, q, mfp, args.steps, args.warmup, {}, args.split,
                             fusion=k if k > 1 else 0, block_rows=fixed_rows)
         stk = msk / args.steps
-        ak = alg_bytes_launch / (stk * k * 1e-3) / 1e9
+        ak = bpu * nx * ny * q * k / (stk * k * 1e-3) / 1e9
         out["fewer_steps_per_launch"][str(k)] = {
             "kernel": KERNELS[k],
             "block_rows": run_gpu.block_rows,
@@ -457,22 +521,30 @@ def main():
             "traffic": (recorded_traffic(FUSED_TRAFFIC_FILES[k], FUSED_SOURCES) if k > 1
                         else recorded_traffic()),
         }
-    if args.large:
+    if not args.no_large:
         nl, ql = 4096, 256
         edges = dict(x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0, t_x_hi=0.0)
         msl, walll, _ = run_gpu(nl, nl, ql, 10.0 * nl, args.large_steps, 10, edges)
         st = msl / args.large_steps
         bl = bytes_per_update(ql) * nl * nl * ql
         out["large"] = {
-            "workload": "4096x4096, Q=256, blackbody x walls (T=1/0), diffuse y walls, Kn=10",
+            "workload": "4096x4096, Q=256, blackbody x walls (T=1/0), diffuse y walls, Kn=10 "
+                        "(MFP 40960 cells), Gaussian pulse sigma0=16 at the seeded position",
             "steps": args.large_steps,
             "value": round(nl * nl * ql / (st * 1e-3) / 1e9, 3),
             "unit": "Gupdates/s",
             "ms_per_step": round(st, 4),
+            "steps_per_launch": 1,
+            "bytes_per_update": bytes_per_update(ql),
             "roofline_frac": round(bl / (st * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         }
+    if args.large:
         # the 2048 x 2048, Q = 128 inverse problem, checkpoints sized to HBM
         out["large_adjoint"] = run_adjoint_ratio(n=2048, q=128, steps=1000, K=50, repeats=1)
+    if not args.no_stream:
+        pbytes = 4 * (nx + 64) * (ny + 2) * q
+        out["stream_ceiling"] = run_stream_ceiling(
+            [("1024x1024_q64", pbytes), ("4096x4096_q256", 4 * (4096 + 64) * 4098 * 256)])
     if not args.no_adjoint:
         adj = run_adjoint_ratio()
         adj["kernel"] = run_adjoint_kernel()

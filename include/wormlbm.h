@@ -138,11 +138,19 @@ wlbm_status wlbm_set_stream(wlbm_lattice* lat, void* stream);
 wlbm_status wlbm_set_temperature(wlbm_lattice* lat, const float* d_T0);
 
 /* Set all populations from a device [q][ny][nx] array, then impose the
- * blackbody walls. */
+ * blackbody walls.  The populations are the directional energy densities
+ * (DDEDs) e_i of Sec. 2.2 Eq. discrete-BTE, one per cell and direction; their
+ * sum over i is the cell energy E of Eq. lbm-energy-density.  The array is
+ * read in stream order and stays the caller's. */
 wlbm_status wlbm_set_populations(wlbm_lattice* lat, const float* d_e);
 
 /* Per-cell mean free path in cells (device [ny][nx]); each cell then relaxes
- * with its own corrected weight.  NULL returns to the uniform MFP of the
+ * with its own corrected weight: W = 1/MFP (Sec. 2.2 Eq. W-Kn, with the group
+ * velocity and time step 1), corrected by Eq. W-correction with the
+ * Lambda_corr of Eq. W-correction-factor-gereralized (Sec. 2.4).  The DDED
+ * that stays or hops relaxes with the weight of its source cell, and a cell
+ * emits its EED with its own weight (the paper has a uniform W; this is the
+ * reading taken for a field).  NULL returns to the uniform MFP of the
  * parameters.  Waits for the stream; returns WLBM_EUNSTABLE (and keeps the
  * previous field) if any corrected weight exceeds 1 or is not finite, or if
  * an MFP is not positive. */
@@ -203,7 +211,9 @@ wlbm_status wlbm_read_heat_flux(wlbm_lattice* lat, float* d_qx, float* d_qy, int
 wlbm_status wlbm_read_populations(wlbm_lattice* lat, float* d_e);
 
 /* Totals over the lattice, accumulated in float64 in a fixed order (so the
- * result is reproducible): energy = sum_x T(x), qx_sum and qy_sum = sum_x q(x).
+ * result is reproducible): energy = sum_x T(x), with T = E = sum_i e_i
+ * (Sec. 2.2 Eq. lbm-energy-density, Eq. pseudo-T in the linear gray model),
+ * and qx_sum, qy_sum = sum_x q(x), q = sum_i e_i s_i (Eq. q_corr).
  * Waits for the stream.  WLBM_ENONFINITE if any of them is not finite.
  * Output pointers may be NULL. */
 wlbm_status wlbm_read_totals(wlbm_lattice* lat, double* energy, double* qx_sum, double* qy_sum);
@@ -211,15 +221,18 @@ wlbm_status wlbm_read_totals(wlbm_lattice* lat, double* energy, double* qx_sum, 
 /* Mean heat flux over the columns x0 <= x < x1 and all rows, summed in
  * float64 in a fixed order: of the trailing flux window of the last
  * wlbm_step call (averaged = 1; WLBM_ESTATE without a complete window) or of
- * the current state (averaged = 0).  Sec. 3.4 takes the in-plane flux of a
- * film from such averages.  Waits for the stream.  Outputs may be NULL. */
+ * the current state (averaged = 0).  Sec. 3.5 takes the in-plane flux of a
+ * film from such averages (over ten steps, as stated in Sec. 3.4).  Waits for the stream.  Outputs may be NULL. */
 wlbm_status wlbm_read_flux_mean(wlbm_lattice* lat, int32_t x0, int32_t x1, int32_t averaged,
                                 double* qx_mean, double* qy_mean);
 
 /* Host-side tables, valid without a GPU (they need only the parameters). */
 
 /* Unit vectors (sx, sy) and weights w of the q directions, host [q] arrays
- * (any may be NULL). */
+ * (any may be NULL): evenly spaced directions with weights 1/Q (Sec. 2.2), or
+ * the D2Q[M x 8] ring set with the angular-gap weights of Sec. 2.4
+ * Eq. weight.  These weights set the equilibrium w_i E of Eq. lbm-energy-
+ * weighting and the imposed DDEDs of every boundary (Sec. 2.6). */
 wlbm_status wlbm_get_directions(const wlbm_params* p, double* sx, double* sy, double* w);
 
 /* Grid-MFP correction Lambda_corr = Q / sum_i c_i (Eq. W-correction-factor-
@@ -347,20 +360,30 @@ wlbm_status wlbm_set_dir_split(wlbm_lattice* lat, int32_t split);
 int32_t wlbm_get_dir_split(const wlbm_lattice* lat);
 
 /* Output rows per block of the kernel that advances k = 2, 3 or 4 steps per
- * launch, for the lattice's current weight mode (uniform or per-cell field).
- * The library picks this height by timing its first multi-step launches of
- * the lattice with each candidate height (two passes of 6 launches per
- * candidate; results do not depend on the height); 0 while it is still doing
- * so or before the first such launch, -1 for NULL or k outside 2 .. 4.
- * The timing synchronizes the stream after each timed sample, so the first
- * multi-step launches of a lattice must not be captured into a HIP graph;
- * wlbm_set_block_rows fixes the height beforehand instead. */
+ * launch, for the lattice's current weight mode (uniform or per-cell field):
+ * the height fixed by wlbm_set_block_rows or chosen by wlbm_tune_block_rows,
+ * else the library's launch model's pick (the height whose blocks fill the
+ * device in the fewest row iterations, from the kernel's occupancy and the
+ * number of compute units).  wlbm_step never times anything itself.  0 if
+ * the lattice runs one step per launch (see step_fusion), -1 for NULL or k
+ * outside 2 .. 4.  Results do not depend on the height. */
 int32_t wlbm_get_block_rows(const wlbm_lattice* lat, int32_t k);
 
 /* Fix the output rows per block of the k-step kernel (k = 2 .. 4) for the
  * lattice's current weight mode: rows + 2 (k - 1) a multiple of 3, 1 .. 62;
- * 0 restarts the timing of candidate heights.  Results do not depend on it. */
+ * 0 returns to the launch model's pick.  Results do not depend on it. */
 wlbm_status wlbm_set_block_rows(wlbm_lattice* lat, int32_t k, int32_t rows);
+
+/* Time every candidate block height of the k-step kernel (k = 2 .. 4) on the
+ * current state, `launches` launches of k steps each (1 .. 1000, after two
+ * warm-up launches, best of two passes), keep the fastest and return it in
+ * *rows (may be NULL).  The state and step count are saved in d_state
+ * (wlbm_state_bytes bytes) and restored after each trial, so the lattice
+ * ends where it started; the flux-window sums are not touched.  Waits for
+ * the stream (not capturable).  WLBM_EINVAL if the lattice runs one step per
+ * launch. */
+wlbm_status wlbm_tune_block_rows(wlbm_lattice* lat, void* d_state, size_t bytes, int32_t k,
+                                 int32_t launches, int32_t* rows);
 
 /* Time `steps` steps (1 .. 10000, after 2 warm-up steps, one step per launch:
  * the split is the single-step kernel's) with each valid split on the
@@ -397,16 +420,17 @@ wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, 
  * step counts, buffers and flux windows are updated).  Wall temperatures and
  * fields are read from the lattices at each call; a member whose q,
  * direction set or grid speeds no longer match its group's is refused
- * (WLBM_EINVAL: create the batch again).  Each whole schedule chunk
- * (sched_chunk steps, when that is even) with no flux-window step and no
- * sources runs as one launch of a HIP graph of its per-step launches,
- * captured on first use for each of the two schedule-ring slots (and again
- * after a change of split or per-cell field use); the kernels, and the bits,
- * are those of step-by-step launches. */
+ * (WLBM_EINVAL: create the batch again).  One kernel launch per step by
+ * default; see wlbm_batch_set_graphs. */
 wlbm_status wlbm_batch_step(wlbm_batch* batch, int64_t nsteps);
 
-/* on = 1 (the default): whole chunks run as graph launches as above; on = 0:
- * one launch per step.  Other values are rejected (WLBM_EINVAL). */
+/* on = 1: each whole schedule chunk (sched_chunk steps, when that is even)
+ * with no flux-window step and no sources runs as one launch of a HIP graph
+ * of its per-step launches, captured on first use for each of the two
+ * schedule-ring slots (and again after a change of split or per-cell field
+ * use); the kernels, and the bits, are those of step-by-step launches.
+ * on = 0 (the default): one launch per step.  Other values are rejected
+ * (WLBM_EINVAL). */
 wlbm_status wlbm_batch_set_graphs(wlbm_batch* batch, int32_t on);
 
 /* Release the batch after waiting for its stream.  NULL is accepted. */

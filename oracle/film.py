@@ -2,7 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY, like the rest of oracle/.  A film of thickness ny
 cells with adiabatic diffuse walls at y = -1/2 and ny - 1/2 is held between
-blackbody columns x = 0 (T_h) and x = nx - 1 (T_c) (Sec. 3.4).  The
+blackbody columns x = 0 (T_h) and x = nx - 1 (T_c) (Sec. 3.5).  The
 effective conductivity is read from the heat flux averaged over the last
 `window` steps (Sec. 3.4 averages over ten steps), taken over the interior
 columns 1 .. nx-2:

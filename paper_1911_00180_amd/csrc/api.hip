@@ -1,4 +1,7 @@
-// C-ABI of libwormlbm.so (declared in include/wormlbm.h).
+// C-ABI of libwormlbm.so (declared in include/wormlbm.h): parameters, lattice
+// set-up, stepping and readout.  Saved states and the adjoint are in
+// api_states.hip, batches in api_batch.hip, launch configuration and tuning
+// in api_tune.hip.
 //
 // A lattice handle owns the host tables (direction set, weights, corrected
 // relaxation weight), the host TAS state and two pinned staging buffers for
@@ -16,15 +19,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/wormlbm.h"
-#include "device.hpp"
-#include "tables.hpp"
+#include "api_internal.hpp"
 
-using namespace wlbm;
+namespace wlbm {
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
 wlbm_status fail(wlbm_status st, const char* fmt, ...) {
   char buf[512];
@@ -36,27 +37,8 @@ wlbm_status fail(wlbm_status st, const char* fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(WLBM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));            \
-  } while (0)
+const char* last_error_text() { return g_last_error.c_str(); }
 
-constexpr size_t kAlign = 256;
-constexpr int kReduceBlocks = 1024;
-constexpr int kDefaultChunk = 240;   // a multiple of 2, 3 and 4 (steps per launch)
-constexpr int64_t kMaxSteps = (int64_t(1) << 31) - 1;
-
-size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
-
-// Byte offsets of the workspace regions.
-struct Carve {
-  size_t e[2], E[2], Wf, Wraw, qsx, qsy, partials, totals, flag, sched, pulls, wtab, sxtab, sytab,
-      mtab, total;
-};
-
-// Lattices that the multi-step kernels can advance (both edges periodic).
 bool fusable(const wlbm_params& p) {
   return p.x_edge == WLBM_EDGE_PERIODIC && p.y_edge == WLBM_EDGE_PERIODIC &&
          fused_supported(p.q, p.nx, p.ny);
@@ -96,6 +78,62 @@ Carve carve(const wlbm_params& p) {
   c.total = off;
   return c;
 }
+
+AdjCarve adj_carve(const wlbm_params& p) {
+  AdjCarve c{};
+  const size_t plane = size_t(padded_plane(p.nx, p.ny)) * sizeof(float);
+  const size_t cells = size_t(p.nx) * size_t(p.ny);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off = align_up(off + bytes);
+    return at;
+  };
+  c.lam[0] = take(plane * size_t(p.q));
+  c.lam[1] = take(plane * size_t(p.q));
+  c.H[0] = take(plane * 8);
+  c.H[1] = take(plane * 8);
+  c.gW = take(cells * sizeof(double));
+  c.gB = take(cells * sizeof(double));
+  c.sched = take(size_t(2) * chunk_steps(p) * size_t(p.q));
+  c.walls = take(4 * sizeof(double));
+  c.flag = take(sizeof(int));
+  c.total = off;
+  return c;
+}
+
+
+wlbm_status check_lat(const wlbm_lattice* l) {
+  if (!l) return fail(WLBM_EINVAL, "lattice is NULL");
+  if (l->broken) return fail(WLBM_ESTATE, "lattice is unusable after an earlier HIP error");
+  return WLBM_OK;
+}
+
+wlbm_status check_steps(const wlbm_lattice* l, int64_t nsteps) {
+  if (nsteps < 0) return fail(WLBM_EINVAL, "nsteps must be >= 0");
+  if (l->tas.n + nsteps > kMaxSteps) return fail(WLBM_EINVAL, "step count would exceed 2^31 - 1");
+  return WLBM_OK;
+}
+
+// Default direction split: as many waves per cell as q allows (up to four),
+// which keeps waves short-lived; measured best on 1024^2 x 64 and
+// 4096^2 x 256 lattices.
+int auto_split(int q) {
+  constexpr size_t kMaxBatchLds = 48 * 1024;
+  if (q % (4 * kMaxGroupPlanes) == 0 && step_batch_lds_bytes(q, 4) <= kMaxBatchLds) return 4;
+  if (q % (2 * kMaxGroupPlanes) == 0 && step_batch_lds_bytes(q, 2) <= kMaxBatchLds) return 2;
+  return 1;
+}
+
+bool lattice_fuses(const wlbm_lattice* l) {
+  return l->p.step_fusion != 0 && l->nsrc == 0 && fusable(l->p);
+}
+
+}  // namespace wlbm
+
+using namespace wlbm;
+
+namespace {
 
 wlbm_status validate(const wlbm_params* p) {
   if (!p) return fail(WLBM_EINVAL, "params is NULL");
@@ -148,223 +186,6 @@ double uniform_wcorr(const wlbm_params& p, double lam, double* W_out) {
   const double W = std::isinf(p.mfp_cells) ? 0.0 : 1.0 / p.mfp_cells;
   if (W_out) *W_out = W;
   return corrected_weight(W, lam, p.emulate_3d != 0, p.mfp_correction != 0);
-}
-
-// Byte offsets of the adjoint workspace regions.
-struct AdjCarve {
-  size_t lam[2], H[2], gW, gB, sched, walls, flag, total;
-};
-
-AdjCarve adj_carve(const wlbm_params& p) {
-  AdjCarve c{};
-  const size_t plane = size_t(padded_plane(p.nx, p.ny)) * sizeof(float);
-  const size_t cells = size_t(p.nx) * size_t(p.ny);
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    const size_t at = off;
-    off = align_up(off + bytes);
-    return at;
-  };
-  c.lam[0] = take(plane * size_t(p.q));
-  c.lam[1] = take(plane * size_t(p.q));
-  c.H[0] = take(plane * 8);
-  c.H[1] = take(plane * 8);
-  c.gW = take(cells * sizeof(double));
-  c.gB = take(cells * sizeof(double));
-  c.sched = take(size_t(2) * chunk_steps(p) * size_t(p.q));
-  c.walls = take(4 * sizeof(double));
-  c.flag = take(sizeof(int));
-  c.total = off;
-  return c;
-}
-
-size_t state_bytes_of(const wlbm_params& p) {
-  return align_up(size_t(padded_plane(p.nx, p.ny)) * sizeof(float) * size_t(p.q + 1));
-}
-
-}  // namespace
-
-// Block height (output rows per block) of a multi-step kernel, chosen by
-// timing real launches: in each of kPasses passes over the candidates, a
-// candidate height runs kSample back-to-back launches, timed from the end of
-// the first to the end of the last (so that the warm-up of the first and the
-// overlap of consecutive launches are as in a long run); the candidate with
-// the best time over the passes is kept.  The populations do not depend on
-// the height, so nothing is repeated or undone.
-struct RowTuner {
-  static constexpr int kMaxCand = 24;
-  static constexpr int kSample = 6;
-  static constexpr int kPasses = 2;
-  int cand[kMaxCand] = {};
-  float ms[kMaxCand] = {};
-  int ncand = 0;
-  int next = 0;     // launches run while tuning
-  int chosen = 0;   // 0 while tuning
-};
-
-struct wlbm_lattice {
-  wlbm_params p{};
-  DirSet dirs;
-  TasState tas;
-  Geometry g{};
-  hipStream_t stream = nullptr;
-  char* ws = nullptr;
-  Carve c{};
-  int cur = 0;              // population buffer holding the current state
-  float W = 0.f;            // uniform corrected weight
-  bool per_cell = false;    // per-cell weight field active
-  int split = 1;            // waves sharing the directions of one cell
-  int chunk = kDefaultChunk;
-  // Rows per block of the multi-step kernels, per [per_cell][k]: chosen by
-  // timing the first launches (the results do not depend on it).
-  RowTuner tuner[2][5];
-  hipEvent_t tev[2] = {nullptr, nullptr};   // timing events of those launches
-  uint8_t* pinned[2] = {nullptr, nullptr};
-  uint32_t* pinned_pulls[2] = {nullptr, nullptr};   // staging of the pull offsets
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  bool ev_pending[2] = {false, false};
-  int64_t chunk_counter = 0;
-  int flux_window = 0;
-  bool flux_valid = false;
-  bool broken = false;
-  Walls walls{};
-  ScheduleBook book;        // schedule rows of any step, for restarts and the adjoint
-  // adjoint (reverse pass) state
-  // internal sources (caller's device arrays, kept valid by the caller)
-  int nsrc = 0;
-  const int32_t* src_cells = nullptr;
-  const float* src_vals = nullptr;
-  char* aws = nullptr;      // caller's adjoint workspace
-  AdjCarve ac{};
-  int acur = 0;             // lam / H buffer holding lam^am
-  int64_t am = -1;          // adjoint step index; -1 when no reverse pass is active
-
-  float* ptr(size_t off) { return reinterpret_cast<float*>(ws + off); }
-  float* aptr(size_t off) { return reinterpret_cast<float*>(aws + off); }
-};
-
-namespace {
-
-wlbm_status check_lat(const wlbm_lattice* l) {
-  if (!l) return fail(WLBM_EINVAL, "lattice is NULL");
-  if (l->broken) return fail(WLBM_ESTATE, "lattice is unusable after an earlier HIP error");
-  return WLBM_OK;
-}
-
-// Default direction split: as many waves per cell as q allows (up to four),
-// which keeps waves short-lived; measured best on 1024^2 x 64 and
-// 4096^2 x 256 lattices.
-int auto_split(int q) {
-  constexpr size_t kMaxBatchLds = 48 * 1024;
-  if (q % (4 * kMaxGroupPlanes) == 0 && step_batch_lds_bytes(q, 4) <= kMaxBatchLds) return 4;
-  if (q % (2 * kMaxGroupPlanes) == 0 && step_batch_lds_bytes(q, 2) <= kMaxBatchLds) return 2;
-  return 1;
-}
-
-void auto_tiling(wlbm_lattice* l) { l->split = l->p.dir_split ? l->p.dir_split : auto_split(l->p.q); }
-
-}  // namespace
-
-// A set of lattices advanced together, one launch per step.
-// Lattices of a batch with one direction set (q, set, grid speeds) share a
-// schedule: one ring of 2 chunks of rows in the batch workspace, and its
-// rows of inward-weight sums.
-struct BatchGroup {
-  wlbm_lattice* lead = nullptr;   // the first member; its directions define the group
-  size_t sched = 0, ins = 0;      // workspace offsets of the group's rings
-  size_t stage = 0;               // offset of its rows in a pinned staging buffer
-};
-
-struct wlbm_batch {
-  std::vector<wlbm_lattice*> lats;
-  std::vector<int> group;         // group of each lattice
-  std::vector<BatchGroup> groups;
-  int qmax = 0;
-  hipStream_t stream = nullptr;
-  char* ws = nullptr;
-  size_t off_args = 0, off_first = 0, off_rc = 0, off_ri = 0;
-  int chunk = 0;
-  uint8_t* pinned[2] = {nullptr, nullptr};     // staging of the schedule rows of every group
-  float* pinned_ins[2] = {nullptr, nullptr};   // staging of the per-step wall sums
-  hipEvent_t ev[2] = {nullptr, nullptr};
-  bool ev_pending[2] = {false, false};
-  int64_t chunk_counter = 0;
-  char* table = nullptr;        // pinned staging of the argument table
-  hipEvent_t table_ev = nullptr;
-  bool table_pending = false;
-  // Full schedule chunks run as one launch of a captured HIP graph per
-  // schedule-ring slot; key: what the graph was captured for.
-  bool use_graphs = true;
-  hipStream_t cap = nullptr;    // private stream the graphs are captured on
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  int64_t gkey[2] = {-1, -1};
-};
-
-namespace {
-
-struct BatchCarve {
-  size_t args, first, rc, ri, total;
-  std::vector<size_t> sched, ins;   // per group
-};
-
-bool same_directions(const wlbm_lattice* a, const wlbm_lattice* b) {
-  return a->p.q == b->p.q && a->p.dirs == b->p.dirs && a->dirs.vgrid == b->dirs.vgrid;
-}
-
-// Group index of each lattice (first-seen order) and the lead of each group.
-void form_groups(wlbm_lattice* const* lats, int n, std::vector<int>& group,
-                 std::vector<wlbm_lattice*>& leads) {
-  group.assign(size_t(n), -1);
-  leads.clear();
-  for (int j = 0; j < n; ++j) {
-    for (size_t g = 0; g < leads.size() && group[j] < 0; ++g)
-      if (same_directions(leads[g], lats[j])) group[j] = int(g);
-    if (group[j] < 0) {
-      group[j] = int(leads.size());
-      leads.push_back(lats[j]);
-    }
-  }
-}
-
-BatchCarve batch_carve(int n, const std::vector<wlbm_lattice*>& leads, int chunk) {
-  BatchCarve c{};
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    const size_t at = off;
-    off = align_up(off + bytes);
-    return at;
-  };
-  c.args = take(size_t(2) * n * sizeof(StepArgs));
-  c.first = take(size_t(n + 1) * sizeof(int));
-  c.rc = take(size_t(n) * sizeof(void*));   // per lattice: its group's schedule ring
-  c.ri = take(size_t(n) * sizeof(void*));   // and ring of inward-weight sums
-  for (const wlbm_lattice* l : leads) {
-    c.sched.push_back(take(size_t(2) * chunk * l->p.q));
-    c.ins.push_back(take(size_t(2) * chunk * 4 * sizeof(float)));
-  }
-  c.total = off;
-  return c;
-}
-
-wlbm_status check_members(wlbm_lattice* const* lats, int32_t n) {
-  if (!lats) return fail(WLBM_EINVAL, "lattice list is NULL");
-  if (n < 1 || n > 4096) return fail(WLBM_EINVAL, "a batch holds 1 .. 4096 lattices");
-  for (int j = 0; j < n; ++j) {
-    wlbm_status st = check_lat(lats[j]);
-    if (st) return st;
-    const wlbm_lattice* a = lats[0];
-    const wlbm_lattice* b = lats[j];
-    if (b->tas.n != a->tas.n)
-      return fail(WLBM_EINVAL, "lattice %d: all lattices of a batch must be at the same step", j);
-    if (b->split != a->split || b->per_cell != a->per_cell || b->chunk != a->chunk)
-      return fail(WLBM_EINVAL,
-                  "lattice %d: direction split, per-cell field use and schedule chunk must agree", j);
-    if (b->flux_window != a->flux_window)
-      return fail(WLBM_EINVAL, "lattice %d: flux windows must agree", j);
-    for (int k = 0; k < j; ++k)
-      if (lats[k] == b) return fail(WLBM_EINVAL, "lattice %d appears twice in the batch", j);
-  }
-  return WLBM_OK;
 }
 
 }  // namespace
@@ -509,14 +330,13 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
   l->walls = {float(p->t_x_lo), float(p->t_x_hi), float(p->t_y_lo), float(p->t_y_hi)};
   l->g = {p->nx, p->ny, p->q, padded_pitch(p->nx), padded_plane(p->nx, p->ny), p->x_edge,
           p->y_edge};
-  auto_tiling(l);
+  l->split = p->dir_split ? p->dir_split : auto_split(p->q);
 
   auto cleanup = [&](wlbm_status s) {
     for (int k = 0; k < 2; ++k) {
       if (l->pinned[k]) (void)hipHostFree(l->pinned[k]);
       if (l->pinned_pulls[k]) (void)hipHostFree(l->pinned_pulls[k]);
       if (l->ev[k]) (void)hipEventDestroy(l->ev[k]);
-      if (l->tev[k]) (void)hipEventDestroy(l->tev[k]);
     }
     delete l;
     return s;
@@ -532,7 +352,6 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
       return cleanup(s);
     }
     e = hipEventCreateWithFlags(&l->ev[k], hipEventDisableTiming);
-    if (e == hipSuccess) e = hipEventCreate(&l->tev[k]);
     if (e != hipSuccess) {
       wlbm_status s = fail(WLBM_EHIP, "hipEventCreate failed: %s", hipGetErrorString(e));
       return cleanup(s);
@@ -585,6 +404,7 @@ wlbm_status wlbm_set_temperature(wlbm_lattice* l, const float* d_T0) {
   HIP_TRY(launch_apply_sources(l->g, l->ptr(l->c.e[l->cur]), l->ptr(l->c.E[l->cur]), l->src_cells,
                                l->src_vals, l->nsrc, l->stream));
   l->flux_valid = false;
+  l->ghosts_full = false;
   return WLBM_OK;
 }
 
@@ -597,6 +417,7 @@ wlbm_status wlbm_set_populations(wlbm_lattice* l, const float* d_e) {
   HIP_TRY(launch_apply_sources(l->g, l->ptr(l->c.e[l->cur]), l->ptr(l->c.E[l->cur]), l->src_cells,
                                l->src_vals, l->nsrc, l->stream));
   l->flux_valid = false;
+  l->ghosts_full = false;
   return WLBM_OK;
 }
 
@@ -622,6 +443,7 @@ wlbm_status wlbm_set_mfp_field(wlbm_lattice* l, const float* d_mfp) {
   HIP_TRY(launch_write_wfield(l->g, d_mfp, l->dirs.lambda_corr, f, l->p.mfp_correction,
                               l->ptr(l->c.Wf), l->ptr(l->c.Wraw), l->stream));
   l->per_cell = true;
+  l->wf_ghosts_full = false;
   return WLBM_OK;
 }
 
@@ -655,6 +477,7 @@ wlbm_status wlbm_set_sources(wlbm_lattice* l, int32_t n, const int32_t* d_cells,
   l->src_vals = d_values;
   HIP_TRY(launch_apply_sources(l->g, l->ptr(l->c.e[l->cur]), l->ptr(l->c.E[l->cur]), d_cells,
                                d_values, n, l->stream));
+  l->ghosts_full = false;
   return WLBM_OK;
 }
 
@@ -716,7 +539,7 @@ wlbm_status wlbm_set_flux_window(wlbm_lattice* l, int32_t window) {
 
 }  // extern "C"
 
-namespace {
+namespace wlbm {
 
 // Advance nsteps (validated by the caller).  Without a tape the state
 // alternates between the two population buffers of the workspace.  With a
@@ -752,17 +575,10 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
   a.y_edge = l->g.y_edge;
   a.tiles_x = tiles_x_for(l->g.nx);
   a.ntiles = a.tiles_x * tiles_y_for(l->g.ny, l->split);
-  // several steps per launch: periodic edges only, no sources, not into a
-  // tape, and a lattice the multi-step kernels are built for
-  const bool fuse = l->p.step_fusion != 0 && !tape && l->nsrc == 0 &&
-                    l->g.x_edge == kPeriodic && l->g.y_edge == kPeriodic &&
-                    fused_supported(q, l->g.nx, l->g.ny);
+  // several steps per launch: not into a tape, and a lattice the multi-step
+  // kernels are built for
+  const bool fuse = !tape && lattice_fuses(l);
   const int k_max = l->p.step_fusion == 1 ? 4 : l->p.step_fusion;
-
-  // the multi-step kernels read three ghost columns; other producers write
-  // the first one only, so the frame is refreshed before the first
-  // multi-step launch and after any single step in between
-  bool refresh_ghosts = true;
 
   int64_t done = 0;
   while (done < nsteps) {
@@ -844,47 +660,29 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
         a2.q = q;
         a2.pitch = a.pitch;
         a2.plane = a.plane;
-        e = hipSuccess;
-        RowTuner& tu = l->tuner[l->per_cell ? 1 : 0][K];
-        if (tu.ncand == 0) tu.ncand = fused_row_candidates(a.ny, K, tu.cand, RowTuner::kMaxCand);
-        const bool timing = tu.chosen == 0;
-        const int ci = (tu.next / RowTuner::kSample) % tu.ncand;
-        const int phase = tu.next % RowTuner::kSample;
-        const bool first_pass = tu.next < RowTuner::kSample * tu.ncand;
-        a2.rows = timing ? tu.cand[ci] : tu.chosen;
+        a2.rows = block_rows_for(l, K);
         a2.strips_x = fused_strips_x(a.nx, K);
         a2.strips_y = (a.ny + a2.rows - 1) / a2.rows;
-        if (refresh_ghosts) {
+        e = hipSuccess;
+        // the multi-step kernels read kGhost ghost columns, which other
+        // producers do not write: refresh the frame once before the first
+        // multi-step launch that follows them
+        if (!l->ghosts_full) {
           e = fill_ghosts(l->ptr(l->c.e[l->cur]), a.plane, q, a.nx, a.ny, a.pitch, l->stream);
           if (e == hipSuccess)
             e = fill_ghosts(l->ptr(l->c.E[l->cur]), a.plane, 1, a.nx, a.ny, a.pitch, l->stream);
-          if (e == hipSuccess && l->per_cell)
-            e = fill_ghosts(l->ptr(l->c.Wf), a.plane, 1, a.nx, a.ny, a.pitch, l->stream);
-          refresh_ghosts = false;
+        }
+        if (e == hipSuccess && l->per_cell && !l->wf_ghosts_full) {
+          e = fill_ghosts(l->ptr(l->c.Wf), a.plane, 1, a.nx, a.ny, a.pitch, l->stream);
+          if (e == hipSuccess) l->wf_ghosts_full = true;
         }
         if (e == hipSuccess) e = launch_fused(a2, K, l->per_cell, l->stream);
-        if (e == hipSuccess && timing) {
-          if (phase == 0) {
-            e = hipEventRecord(l->tev[0], l->stream);
-          } else if (phase == RowTuner::kSample - 1) {
-            float ms = 0.f;
-            e = hipEventRecord(l->tev[1], l->stream);
-            if (e == hipSuccess) e = hipEventSynchronize(l->tev[1]);
-            if (e == hipSuccess) e = hipEventElapsedTime(&ms, l->tev[0], l->tev[1]);
-            if (first_pass || ms < tu.ms[ci]) tu.ms[ci] = ms;
-          }
-          if (e == hipSuccess && ++tu.next == RowTuner::kPasses * RowTuner::kSample * tu.ncand) {
-            int b = 0;
-            for (int c = 1; c < tu.ncand; ++c)
-              if (tu.ms[c] < tu.ms[b]) b = c;
-            tu.chosen = tu.cand[b];
-          }
-        }
         if (e != hipSuccess) {
           l->broken = true;
           return fail(WLBM_EHIP, "fused step kernel launch failed: %s", hipGetErrorString(e));
         }
         l->cur = 1 - l->cur;
+        l->ghosts_full = true;   // the kernel writes the whole frame of its output
         j += K - 1;
         continue;
       }
@@ -916,7 +714,7 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
         return fail(WLBM_EHIP, "step kernel launch failed: %s", hipGetErrorString(e));
       }
       if (!tape) l->cur = 1 - l->cur;
-      refresh_ghosts = true;
+      l->ghosts_full = false;
     }
     done += cnt;
   }
@@ -937,13 +735,7 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
   return WLBM_OK;
 }
 
-wlbm_status check_steps(const wlbm_lattice* l, int64_t nsteps) {
-  if (nsteps < 0) return fail(WLBM_EINVAL, "nsteps must be >= 0");
-  if (l->tas.n + nsteps > kMaxSteps) return fail(WLBM_EINVAL, "step count would exceed 2^31 - 1");
-  return WLBM_OK;
-}
-
-}  // namespace
+}  // namespace wlbm
 
 extern "C" {
 
@@ -953,27 +745,6 @@ wlbm_status wlbm_step(wlbm_lattice* l, int64_t nsteps) {
   if (st) return st;
   if (nsteps == 0) return WLBM_OK;
   return run_steps(l, nsteps, nullptr, 0);
-}
-
-wlbm_status wlbm_state_bytes(const wlbm_lattice* l, size_t* bytes) {
-  if (!l) return fail(WLBM_EINVAL, "lattice is NULL");
-  if (!bytes) return fail(WLBM_EINVAL, "bytes is NULL");
-  *bytes = state_bytes_of(l->p);
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_step_tape(wlbm_lattice* l, int64_t nsteps, void* d_tape, size_t slot_bytes) {
-  wlbm_status st = check_lat(l);
-  if (!st) st = check_steps(l, nsteps);
-  if (st) return st;
-  if (nsteps == 0) return WLBM_OK;
-  if (!d_tape) return fail(WLBM_EINVAL, "tape is NULL");
-  if (reinterpret_cast<uintptr_t>(d_tape) % kAlign || slot_bytes % kAlign)
-    return fail(WLBM_EINVAL, "tape and slot size must be 256-byte aligned");
-  if (slot_bytes < state_bytes_of(l->p))
-    return fail(WLBM_EINVAL, "slot of %zu bytes is smaller than a state (%zu bytes)", slot_bytes,
-                state_bytes_of(l->p));
-  return run_steps(l, nsteps, static_cast<char*>(d_tape), slot_bytes);
 }
 
 wlbm_status wlbm_read_temperature(wlbm_lattice* l, float* d_T) {
@@ -1036,689 +807,6 @@ wlbm_status wlbm_read_totals(wlbm_lattice* l, double* energy, double* qx_sum, do
   return WLBM_OK;
 }
 
-wlbm_status wlbm_save_state(wlbm_lattice* l, void* d_buf, size_t bytes) {
-  wlbm_status st = check_lat(l);
-  if (st) return st;
-  if (!d_buf) return fail(WLBM_EINVAL, "state buffer is NULL");
-  if (bytes < state_bytes_of(l->p))
-    return fail(WLBM_EINVAL, "state buffer of %zu bytes is smaller than a state (%zu bytes)",
-                bytes, state_bytes_of(l->p));
-  const size_t pbytes = size_t(l->g.plane) * sizeof(float);
-  char* b = static_cast<char*>(d_buf);
-  HIP_TRY(hipMemcpyAsync(b, l->ptr(l->c.e[l->cur]), pbytes * l->p.q, hipMemcpyDeviceToDevice,
-                         l->stream));
-  HIP_TRY(hipMemcpyAsync(b + pbytes * l->p.q, l->ptr(l->c.E[l->cur]), pbytes,
-                         hipMemcpyDeviceToDevice, l->stream));
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_load_state(wlbm_lattice* l, const void* d_buf, size_t bytes, int64_t step) {
-  wlbm_status st = check_lat(l);
-  if (st) return st;
-  if (!d_buf) return fail(WLBM_EINVAL, "state buffer is NULL");
-  if (bytes < state_bytes_of(l->p))
-    return fail(WLBM_EINVAL, "state buffer of %zu bytes is smaller than a state (%zu bytes)",
-                bytes, state_bytes_of(l->p));
-  if (step < 0 || step > kMaxSteps) return fail(WLBM_EINVAL, "step must be in 0 .. 2^31 - 1");
-  const size_t pbytes = size_t(l->g.plane) * sizeof(float);
-  const char* b = static_cast<const char*>(d_buf);
-  HIP_TRY(hipMemcpyAsync(l->ptr(l->c.e[l->cur]), b, pbytes * l->p.q, hipMemcpyDeviceToDevice,
-                         l->stream));
-  HIP_TRY(hipMemcpyAsync(l->ptr(l->c.E[l->cur]), b + pbytes * l->p.q, pbytes,
-                         hipMemcpyDeviceToDevice, l->stream));
-  try {
-    l->book.state_at(step, l->tas);
-  } catch (const std::exception& e) {
-    return fail(WLBM_ENOMEM, "schedule restore failed: %s", e.what());
-  }
-  l->flux_valid = false;
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_read_probes(wlbm_lattice* l, int32_t n, const int32_t* d_cells, float* d_T) {
-  wlbm_status st = check_lat(l);
-  if (st) return st;
-  if (n < 0) return fail(WLBM_EINVAL, "probe count must be >= 0");
-  if (n > 0 && (!d_cells || !d_T)) return fail(WLBM_EINVAL, "probe arrays must not be NULL");
-  HIP_TRY(launch_read_probes(l->g, l->ptr(l->c.E[l->cur]), d_cells, n, d_T, l->stream));
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_adjoint_bytes(const wlbm_lattice* l, size_t* bytes) {
-  if (!l) return fail(WLBM_EINVAL, "lattice is NULL");
-  if (!bytes) return fail(WLBM_EINVAL, "bytes is NULL");
-  *bytes = adj_carve(l->p).total;
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_adjoint_begin(wlbm_lattice* l, void* d_ws, size_t bytes, int64_t step) {
-  wlbm_status st = check_lat(l);
-  if (st) return st;
-  if (l->p.y_edge == WLBM_EDGE_DIFFUSE)
-    return fail(WLBM_EINVAL, "the adjoint covers periodic and blackbody edges only");
-  if (l->nsrc) return fail(WLBM_EINVAL, "the adjoint does not cover internal sources");
-  if (step < 0 || step > kMaxSteps) return fail(WLBM_EINVAL, "step must be in 0 .. 2^31 - 1");
-  if (!d_ws) return fail(WLBM_EINVAL, "adjoint workspace is NULL");
-  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
-    return fail(WLBM_EINVAL, "adjoint workspace must be 256-byte aligned");
-  const AdjCarve ac = adj_carve(l->p);
-  if (bytes < ac.total)
-    return fail(WLBM_ENOMEM, "adjoint workspace too small: %zu bytes given, %zu needed", bytes,
-                ac.total);
-  HIP_TRY(hipMemsetAsync(d_ws, 0, ac.total, l->stream));
-  l->aws = static_cast<char*>(d_ws);
-  l->ac = ac;
-  l->acur = 0;
-  l->am = step;
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_adjoint_seed(wlbm_lattice* l, int32_t n, const int32_t* d_cells,
-                              const float* d_dT) {
-  wlbm_status st = check_lat(l);
-  if (st) return st;
-  if (l->am < 0) return fail(WLBM_ESTATE, "no reverse pass: call wlbm_adjoint_begin first");
-  if (n < 0) return fail(WLBM_EINVAL, "probe count must be >= 0");
-  if (n == 0) return WLBM_OK;
-  if (!d_cells || !d_dT) return fail(WLBM_EINVAL, "seed arrays must not be NULL");
-  const int q = l->p.q;
-  AdjSeedArgs a{};
-  a.lam = l->aptr(l->ac.lam[l->acur]);
-  a.H = l->aptr(l->ac.H[l->acur]);
-  a.gB = reinterpret_cast<double*>(l->aws + l->ac.gB);
-  a.cells = d_cells;
-  a.vals = d_dT;
-  a.flag = reinterpret_cast<int*>(l->aws + l->ac.flag);
-  a.n = n;
-  double wc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  double wall_w = 0.0;
-  for (int i = 0; i < q; ++i) wall_w += l->dirs.w[i];
-  if (l->am >= 1) {
-    // the partial sums of lam^am are classed by the moves of step am
-    std::vector<int8_t> dx(q), dy(q);
-    std::vector<uint8_t> hop(q);
-    try {
-      l->book.rows(l->am, 1, dx.data(), dy.data(), hop.data());
-    } catch (const std::exception& e) {
-      return fail(WLBM_ENOMEM, "schedule restore failed: %s", e.what());
-    }
-    for (int i = 0; i < q; ++i) wc[host_move_class(dx[i], dy[i])] += l->dirs.w[i];
-  }
-  for (int c = 0; c < 8; ++c) a.wcls[c] = float(wc[c]);
-  a.wall_w = wall_w;
-  a.nx = l->g.nx;
-  a.ny = l->g.ny;
-  a.q = q;
-  a.pitch = l->g.pitch;
-  a.plane = l->g.plane;
-  a.x_edge = l->g.x_edge;
-  a.y_edge = l->g.y_edge;
-  HIP_TRY(launch_adj_seed(a, l->stream));
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_adjoint_steps(wlbm_lattice* l, int64_t n, const void* d_states,
-                               size_t slot_bytes) {
-  wlbm_status st = check_lat(l);
-  if (st) return st;
-  if (l->am < 0) return fail(WLBM_ESTATE, "no reverse pass: call wlbm_adjoint_begin first");
-  if (n < 0 || n > l->am)
-    return fail(WLBM_EINVAL, "n must be in 0 .. %lld (the current adjoint step)",
-                (long long)l->am);
-  if (n == 0) return WLBM_OK;
-  if (!d_states) return fail(WLBM_EINVAL, "states pointer is NULL");
-  if (reinterpret_cast<uintptr_t>(d_states) % kAlign || slot_bytes % kAlign)
-    return fail(WLBM_EINVAL, "states and slot size must be 256-byte aligned");
-  if (slot_bytes < state_bytes_of(l->p))
-    return fail(WLBM_EINVAL, "slot of %zu bytes is smaller than a state (%zu bytes)", slot_bytes,
-                state_bytes_of(l->p));
-  const int q = l->p.q;
-  const char* states = static_cast<const char*>(d_states);
-  const int64_t m0 = l->am;
-  const int64_t base = m0 - n;  // step of the state in slot 0
-  AdjArgs a{};
-  a.Wf = l->ptr(l->c.Wf);
-  a.gW = reinterpret_cast<double*>(l->aws + l->ac.gW);
-  a.gB = reinterpret_cast<double*>(l->aws + l->ac.gB);
-  a.wtab = l->ptr(l->c.wtab);
-  a.W = l->W;
-  a.nx = l->g.nx;
-  a.ny = l->g.ny;
-  a.q = q;
-  a.pitch = l->g.pitch;
-  a.plane = l->g.plane;
-  a.x_edge = l->g.x_edge;
-  a.y_edge = l->g.y_edge;
-  a.tiles_x = tiles_x_for(l->g.nx);
-  a.ntiles = a.tiles_x * tiles_y_for(l->g.ny, l->split);
-  std::vector<int8_t> dx, dy;
-  std::vector<uint8_t> hop;
-  const int64_t per = l->chunk - 1;  // reverse steps per upload: rows m-cnt .. m
-  int64_t done = 0;
-  while (done < n) {
-    const int64_t cnt = std::min<int64_t>(per, n - done);
-    const int64_t m_hi = m0 - done;
-    const int64_t first = std::max<int64_t>(1, m_hi - cnt);
-    const int64_t nrows = m_hi - first + 1;
-    const int slot = int(l->chunk_counter & 1);
-    if (l->ev_pending[slot]) {
-      hipError_t e = hipEventSynchronize(l->ev[slot]);
-      if (e != hipSuccess) {
-        l->broken = true;
-        return fail(WLBM_EHIP, "hipEventSynchronize failed: %s", hipGetErrorString(e));
-      }
-      l->ev_pending[slot] = false;
-    }
-    dx.resize(size_t(nrows) * q);
-    dy.resize(size_t(nrows) * q);
-    hop.resize(size_t(nrows) * q);
-    try {
-      l->book.rows(first, nrows, dx.data(), dy.data(), hop.data());
-    } catch (const std::exception& e) {
-      return fail(WLBM_ENOMEM, "schedule restore failed: %s", e.what());
-    }
-    uint8_t* rows = l->pinned[slot];
-    for (size_t k = 0; k < size_t(nrows) * q; ++k) rows[k] = pack_code(dx[k], dy[k], hop[k]);
-    uint8_t* dev_rows =
-        reinterpret_cast<uint8_t*>(l->aws + l->ac.sched) + size_t(slot) * l->chunk * q;
-    hipError_t e = hipMemcpyAsync(dev_rows, rows, size_t(nrows) * q, hipMemcpyHostToDevice,
-                                  l->stream);
-    if (e == hipSuccess) e = hipEventRecord(l->ev[slot], l->stream);
-    if (e != hipSuccess) {
-      l->broken = true;
-      return fail(WLBM_EHIP, "schedule upload failed: %s", hipGetErrorString(e));
-    }
-    l->ev_pending[slot] = true;
-    ++l->chunk_counter;
-    for (int64_t j = 0; j < cnt; ++j) {
-      const int64_t m = m_hi - j;
-      const uint8_t* row_m = dev_rows + size_t(m - first) * q;
-      const uint8_t* row_next = m - 1 >= 1 ? dev_rows + size_t(m - 1 - first) * q : row_m;
-      const char* sp = states + size_t(m - 1 - base) * slot_bytes;
-      a.codes = reinterpret_cast<const uint32_t*>(row_m);
-      a.codes_next = reinterpret_cast<const uint32_t*>(row_next);
-      a.e_prev = reinterpret_cast<const float*>(sp);
-      a.E_prev = reinterpret_cast<const float*>(sp) + size_t(q) * l->g.plane;
-      a.lam_in = l->aptr(l->ac.lam[l->acur]);
-      a.lam_out = l->aptr(l->ac.lam[1 - l->acur]);
-      a.H_in = l->aptr(l->ac.H[l->acur]);
-      a.H_out = l->aptr(l->ac.H[1 - l->acur]);
-      e = launch_adjoint(a, l->split, l->per_cell, l->stream);
-      if (e != hipSuccess) {
-        l->broken = true;
-        return fail(WLBM_EHIP, "adjoint kernel launch failed: %s", hipGetErrorString(e));
-      }
-      l->acur = 1 - l->acur;
-    }
-    done += cnt;
-  }
-  l->am = m0 - n;
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_adjoint_read(wlbm_lattice* l, float* d_g_mfp, float* d_g_T0, double* g_walls) {
-  wlbm_status st = check_lat(l);
-  if (st) return st;
-  if (l->am < 0) return fail(WLBM_ESTATE, "no reverse pass: call wlbm_adjoint_begin first");
-  const double f = l->p.emulate_3d ? 1.5 : 1.0;
-  const double W = std::isinf(l->p.mfp_cells) ? 0.0 : 1.0 / l->p.mfp_cells;
-  if (d_g_mfp)
-    HIP_TRY(launch_adj_grad_mfp(l->g, reinterpret_cast<const double*>(l->aws + l->ac.gW),
-                                l->per_cell ? l->ptr(l->c.Wraw) : nullptr, W,
-                                l->dirs.lambda_corr, f, l->p.mfp_correction, d_g_mfp,
-                                l->stream));
-  if (d_g_T0)
-    HIP_TRY(launch_adj_grad_t0(l->g, l->aptr(l->ac.lam[l->acur]), l->ptr(l->c.wtab), d_g_T0,
-                               l->stream));
-  double* dev_walls = reinterpret_cast<double*>(l->aws + l->ac.walls);
-  HIP_TRY(launch_adj_walls(l->g, reinterpret_cast<const double*>(l->aws + l->ac.gB), dev_walls,
-                           l->stream));
-  double hw[4];
-  int flag = 0;
-  HIP_TRY(hipMemcpyAsync(hw, dev_walls, sizeof(hw), hipMemcpyDeviceToHost, l->stream));
-  HIP_TRY(hipMemcpyAsync(&flag, l->aws + l->ac.flag, sizeof(int), hipMemcpyDeviceToHost,
-                         l->stream));
-  HIP_TRY(hipStreamSynchronize(l->stream));
-  if (flag) return fail(WLBM_EINVAL, "a seed cell was outside the lattice (it was skipped)");
-  if (g_walls)
-    for (int k = 0; k < 4; ++k) g_walls[k] = hw[k];
-  return WLBM_OK;
-}
-
-int64_t wlbm_adjoint_step_index(const wlbm_lattice* l) { return l ? l->am : -1; }
-
-wlbm_status wlbm_set_dir_split(wlbm_lattice* l, int32_t split) {
-  wlbm_status st = check_lat(l);
-  if (st) return st;
-  if (split == 0) {
-    l->split = auto_split(l->p.q);
-    return WLBM_OK;
-  }
-  if (split != 1 && split != 2 && split != 4)
-    return fail(WLBM_EINVAL, "dir_split must be 0, 1, 2 or 4");
-  if (l->p.q % (kMaxGroupPlanes * split) != 0)
-    return fail(WLBM_EINVAL, "q = %d cannot be split over %d waves", l->p.q, split);
-  if (step_batch_lds_bytes(l->p.q, split) > 48 * 1024)
-    return fail(WLBM_EINVAL, "q = %d is too large for a split over %d waves", l->p.q, split);
-  l->split = split;
-  return WLBM_OK;
-}
-
-int32_t wlbm_get_dir_split(const wlbm_lattice* l) { return l ? l->split : -1; }
-
-int32_t wlbm_get_block_rows(const wlbm_lattice* l, int32_t k) {
-  if (!l || k < 2 || k > 4) return -1;
-  return l->tuner[l->per_cell ? 1 : 0][k].chosen;
-}
-
-wlbm_status wlbm_set_block_rows(wlbm_lattice* l, int32_t k, int32_t rows) {
-  wlbm_status st = check_lat(l);
-  if (st) return st;
-  if (k < 2 || k > 4) return fail(WLBM_EINVAL, "k must be 2, 3 or 4 (got %d)", k);
-  if (rows < 0 || rows > 62 || (rows > 0 && (rows + 2 * (k - 1)) % 3 != 0))
-    return fail(WLBM_EINVAL,
-                "rows must be 0 or 1 .. 62 with rows + 2 (k - 1) a multiple of 3 (got %d)", rows);
-  RowTuner& tu = l->tuner[l->per_cell ? 1 : 0][k];
-  tu.next = 0;
-  tu.chosen = rows;
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_batch_bytes(wlbm_lattice* const* lats, int32_t n, size_t* bytes) {
-  wlbm_status st = check_members(lats, n);
-  if (st) return st;
-  if (!bytes) return fail(WLBM_EINVAL, "bytes is NULL");
-  std::vector<int> group;
-  std::vector<wlbm_lattice*> leads;
-  form_groups(lats, n, group, leads);
-  *bytes = batch_carve(n, leads, lats[0]->chunk).total;
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, size_t bytes,
-                              void* stream, wlbm_batch** out) {
-  if (!out) return fail(WLBM_EINVAL, "out is NULL");
-  *out = nullptr;
-  wlbm_status st = check_members(lats, n);
-  if (st) return st;
-  std::vector<int> group;
-  std::vector<wlbm_lattice*> leads;
-  form_groups(lats, n, group, leads);
-  const BatchCarve bc = batch_carve(n, leads, lats[0]->chunk);
-  if (!d_ws) return fail(WLBM_EINVAL, "batch workspace is NULL");
-  if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
-    return fail(WLBM_EINVAL, "batch workspace must be 256-byte aligned");
-  if (bytes < bc.total)
-    return fail(WLBM_ENOMEM, "batch workspace too small: %zu bytes given, %zu needed", bytes,
-                bc.total);
-  wlbm_batch* b = new (std::nothrow) wlbm_batch();
-  if (!b) return fail(WLBM_ENOMEM, "host allocation failed");
-  b->lats.assign(lats, lats + n);
-  b->group = group;
-  b->stream = static_cast<hipStream_t>(stream);
-  b->ws = static_cast<char*>(d_ws);
-  b->off_args = bc.args;
-  b->off_first = bc.first;
-  b->off_rc = bc.rc;
-  b->off_ri = bc.ri;
-  b->chunk = lats[0]->chunk;
-  size_t stage = 0;
-  for (size_t g = 0; g < leads.size(); ++g) {
-    BatchGroup bg;
-    bg.lead = leads[g];
-    bg.sched = bc.sched[g];
-    bg.ins = bc.ins[g];
-    bg.stage = stage;
-    stage += size_t(b->chunk) * leads[g]->p.q;
-    b->groups.push_back(bg);
-    b->qmax = std::max(b->qmax, leads[g]->p.q);
-  }
-  const size_t ngroups = leads.size();
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-    e = hipHostMalloc(reinterpret_cast<void**>(&b->pinned[k]), stage, hipHostMallocDefault);
-    if (e == hipSuccess)
-      e = hipHostMalloc(reinterpret_cast<void**>(&b->pinned_ins[k]),
-                        ngroups * b->chunk * 4 * sizeof(float), hipHostMallocDefault);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming);
-  }
-  if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
-  if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&b->table), bc.ri + size_t(n) * sizeof(void*),
-                      hipHostMallocDefault);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->table_ev, hipEventDisableTiming);
-  if (e != hipSuccess) {
-    (void)wlbm_batch_destroy(b);
-    return fail(WLBM_ENOMEM, "batch set-up failed: %s", hipGetErrorString(e));
-  }
-  *out = b;
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
-  if (!b) return fail(WLBM_EINVAL, "batch is NULL");
-  const int n = int(b->lats.size());
-  wlbm_status st = check_members(b->lats.data(), n);
-  if (st) return st;
-  for (int j = 0; j < n; ++j)
-    if (!same_directions(b->groups[size_t(b->group[j])].lead, b->lats[j]))
-      return fail(WLBM_EINVAL,
-                  "lattice %d: its directions or grid speeds changed since the batch was "
-                  "created; create the batch again", j);
-  wlbm_lattice* l0 = b->lats[0];
-  st = check_steps(l0, nsteps);
-  if (st) return st;
-  if (nsteps == 0) return WLBM_OK;
-  const int ngroups = int(b->groups.size());
-  // argument table: lattice j, buffer parity p (p = 1 after an odd number of
-  // steps of this call); wall temperatures and fields as they are now.  The
-  // pinned staging copy of the previous call must have been consumed.
-  if (b->table_pending) {
-    hipError_t e = hipEventSynchronize(b->table_ev);
-    if (e != hipSuccess) return fail(WLBM_EHIP, "hipEventSynchronize failed: %s",
-                                     hipGetErrorString(e));
-    b->table_pending = false;
-  }
-  StepArgs* table = reinterpret_cast<StepArgs*>(b->table);
-  int* first = reinterpret_cast<int*>(b->table + b->off_first);
-  const void** ring_codes = reinterpret_cast<const void**>(b->table + b->off_rc);
-  const void** ring_ins = reinterpret_cast<const void**>(b->table + b->off_ri);
-  first[0] = 0;
-  for (int j = 0; j < n; ++j) {
-    wlbm_lattice* l = b->lats[j];
-    const BatchGroup& bg = b->groups[size_t(b->group[j])];
-    ring_codes[j] = b->ws + bg.sched;
-    ring_ins[j] = b->ws + bg.ins;
-    for (int par = 0; par < 2; ++par) {
-      StepArgs& a = table[size_t(2) * j + par];
-      const int in = l->cur ^ par;
-      a.e_in = l->ptr(l->c.e[in]);
-      a.e_out = l->ptr(l->c.e[1 - in]);
-      a.E_in = l->ptr(l->c.E[in]);
-      a.E_out = l->ptr(l->c.E[1 - in]);
-      a.Wf = l->ptr(l->c.Wf);
-      a.qsx = l->ptr(l->c.qsx);
-      a.qsy = l->ptr(l->c.qsy);
-      a.wtab = l->ptr(l->c.wtab);
-      a.sxtab = l->ptr(l->c.sxtab);
-      a.sytab = l->ptr(l->c.sytab);
-      a.mtab = reinterpret_cast<const int*>(l->ws + l->c.mtab);
-      a.W = l->W;
-      a.spec = float(l->p.y_specularity);
-      a.t_x_lo = l->walls.x_lo;
-      a.t_x_hi = l->walls.x_hi;
-      a.t_y_lo = l->walls.y_lo;
-      a.t_y_hi = l->walls.y_hi;
-      a.nx = l->g.nx;
-      a.ny = l->g.ny;
-      a.q = l->p.q;
-      a.pitch = l->g.pitch;
-      a.plane = l->g.plane;
-      a.x_edge = l->g.x_edge;
-      a.y_edge = l->g.y_edge;
-      a.tiles_x = tiles_x_for(l->g.nx);
-      a.ntiles = a.tiles_x * tiles_y_for(l->g.ny, l->split);
-    }
-    first[size_t(j) + 1] = first[size_t(j)] + table[size_t(2) * j].ntiles;
-  }
-  // the table, first[] and the ring pointers sit at the same offsets in the
-  // staging buffer and in the workspace, so one copy moves them all
-  HIP_TRY(hipMemcpyAsync(b->ws, b->table, b->off_ri + size_t(n) * sizeof(void*),
-                         hipMemcpyHostToDevice, b->stream));
-  HIP_TRY(hipEventRecord(b->table_ev, b->stream));
-  b->table_pending = true;
-  BatchStepArgs ba{};
-  ba.lats = reinterpret_cast<const StepArgs*>(b->ws + b->off_args);
-  ba.first = reinterpret_cast<const int*>(b->ws + b->off_first);
-  ba.n = n;
-  ba.nblocks = first[size_t(n)];
-  ba.q = b->qmax;
-  ba.ring_codes = reinterpret_cast<const uint32_t* const*>(b->ws + b->off_rc);
-  ba.ring_ins = reinterpret_cast<const float* const*>(b->ws + b->off_ri);
-  const bool grouped = ngroups > 1;
-  // group 0's row and sums of step j in ring slot `slot`
-  const BatchGroup& g0 = b->groups[0];
-  auto rows0 = [&](int slot_, int j) {
-    return reinterpret_cast<const uint32_t*>(b->ws + g0.sched +
-                                             (size_t(slot_) * b->chunk + j) * g0.lead->p.q);
-  };
-  auto ins0 = [&](int slot_, int j) {
-    return reinterpret_cast<const float*>(b->ws + g0.ins) + (size_t(slot_) * b->chunk + j) * 4;
-  };
-  const int64_t flux_from = l0->flux_window > 0 ? nsteps - l0->flux_window : nsteps;
-  bool has_sources = false;
-  for (wlbm_lattice* l : b->lats) has_sources = has_sources || l->nsrc > 0;
-  // each group advances its own schedule state
-  std::vector<TasState> tas;
-  for (const BatchGroup& bg : b->groups) tas.push_back(bg.lead->tas);
-  std::vector<int8_t> dx(size_t(b->qmax)), dy(size_t(b->qmax));
-  std::vector<uint8_t> hop(size_t(b->qmax));
-  int64_t done = 0;
-  while (done < nsteps) {
-    const int cnt = int(std::min<int64_t>(b->chunk, nsteps - done));
-    const int slot = int(b->chunk_counter & 1);
-    if (b->ev_pending[slot]) {
-      hipError_t e = hipEventSynchronize(b->ev[slot]);
-      if (e != hipSuccess) return fail(WLBM_EHIP, "hipEventSynchronize failed: %s",
-                                       hipGetErrorString(e));
-      b->ev_pending[slot] = false;
-    }
-    // Build the schedule rows of this chunk (Sec. 2.3, Sec. 2.5) and the
-    // per-step sums of inward weights used by diffuse walls, for each group,
-    // and upload them into the group's ring slot.
-    hipError_t e = hipSuccess;
-    for (int g = 0; g < ngroups && e == hipSuccess; ++g) {
-      const BatchGroup& bg = b->groups[size_t(g)];
-      const wlbm_lattice* lead = bg.lead;
-      const int q = lead->p.q;
-      uint8_t* rows = b->pinned[slot] + bg.stage;
-      float* insums = b->pinned_ins[slot] + size_t(g) * b->chunk * 4;
-      for (int j = 0; j < cnt; ++j) {
-        tas_advance(lead->dirs, tas[size_t(g)], dx.data(), dy.data(), hop.data());
-        for (int m = 0; m < n; ++m)
-          if (b->group[m] == g) b->lats[m]->book.note(tas[size_t(g)]);
-        double lo_h = 0, lo_a = 0, hi_h = 0, hi_a = 0;
-        for (int i = 0; i < q; ++i) {
-          rows[size_t(j) * q + i] = pack_code(dx[i], dy[i], hop[i]);
-          if (dy[i] == 1) {
-            lo_a += lead->dirs.w[i];
-            if (hop[i]) lo_h += lead->dirs.w[i];
-          } else if (dy[i] == -1) {
-            hi_a += lead->dirs.w[i];
-            if (hop[i]) hi_h += lead->dirs.w[i];
-          }
-        }
-        insums[4 * j] = float(lo_h);
-        insums[4 * j + 1] = float(lo_a);
-        insums[4 * j + 2] = float(hi_h);
-        insums[4 * j + 3] = float(hi_a);
-      }
-      uint8_t* dev_rows =
-          reinterpret_cast<uint8_t*>(b->ws + bg.sched) + size_t(slot) * b->chunk * q;
-      float* dev_ins = reinterpret_cast<float*>(b->ws + bg.ins) + size_t(slot) * b->chunk * 4;
-      e = hipMemcpyAsync(dev_rows, rows, size_t(cnt) * q, hipMemcpyHostToDevice, b->stream);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(dev_ins, insums, size_t(cnt) * 4 * sizeof(float),
-                           hipMemcpyHostToDevice, b->stream);
-    }
-    if (e == hipSuccess) e = hipEventRecord(b->ev[slot], b->stream);
-    if (e != hipSuccess) return fail(WLBM_EHIP, "schedule upload failed: %s", hipGetErrorString(e));
-    b->ev_pending[slot] = true;
-    ++b->chunk_counter;
-    // A whole chunk with no flux-window step and no sources, starting on an
-    // even step of this call, is one launch of the slot's captured graph:
-    // its kernels read the schedule rows and sums just uploaded, and the
-    // argument table of this call.
-    const bool graph = b->use_graphs && cnt == b->chunk && b->chunk % 2 == 0 &&
-                       done % 2 == 0 && done + cnt <= flux_from && !has_sources;
-    if (graph) {
-      const int64_t key = (int64_t(ba.nblocks) << 8) | (int64_t(l0->split) << 1) |
-                          int64_t(l0->per_cell ? 1 : 0);
-      if (!b->gexec[slot] || b->gkey[slot] != key) {
-        if (b->gexec[slot]) {
-          // the old graph may still be running: let it finish first
-          e = hipStreamSynchronize(b->stream);
-          if (e == hipSuccess) e = hipGraphExecDestroy(b->gexec[slot]);
-          b->gexec[slot] = nullptr;
-          b->gkey[slot] = -1;
-        }
-        hipGraph_t gr = nullptr;
-        if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed);
-        if (e == hipSuccess) {
-          hipError_t el = hipSuccess;
-          for (int j = 0; j < cnt && el == hipSuccess; ++j) {
-            BatchStepArgs bj = ba;
-            bj.row = slot * b->chunk + j;
-            bj.codes = rows0(slot, j);
-            bj.ins = ins0(slot, j);
-            bj.parity = j & 1;
-            bj.q_first = 0;
-            el = launch_step_batch(bj, l0->split, l0->per_cell, false, grouped, b->cap);
-          }
-          e = hipStreamEndCapture(b->cap, &gr);
-          if (el != hipSuccess) e = el;
-        }
-        if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec[slot], gr, nullptr, nullptr, 0);
-        if (gr) (void)hipGraphDestroy(gr);
-        if (e != hipSuccess) {
-          for (wlbm_lattice* l : b->lats) l->broken = true;
-          return fail(WLBM_EHIP, "batch graph capture failed: %s", hipGetErrorString(e));
-        }
-        b->gkey[slot] = key;
-      }
-      e = hipGraphLaunch(b->gexec[slot], b->stream);
-      if (e != hipSuccess) {
-        for (wlbm_lattice* l : b->lats) l->broken = true;
-        return fail(WLBM_EHIP, "batch graph launch failed: %s", hipGetErrorString(e));
-      }
-      done += cnt;
-      continue;
-    }
-    for (int j = 0; j < cnt; ++j) {
-      const int64_t k = done + j;
-      const bool flux = k >= flux_from;
-      ba.row = slot * b->chunk + j;
-      ba.codes = rows0(slot, j);
-      ba.ins = ins0(slot, j);
-      ba.parity = int(k & 1);
-      ba.q_first = (flux && k == flux_from) ? 1 : 0;
-      e = launch_step_batch(ba, l0->split, l0->per_cell, flux, grouped, b->stream);
-      for (int jl = 0; jl < n && e == hipSuccess; ++jl) {
-        wlbm_lattice* l = b->lats[jl];
-        if (!l->nsrc) continue;
-        const int out = 1 - (l->cur ^ int(k & 1));
-        e = launch_apply_sources(l->g, l->ptr(l->c.e[out]), l->ptr(l->c.E[out]), l->src_cells,
-                                 l->src_vals, l->nsrc, b->stream);
-      }
-      if (e != hipSuccess) {
-        for (wlbm_lattice* l : b->lats) l->broken = true;
-        return fail(WLBM_EHIP, "batch step launch failed: %s", hipGetErrorString(e));
-      }
-    }
-    done += cnt;
-  }
-  for (int j = 0; j < n; ++j) {
-    wlbm_lattice* l = b->lats[j];
-    l->tas = tas[size_t(b->group[j])];
-    l->cur ^= int(nsteps & 1);
-    l->flux_valid = l->flux_window > 0 && nsteps >= l->flux_window;
-  }
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_batch_set_graphs(wlbm_batch* b, int32_t on) {
-  if (!b) return fail(WLBM_EINVAL, "batch is NULL");
-  if (on != 0 && on != 1) return fail(WLBM_EINVAL, "on must be 0 or 1");
-  b->use_graphs = on != 0;
-  return WLBM_OK;
-}
-
-wlbm_status wlbm_batch_destroy(wlbm_batch* b) {
-  if (!b) return WLBM_OK;
-  hipError_t e = hipStreamSynchronize(b->stream);
-  for (int k = 0; k < 2; ++k) {
-    if (b->gexec[k]) (void)hipGraphExecDestroy(b->gexec[k]);
-    if (b->pinned[k]) (void)hipHostFree(b->pinned[k]);
-    if (b->pinned_ins[k]) (void)hipHostFree(b->pinned_ins[k]);
-    if (b->ev[k]) (void)hipEventDestroy(b->ev[k]);
-  }
-  if (b->cap) (void)hipStreamDestroy(b->cap);
-  if (b->table) (void)hipHostFree(b->table);
-  if (b->table_ev) (void)hipEventDestroy(b->table_ev);
-  delete b;
-  if (e != hipSuccess) return fail(WLBM_EHIP, "stream sync at destroy: %s", hipGetErrorString(e));
-  return WLBM_OK;
-}
-
-
-wlbm_status wlbm_autotune(wlbm_lattice* l, void* d_state, size_t bytes, int32_t steps,
-                          float* ms_by_split, int32_t* chosen) {
-  wlbm_status st = check_lat(l);
-  if (st) return st;
-  if (steps < 1 || steps > 10000) return fail(WLBM_EINVAL, "steps must be in 1 .. 10000");
-  if (l->tas.n + steps + 2 > kMaxSteps) return fail(WLBM_EINVAL, "step count would overflow");
-  const int64_t step0 = l->tas.n;
-  const bool flux_valid = l->flux_valid;
-  const int flux_window = l->flux_window;
-  const int keep_split = l->split;
-  const int keep_fusion = l->p.step_fusion;
-  st = wlbm_save_state(l, d_state, bytes);
-  if (st) return st;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIP_TRY(hipEventCreate(&e0));
-  hipError_t he = hipEventCreate(&e1);
-  if (he != hipSuccess) {
-    (void)hipEventDestroy(e0);
-    return fail(WLBM_EHIP, "hipEventCreate failed: %s", hipGetErrorString(he));
-  }
-  const int cand[3] = {1, 2, 4};
-  float best = 0.f;
-  int best_split = keep_split;
-  bool have = false;
-  l->flux_window = 0;  // the tuning steps leave the flux-window sums alone
-  l->p.step_fusion = 0;  // the split is the single-step kernel's: time that one
-  for (int k = 0; k < 3 && st == WLBM_OK; ++k) {
-    float ms = -1.f;
-    if (l->p.q % (kMaxGroupPlanes * cand[k]) == 0 &&
-        step_batch_lds_bytes(l->p.q, cand[k]) <= 48 * 1024) {
-      l->split = cand[k];
-      st = run_steps(l, 2, nullptr, 0);  // warm-up
-      if (!st && (he = hipEventRecord(e0, l->stream)) != hipSuccess)
-        st = fail(WLBM_EHIP, "hipEventRecord failed: %s", hipGetErrorString(he));
-      if (!st) st = run_steps(l, steps, nullptr, 0);
-      if (!st && (he = hipEventRecord(e1, l->stream)) != hipSuccess)
-        st = fail(WLBM_EHIP, "hipEventRecord failed: %s", hipGetErrorString(he));
-      if (!st && (he = hipEventSynchronize(e1)) != hipSuccess)
-        st = fail(WLBM_EHIP, "hipEventSynchronize failed: %s", hipGetErrorString(he));
-      if (!st && (he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
-        st = fail(WLBM_EHIP, "hipEventElapsedTime failed: %s", hipGetErrorString(he));
-      if (!st) {
-        ms /= float(steps);
-        if (!have || ms < best) {
-          best = ms;
-          best_split = cand[k];
-          have = true;
-        }
-      }
-      if (!st) st = wlbm_load_state(l, d_state, bytes, step0);
-    }
-    if (ms_by_split) ms_by_split[k] = ms;
-  }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  l->flux_window = flux_window;
-  l->p.step_fusion = keep_fusion;
-  if (st) {
-    l->split = keep_split;
-    return st;
-  }
-  l->split = best_split;
-  l->flux_valid = flux_valid;
-  if (chosen) *chosen = best_split;
-  return WLBM_OK;
-}
-
-
 wlbm_status wlbm_read_flux_mean(wlbm_lattice* l, int32_t x0, int32_t x1, int32_t averaged,
                                 double* qx_mean, double* qy_mean) {
   wlbm_status st = check_lat(l);
@@ -1745,7 +833,7 @@ wlbm_status wlbm_read_flux_mean(wlbm_lattice* l, int32_t x0, int32_t x1, int32_t
 
 int64_t wlbm_step_count(const wlbm_lattice* l) { return l ? l->tas.n : -1; }
 
-const char* wlbm_last_error(void) { return g_last_error.c_str(); }
+const char* wlbm_last_error(void) { return wlbm::last_error_text(); }
 
 wlbm_status wlbm_destroy(wlbm_lattice* l) {
   if (!l) return WLBM_OK;
@@ -1754,7 +842,6 @@ wlbm_status wlbm_destroy(wlbm_lattice* l) {
     if (l->pinned[k]) (void)hipHostFree(l->pinned[k]);
     if (l->pinned_pulls[k]) (void)hipHostFree(l->pinned_pulls[k]);
     if (l->ev[k]) (void)hipEventDestroy(l->ev[k]);
-    if (l->tev[k]) (void)hipEventDestroy(l->tev[k]);
   }
   delete l;
   if (e != hipSuccess) return fail(WLBM_EHIP, "stream sync at destroy: %s", hipGetErrorString(e));

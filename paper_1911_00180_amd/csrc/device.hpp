@@ -124,6 +124,9 @@ int fused_row_candidates(int ny, int k, int* cand, int max_cand);
 // Whether the multi-step kernels take this lattice: q a multiple of 8 up to
 // 64 or of 16 up to 128, nx >= 8, ny >= 2.
 bool fused_supported(int q, int nx, int ny);
+// Resident blocks per CU of the k-step kernel for q directions (occupancy
+// query of the runtime; 0 if it fails).
+int fused_blocks_per_cu(int q, int k, bool per_cell);
 
 // One time step of n lattices in one launch (same split, per-cell field use
 // and step; lattices with the same q, direction set and grid speeds share a

@@ -553,6 +553,46 @@ int fused_row_candidates(int ny, int k, int* cand, int max_cand) {
   return n;
 }
 
+template <int NW, int SH>
+int blocks_per_cu_tmpl(int k, bool wf) {
+  int n = 0;
+  hipError_t e = hipSuccess;
+  const int bs = 64 * NW;
+  if (k == 2)
+    e = wf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stepk<NW, SH, true, 2>, bs, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stepk<NW, SH, false, 2>, bs, 0);
+  else if (k == 3)
+    e = wf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stepk<NW, SH, true, 3>, bs, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stepk<NW, SH, false, 3>, bs, 0);
+  else
+    e = wf ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stepk<NW, SH, true, 4>, bs, 0)
+           : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stepk<NW, SH, false, 4>, bs, 0);
+  return e == hipSuccess ? n : 0;
+}
+
+int fused_blocks_per_cu(int q, int k, bool per_cell) {
+  if (q <= 64) {
+    switch (q / 8) {
+      case 1: return blocks_per_cu_tmpl<1, 8>(k, per_cell);
+      case 2: return blocks_per_cu_tmpl<2, 8>(k, per_cell);
+      case 3: return blocks_per_cu_tmpl<3, 8>(k, per_cell);
+      case 4: return blocks_per_cu_tmpl<4, 8>(k, per_cell);
+      case 5: return blocks_per_cu_tmpl<5, 8>(k, per_cell);
+      case 6: return blocks_per_cu_tmpl<6, 8>(k, per_cell);
+      case 7: return blocks_per_cu_tmpl<7, 8>(k, per_cell);
+      case 8: return blocks_per_cu_tmpl<8, 8>(k, per_cell);
+      default: return 0;
+    }
+  }
+  switch (q / 16) {
+    case 5: return blocks_per_cu_tmpl<5, 16>(k, per_cell);
+    case 6: return blocks_per_cu_tmpl<6, 16>(k, per_cell);
+    case 7: return blocks_per_cu_tmpl<7, 16>(k, per_cell);
+    case 8: return blocks_per_cu_tmpl<8, 16>(k, per_cell);
+    default: return 0;
+  }
+}
+
 // Waves per block: one per 8 directions up to q = 64, one per 16 up to 128.
 bool fused_supported(int q, int nx, int ny) {
   return nx >= 2 * kGhost && ny >= 2 && q % kMaxGroupPlanes == 0 &&

@@ -555,97 +555,6 @@ __global__ __launch_bounds__(kBlock) void k_scale_pair(int n, const float* ax, c
   by[c] = ay[c] * s;
 }
 
-// Deterministic block sum of three doubles in shared memory.
-__device__ void block_sum3(double* sh, double a, double b, double c, double* out) {
-  sh[threadIdx.x] = a;
-  sh[kBlock + threadIdx.x] = b;
-  sh[2 * kBlock + threadIdx.x] = c;
-  __syncthreads();
-  for (int s = kBlock / 2; s > 0; s >>= 1) {
-    if (threadIdx.x < s) {
-      sh[threadIdx.x] += sh[threadIdx.x + s];
-      sh[kBlock + threadIdx.x] += sh[kBlock + threadIdx.x + s];
-      sh[2 * kBlock + threadIdx.x] += sh[2 * kBlock + threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    out[0] = sh[0];
-    out[1] = sh[kBlock];
-    out[2] = sh[2 * kBlock];
-  }
-}
-
-__global__ __launch_bounds__(kBlock) void k_totals_partial(const Geometry g, const float* e,
-                                                          const float* E, const float* sxtab,
-                                                          const float* sytab,
-                                                          double* partials) {
-  __shared__ double sh[3 * kBlock];
-  const long long ncell = (long long)g.nx * g.ny;
-  double se = 0.0, sqx = 0.0, sqy = 0.0;
-  for (long long c = (long long)blockIdx.x * kBlock + threadIdx.x; c < ncell;
-       c += (long long)gridDim.x * kBlock) {
-    const long long o = cell(int(c % g.nx), int(c / g.nx), g.pitch);
-    se += double(E[o]);
-    double ax = 0.0, ay = 0.0;
-    for (int i = 0; i < g.q; ++i) {
-      const double v = e[(long long)i * g.plane + o];
-      ax += v * double(sxtab[i]);
-      ay += v * double(sytab[i]);
-    }
-    sqx += ax;
-    sqy += ay;
-  }
-  block_sum3(sh, se, sqx, sqy, partials + 3 * blockIdx.x);
-}
-
-__global__ __launch_bounds__(kBlock) void k_totals_final(const double* partials, int nb,
-                                                        double* out) {
-  __shared__ double sh[3 * kBlock];
-  double a = 0.0, b = 0.0, c = 0.0;
-  for (int k = threadIdx.x; k < nb; k += kBlock) {
-    a += partials[3 * k];
-    b += partials[3 * k + 1];
-    c += partials[3 * k + 2];
-  }
-  block_sum3(sh, a, b, c, out);
-}
-
-// Sums of the heat flux over the columns x0 <= x < x1 (all rows), in
-// float64: from the flux-window sums (window mode) or from the populations.
-__global__ __launch_bounds__(kBlock) void k_flux_sum_partial(const Geometry g, const float* e,
-                                                            const float* sxtab,
-                                                            const float* sytab,
-                                                            const float* qsx, const float* qsy,
-                                                            int window, int x0, int x1,
-                                                            double* partials) {
-  __shared__ double sh[3 * kBlock];
-  const int w = x1 - x0;
-  const long long n = (long long)w * g.ny;
-  double sx = 0.0, sy = 0.0;
-  for (long long c = (long long)blockIdx.x * kBlock + threadIdx.x; c < n;
-       c += (long long)gridDim.x * kBlock) {
-    const int x = x0 + int(c % w);
-    const int y = int(c / w);
-    if (window) {
-      const long long o = (long long)y * g.nx + x;
-      sx += double(qsx[o]);
-      sy += double(qsy[o]);
-    } else {
-      const long long o = cell(x, y, g.pitch);
-      double ax = 0.0, ay = 0.0;
-      for (int i = 0; i < g.q; ++i) {
-        const double v = e[(long long)i * g.plane + o];
-        ax += v * double(sxtab[i]);
-        ay += v * double(sytab[i]);
-      }
-      sx += ax;
-      sy += ay;
-    }
-  }
-  block_sum3(sh, sx, sy, 0.0, partials + 3 * blockIdx.x);
-}
-
 __device__ __forceinline__ double corrected(double mfp, double lam, double f, int corr) {
   const double W = isinf(mfp) ? 0.0 : 1.0 / mfp;
   if (!corr) return W;
@@ -786,33 +695,6 @@ hipError_t launch_scale_pair(int n, const float* ax, const float* ay, float scal
                              float* by, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_pair, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, ax, ay,
                      scale, bx, by);
-  return hipGetLastError();
-}
-
-hipError_t launch_totals(const Geometry& g, const float* e, const float* E, const float* sxtab,
-                         const float* sytab, double* partials, int max_blocks, double* out,
-                         hipStream_t s) {
-  const long long need = ((long long)g.nx * g.ny + kBlock - 1) / kBlock;
-  const int nb = int(need < max_blocks ? need : max_blocks);
-  hipLaunchKernelGGL(k_totals_partial, dim3(nb), dim3(kBlock), 0, s, g, e, E, sxtab, sytab,
-                     partials);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(kBlock), 0, s, partials, nb, out);
-  return hipGetLastError();
-}
-
-hipError_t launch_flux_sum(const Geometry& g, const float* e, const float* sxtab,
-                           const float* sytab, const float* qsx, const float* qsy, int window,
-                           int x0, int x1, double* partials, int max_blocks, double* out,
-                           hipStream_t s) {
-  const long long need = ((long long)(x1 - x0) * g.ny + kBlock - 1) / kBlock;
-  const int nb = int(need < max_blocks ? need : max_blocks);
-  hipLaunchKernelGGL(k_flux_sum_partial, dim3(nb), dim3(kBlock), 0, s, g, e, sxtab, sytab, qsx,
-                     qsy, window, x0, x1, partials);
-  hipError_t err = hipGetLastError();
-  if (err != hipSuccess) return err;
-  hipLaunchKernelGGL(k_totals_final, dim3(1), dim3(kBlock), 0, s, partials, nb, out);
   return hipGetLastError();
 }
 

@@ -1,4 +1,4 @@
-"""In-plane conductivity of thin films versus Knudsen number (Sec. 3.4).
+"""In-plane conductivity of thin films versus Knudsen number (Sec. 3.5).
 
 A film of thickness Ny cells with adiabatic diffuse walls (y) is held
 between blackbody columns x = 0 (T = 1) and x = Nx - 1 (T = 0), starting

@@ -158,14 +158,22 @@ class Lattice:
         return W.wlbm_get_dir_split(self.handle)
 
     def block_rows(self, k: int) -> int:
-        """Output rows per block the library chose for k = 2, 3 or 4 steps per
-        launch (0 while still timing candidates)."""
+        """Output rows per block of the kernel for k = 2, 3 or 4 steps per
+        launch (fixed, tuned or the launch model's pick; 0 if this lattice runs
+        one step per launch)."""
         return W.wlbm_get_block_rows(self.handle, k)
 
     def set_block_rows(self, k: int, rows: int) -> None:
-        """Fix the output rows per block for k steps per launch (0: time the
-        candidates again)."""
+        """Fix the output rows per block for k steps per launch (0: back to
+        the launch model's pick)."""
         W.wlbm_set_block_rows(self.handle, k, rows)
+
+    def tune_block_rows(self, k: int, launches: int = 6) -> int:
+        """Time every candidate block height for k steps per launch on the
+        current state (restored afterwards) and keep the fastest."""
+        self._sync_stream()
+        buf = torch.empty(self.state_bytes, dtype=torch.uint8, device=self.device)
+        return W.wlbm_tune_block_rows(self.handle, buf.data_ptr(), buf.numel(), k, launches)
 
     def set_dir_split(self, split: int) -> None:
         W.wlbm_set_dir_split(self.handle, split)
@@ -198,8 +206,8 @@ class Lattice:
 class Batch:
     """Lattices advanced together, one kernel launch per step (same step
     count, split, per-cell field use and flux window; q, direction sets and
-    grid speeds may differ); whole schedule chunks run as one HIP graph
-    launch unless ``set_graphs(False)``."""
+    grid speeds may differ); ``set_graphs(True)`` replays whole schedule
+    chunks as one HIP graph launch."""
 
     def __init__(self, lattices):
         self.lattices = list(lattices)

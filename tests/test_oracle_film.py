@@ -4,7 +4,7 @@
   points away from the hot wall carries w_i T_h once it has crossed the film,
   the others carry T_c = 0 (or the initial 0), so the interior flux is
   exactly T_h * sum_{s_x > 0} w_i s_x,i.
-* Ordering (Sec. 3.4: boundary scattering lowers the in-plane conductivity):
+* Ordering (Sec. 3.5: boundary scattering lowers the in-plane conductivity):
   kappa_eff/kappa falls as Kn grows, and diffuse walls conduct less than no
   walls at the same Kn.
 """
