@@ -218,6 +218,22 @@ wlbm_status wlbm_read_populations(wlbm_lattice* lat, float* d_e);
  * Output pointers may be NULL. */
 wlbm_status wlbm_read_totals(wlbm_lattice* lat, double* energy, double* qx_sum, double* qy_sum);
 
+/* For callers that cannot allocate or wait (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the totals of
+ * wlbm_read_totals, written in stream order to the caller's device buffer
+ * d_totals ([3] float64: energy, qx_sum, qy_sum), with no host wait and no
+ * finiteness check.  Same kernels and summation order as wlbm_read_totals,
+ * so the values are identical.  The float64 block partials live in a fixed
+ * array of the library (24 KiB per GPU, looked up at wlbm_create and held
+ * until the process ends) instead of the lattice workspace; the reduction
+ * uses at most its 1024 partials whatever the lattice size, so no size is
+ * refused.  Every call on one GPU shares that array: calls that overlap on
+ * one GPU (different streams, or threads) race and must be ordered by the
+ * caller.  Nothing needs clearing between calls (each call writes every
+ * partial it reads).  The call allocates nothing and calls no allocating
+ * routine. */
+wlbm_status wlbm_read_totals_noalloc(wlbm_lattice* lat, double* d_totals);
+
 /* Mean heat flux over the columns x0 <= x < x1 and all rows, summed in
  * float64 in a fixed order: of the trailing flux window of the last
  * wlbm_step call (averaged = 1; WLBM_ESTATE without a complete window) or of

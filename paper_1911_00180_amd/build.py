@@ -18,7 +18,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libwormlbm.so")
 SOURCES = ["tables.cpp", "kernels.hip", "fused.hip", "adjoint.hip", "reduce.hip", "api.hip",
-           "api_states.hip", "api_batch.hip", "api_tune.hip"]
+           "api_states.hip", "api_batch.hip", "api_tune.hip", "api_noalloc.hip"]
 # Stand-alone HBM stream kernel used by the benchmark to measure the
 # practical read+write ceiling of the device (not part of the library).
 PROBE_LIB = os.path.join(PKG, "libwlbm_probe.so")

@@ -324,6 +324,17 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
   l->book.reset(&l->dirs);
   l->stream = static_cast<hipStream_t>(stream);
   l->ws = static_cast<char*>(d_workspace);
+  {
+    // the device that holds the workspace (the caller's current device if
+    // the runtime cannot tell)
+    hipPointerAttribute_t attr{};
+    if (hipPointerGetAttributes(&attr, d_workspace) != hipSuccess ||
+        attr.type != hipMemoryTypeDevice || attr.device < 0) {
+      (void)hipGetLastError();
+      if (hipGetDevice(&attr.device) != hipSuccess) attr.device = 0;
+    }
+    l->device = attr.device;
+  }
   l->c = carve(*p);
   l->chunk = chunk_steps(*p);
   l->W = float(uniform_wcorr(*p, l->dirs.lambda_corr, nullptr));
@@ -385,6 +396,8 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
     wlbm_status s = fail(WLBM_EHIP, "workspace set-up failed: %s", hipGetErrorString(e));
     return cleanup(s);
   }
+  const wlbm_status ns = noalloc_setup(l->device);
+  if (ns) return cleanup(ns);
   *out = l;
   return WLBM_OK;
 }

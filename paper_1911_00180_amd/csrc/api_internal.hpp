@@ -63,6 +63,7 @@ struct wlbm_lattice {
   wlbm::TasState tas;
   wlbm::Geometry g{};
   hipStream_t stream = nullptr;
+  int device = 0;           // GPU holding the workspace
   char* ws = nullptr;
   wlbm::Carve c{};
   int cur = 0;              // population buffer holding the current state
@@ -119,5 +120,7 @@ bool lattice_fuses(const wlbm_lattice* l);
 // Output rows per block of the k-step kernel for the lattice's current
 // weight mode: the fixed or tuned height, else the launch model's pick.
 int block_rows_for(const wlbm_lattice* l, int k);
+// Per-device set-up of the allocation-free readout (api_noalloc.hip).
+wlbm_status noalloc_setup(int device);
 
 }  // namespace wlbm
