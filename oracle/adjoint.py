@@ -76,33 +76,88 @@ def transposed_step(lat: Lattice, n: int, lam: np.ndarray):
     return out, G
 
 
-def probe_loss(cfg: Config, T0, nsteps, probes, every, targets, keep_states=False):
+def probe_loss(cfg: Config, T0, nsteps, probes, every, targets, keep_states=False,
+               checkpoint_every=None):
     """Forward run and loss.  probes: int [P, 2] (x, y); targets:
-    [nsteps // every, P]."""
+    [nsteps // every, P].  keep_states: also return every state e^0 ..
+    e^nsteps; checkpoint_every = K: return the states e^0, e^K, e^2K, ... as a
+    dict {step: state} instead."""
     if cfg.y_edge == DIFFUSE:
         raise ValueError("the adjoint covers periodic and blackbody edges")
     lat = Lattice(cfg)
     lat.set_temperature(np.asarray(T0, dtype=np.float64))
     lat.schedule(nsteps)
     states = [lat.e.copy()] if keep_states else None
+    ck = {0: lat.e.copy()} if checkpoint_every else None
     loss = 0.0
     px, py = probes[:, 0], probes[:, 1]
     for n in range(1, nsteps + 1):
         lat.step()
         if keep_states:
             states.append(lat.e.copy())
+        if ck is not None and n % checkpoint_every == 0:
+            ck[n] = lat.e.copy()
         if n % every == 0:
             T = lat.temperature()
             d = T[py, px] - targets[n // every - 1]
             loss += float(np.sum(d * d))
-    return loss, lat, states
+    return loss, lat, (ck if ck is not None else states)
 
 
-def probe_loss_gradients(cfg: Config, T0, nsteps, probes, every, targets):
+def probe_temperatures(cfg: Config, T0, nsteps, probes, every) -> np.ndarray:
+    """T^k(p) of a forward run at steps k = every, 2 every, ..., nsteps:
+    [nsteps // every, P]."""
+    lat = Lattice(cfg)
+    lat.set_temperature(np.asarray(T0, dtype=np.float64))
+    lat.schedule(nsteps)
+    px, py = probes[:, 0], probes[:, 1]
+    out = []
+    for n in range(1, nsteps + 1):
+        lat.step()
+        if n % every == 0:
+            out.append(lat.temperature()[py, px].copy())
+    return np.array(out)
+
+
+class _Recomputed:
+    """States e^n of a forward run from checkpoints every K steps: the states
+    of the segment holding n are recomputed from its checkpoint by the
+    forward step (the reverse pass asks for them in decreasing order, so one
+    segment is held at a time)."""
+
+    def __init__(self, lat: Lattice, ck: dict, K: int, nsteps: int):
+        self.lat, self.ck, self.K, self.nsteps = lat, ck, K, nsteps
+        self.base, self.seg = None, None
+
+    def __getitem__(self, n: int) -> np.ndarray:
+        base = (n // self.K) * self.K
+        if base != self.base:
+            self.lat.e = self.ck[base].copy()
+            self.lat.n = base
+            seg = [self.lat.e.copy()]
+            for _ in range(min(self.K, self.nsteps + 1 - base) - 1):
+                self.lat.step()
+                seg.append(self.lat.e.copy())
+            self.base, self.seg = base, seg
+        return self.seg[n - base]
+
+
+def probe_loss_gradients(cfg: Config, T0, nsteps, probes, every, targets,
+                         checkpoint_every=None):
     """Loss and its gradients by the transposed recursion.
 
+    checkpoint_every = K keeps only every K-th forward state and recomputes
+    the others segment by segment during the reverse pass (same arithmetic,
+    same results; for runs whose states do not all fit in memory).
+
     Returns (loss, dL/dmfp [ny, nx], dL/dT0 [ny, nx], dict of dL/dT_wall)."""
-    loss, lat, states = probe_loss(cfg, T0, nsteps, probes, every, targets, keep_states=True)
+    if checkpoint_every:
+        loss, lat, ck = probe_loss(cfg, T0, nsteps, probes, every, targets,
+                                   checkpoint_every=checkpoint_every)
+        states = _Recomputed(lat, ck, checkpoint_every, nsteps)
+    else:
+        loss, lat, states = probe_loss(cfg, T0, nsteps, probes, every, targets,
+                                       keep_states=True)
     c = cfg
     own = _wall_owner(c)
     wall = own != ""
@@ -126,7 +181,7 @@ def probe_loss_gradients(cfg: Config, T0, nsteps, probes, every, targets):
             gTb[key] += float(contrib[own == key].sum())
         lam[:, wall] = 0.0
 
-    lam = np.zeros_like(states[0])
+    lam = np.zeros((c.q, c.ny, c.nx))
     lam += seed(nsteps)[None]
     absorb_walls(lam)
     for n in range(nsteps, 0, -1):
