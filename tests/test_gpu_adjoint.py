@@ -15,6 +15,8 @@ the FP32 error grows at most like n * eps (n = 60 steps, eps = 6e-8, about
 differences of the FP32 forward (full size) carry their own truncation and
 rounding error and are held to 2e-3.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -23,6 +25,10 @@ from oracle import worm_lbm as o
 from paper_1911_00180_amd import inputs
 
 pytestmark = pytest.mark.gpu
+
+# Gradient tolerance of the 1000-step full-size case (relative to the
+# largest value of each gradient), as for the 60-step cases.
+GRAD_RTOL_1000 = 1e-5
 
 torch = pytest.importorskip("torch")
 
@@ -184,6 +190,54 @@ def test_adjoint_rejects_diffuse_walls():
     ws = torch.empty(W.wlbm_adjoint_bytes(lat.handle), dtype=torch.uint8, device="cuda")
     with pytest.raises(W.WormLBMError):
         W.wlbm_adjoint_begin(lat.handle, ws.data_ptr(), ws.numel(), 10)
+    lat.close()
+
+
+GOLDEN_INVERSE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                              "inverse256_q64.npz")
+
+
+def _golden_input_hash(mfp, tgt, T0, probes):
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "make_inverse_reference", os.path.join(os.path.dirname(GOLDEN_INVERSE),
+                                               "make_inverse_reference.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod.input_hash(mfp, tgt, T0, probes)
+
+
+def test_c4_full_size_against_oracle_gradients():
+    """The inverse problem at its stated size (256 x 256, Q = 64, per-cell MFP
+    field, blackbody x walls 0.5 / 0, periodic y, 1000 steps, 32 probes, loss
+    every 10 steps, checkpoints every 50) against the FP64 oracle's stored
+    run (tests/golden/inverse256_q64.npz, written by make_inverse_reference.py
+    from the oracle alone, targets included): probe temperatures within
+    1e-5 of their largest value, the loss within 1e-4, and dL/dMFP, dL/dT0
+    and the wall gradients element by element against their largest values
+    (tolerance in the module docstring)."""
+    from paper_1911_00180_amd.autodiff import ProbeSeries
+    from paper_1911_00180_amd.lattice import Lattice
+    ref = np.load(GOLDEN_INVERSE, allow_pickle=False)
+    n, mfp, tgt, T0, probes = inputs.inverse_problem_256()
+    assert str(ref["input_hash"]) == _golden_input_hash(mfp, tgt, T0, probes)
+    lat = Lattice(n, n, 64, mfp=16.0, x_edge="blackbody", y_edge="periodic")
+    series = ProbeSeries(lat, probes, 1000, 10, checkpoint_every=50)
+    walls = np.array([0.5, 0.0, 0.0, 0.0], dtype=np.float32)
+    out, loss, g_mfp, g_T0, g_w = _gpu_grads(series, mfp, T0, walls,
+                                             ref["targets"].astype(np.float32))
+    T_ref = ref["T_probes"]
+    err_T = np.abs(out - T_ref).max() / np.abs(T_ref).max()
+    err_mfp = np.abs(g_mfp - ref["g_mfp"]).max() / np.abs(ref["g_mfp"]).max()
+    err_T0 = np.abs(g_T0 - ref["g_T0"]).max() / np.abs(ref["g_T0"]).max()
+    err_w = np.abs(g_w - ref["g_walls"]).max() / np.abs(ref["g_walls"]).max()
+    print(f"probe T {err_T:.2e}, loss {abs(loss - ref['loss']) / ref['loss']:.2e}, "
+          f"dL/dMFP {err_mfp:.2e}, dL/dT0 {err_T0:.2e}, walls {err_w:.2e}")
+    assert err_T <= 1e-5
+    assert abs(loss - float(ref["loss"])) <= 1e-4 * float(ref["loss"])
+    assert err_mfp <= GRAD_RTOL_1000
+    assert err_T0 <= GRAD_RTOL_1000
+    assert err_w <= GRAD_RTOL_1000
     lat.close()
 
 

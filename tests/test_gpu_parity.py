@@ -258,6 +258,7 @@ def test_full_size_1024_energy_and_sampled_cells():
     half = n + 2
     samples = [(x0, y0), ((x0 + 20) % nx, (y0 - 13) % ny), (0, 0), (nx - 1, 5)]
     samples += [tuple(int(v) for v in rng.integers(0, nx, 2)) for _ in range(2)]
+    got, want, tmax = [], [], 0.0
     for (sx, sy) in samples:
         xs = (np.arange(sx - half, sx + half + 1)) % nx
         ys = (np.arange(sy - half, sy + half + 1)) % ny
@@ -265,8 +266,15 @@ def test_full_size_1024_energy_and_sampled_cells():
         ora = _oracle(2 * half + 1, 2 * half + 1, q, 102.4)
         ora.set_temperature(win)
         ora.run(n)
-        want = ora.temperature()[half, half]
-        assert abs(T[sy, sx] - want) <= RTOL * max(T0.max(), 1e-30), (sx, sy)
+        Tw = ora.temperature()
+        want.append(Tw[half, half])
+        got.append(T[sy, sx])
+        tmax = max(tmax, float(np.abs(Tw).max()))
+    # against the largest |T| of the oracle windows after the run (the
+    # pulse's window holds the field's maximum), not of T0
+    assert tmax > 0.0
+    for (sx, sy), g, w in zip(samples, got, want):
+        assert abs(g - w) <= RTOL * tmax, (sx, sy, g, w, tmax)
 
 
 def _window(s, half, n, walled):
