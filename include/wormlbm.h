@@ -102,12 +102,13 @@ typedef struct wlbm_params {
                              /* (Eq. adiabatic-specular); 1 - p is scattered     */
                              /* diffusely (Eq. adiabatic-diffuse)                */
   int32_t step_fusion;       /* time steps per kernel launch where possible      */
-                             /* (periodic edges, no sources, q a multiple of 8   */
-                             /* up to 64 or of 16 up to 128, nx >= 8, ny >= 2,   */
-                             /* outside flux windows and tapes): 1 = default     */
-                             /* (up to four), 2 .. 4 = at most that many, 0 =    */
-                             /* one step per launch.  Results are identical to   */
-                             /* single steps in every case.                      */
+                             /* (any edges but partly specular walls, no         */
+                             /* sources, q a multiple of 8 up to 64 or of 16 up  */
+                             /* to 128, nx >= 8, ny >= 2, outside flux windows   */
+                             /* and tapes; periodic x with diffuse y: at most    */
+                             /* two): 1 = default (up to four), 2 .. 4 = at most */
+                             /* that many, 0 = one step per launch.  Results are */
+                             /* identical to single steps in every case.         */
   int32_t reserved[3];       /* must be zero                                     */
 } wlbm_params;
 
@@ -397,7 +398,8 @@ wlbm_status wlbm_set_block_rows(wlbm_lattice* lat, int32_t k, int32_t rows);
  * (wlbm_state_bytes bytes) and restored after each trial, so the lattice
  * ends where it started; the flux-window sums are not touched.  Waits for
  * the stream (not capturable).  WLBM_EINVAL if the lattice runs one step per
- * launch. */
+ * launch, or fewer than k (periodic x edges with diffuse y walls run at most
+ * two). */
 wlbm_status wlbm_tune_block_rows(wlbm_lattice* lat, void* d_state, size_t bytes, int32_t k,
                                  int32_t launches, int32_t* rows);
 

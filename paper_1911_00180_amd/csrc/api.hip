@@ -40,8 +40,9 @@ wlbm_status fail(wlbm_status st, const char* fmt, ...) {
 const char* last_error_text() { return g_last_error.c_str(); }
 
 bool fusable(const wlbm_params& p) {
-  return p.x_edge == WLBM_EDGE_PERIODIC && p.y_edge == WLBM_EDGE_PERIODIC &&
-         fused_supported(p.q, p.nx, p.ny);
+  // every edge type except partly specular y walls
+  const bool walls_ok = p.y_edge != WLBM_EDGE_DIFFUSE || p.y_specularity == 0.0;
+  return walls_ok && fused_supported(p.q, p.nx, p.ny);
 }
 
 int chunk_steps(const wlbm_params& p) { return p.sched_chunk ? p.sched_chunk : kDefaultChunk; }
@@ -71,6 +72,8 @@ Carve carve(const wlbm_params& p) {
   // per step, the multi-step kernels' pull offsets and selection-table
   // offsets of every direction (FusedArgs::pulls, FusedArgs::sels)
   c.pulls = take(fusable(p) ? size_t(4) * chunk_steps(p) * size_t(p.q) * sizeof(uint32_t) : 0);
+  // per step, the inward-weight sums of diffuse walls (FusedArgs::ins)
+  c.ins = take(fusable(p) ? size_t(2) * chunk_steps(p) * 4 * sizeof(float) : 0);
   c.wtab = take(size_t(p.q) * sizeof(float));
   c.sxtab = take(size_t(p.q) * sizeof(float));
   c.sytab = take(size_t(p.q) * sizeof(float));
@@ -127,6 +130,24 @@ int auto_split(int q) {
 
 bool lattice_fuses(const wlbm_lattice* l) {
   return l->p.step_fusion != 0 && l->nsrc == 0 && fusable(l->p);
+}
+
+// Along a diffuse wall the dependence reaches two columns per step, which
+// the ghost frame of a periodic x edge covers for two steps per launch.
+int fused_k_cap(const wlbm_lattice* l) {
+  return (l->g.x_edge == kPeriodic && l->g.y_edge == kDiffuse) ? 2 : 4;
+}
+
+// Automatic steps per launch, from measurements on MI355X: periodic
+// lattices gain up to four steps (1024^2 x 64: 1, 2, 3, 4 steps 552, 1001,
+// 1338, 1648 G updates/s); lattices with walls run a kernel with more
+// registers, and with q above 64 (16 directions a wave) or a per-cell field
+// two steps were fastest (512 x 256 x 128 diffuse film: 1, 2, 3, 4 steps 291,
+// 551, 426, 425 G updates/s).
+int fused_k_max(const wlbm_lattice* l) {
+  const bool walls = l->g.x_edge != kPeriodic || l->g.y_edge != kPeriodic;
+  const int k_auto = walls && (l->p.q > 64 || l->per_cell) ? 2 : 4;
+  return std::min(fused_k_cap(l), l->p.step_fusion == 1 ? k_auto : l->p.step_fusion);
 }
 
 }  // namespace wlbm
@@ -347,6 +368,7 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
     for (int k = 0; k < 2; ++k) {
       if (l->pinned[k]) (void)hipHostFree(l->pinned[k]);
       if (l->pinned_pulls[k]) (void)hipHostFree(l->pinned_pulls[k]);
+      if (l->pinned_ins[k]) (void)hipHostFree(l->pinned_ins[k]);
       if (l->ev[k]) (void)hipEventDestroy(l->ev[k]);
     }
     delete l;
@@ -358,6 +380,9 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
     if (e == hipSuccess && fusable(*p))
       e = hipHostMalloc(reinterpret_cast<void**>(&l->pinned_pulls[k]),
                         size_t(2) * l->chunk * p->q * sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess && fusable(*p))
+      e = hipHostMalloc(reinterpret_cast<void**>(&l->pinned_ins[k]),
+                        size_t(l->chunk) * 4 * sizeof(float), hipHostMallocDefault);
     if (e != hipSuccess) {
       wlbm_status s = fail(WLBM_ENOMEM, "hipHostMalloc failed: %s", hipGetErrorString(e));
       return cleanup(s);
@@ -591,7 +616,7 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
   // several steps per launch: not into a tape, and a lattice the multi-step
   // kernels are built for
   const bool fuse = !tape && lattice_fuses(l);
-  const int k_max = l->p.step_fusion == 1 ? 4 : l->p.step_fusion;
+  const int k_max = fused_k_max(l);
 
   int64_t done = 0;
   while (done < nsteps) {
@@ -640,10 +665,16 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
     uint8_t* dev_rows = reinterpret_cast<uint8_t*>(l->ws + l->c.sched) + size_t(slot) * l->chunk * q;
     uint32_t* dev_pulls =
         reinterpret_cast<uint32_t*>(l->ws + l->c.pulls) + size_t(2 * slot) * l->chunk * q;
+    float* dev_ins = reinterpret_cast<float*>(l->ws + l->c.ins) + size_t(slot) * l->chunk * 4;
     hipError_t e = hipMemcpyAsync(dev_rows, rows, size_t(cnt) * q, hipMemcpyHostToDevice, l->stream);
     if (e == hipSuccess && pw)
       e = hipMemcpyAsync(dev_pulls, pw, size_t(2 * cnt) * q * sizeof(uint32_t),
                          hipMemcpyHostToDevice, l->stream);
+    if (e == hipSuccess && pw) {
+      std::memcpy(l->pinned_ins[slot], insums.data(), size_t(cnt) * 4 * sizeof(float));
+      e = hipMemcpyAsync(dev_ins, l->pinned_ins[slot], size_t(cnt) * 4 * sizeof(float),
+                         hipMemcpyHostToDevice, l->stream);
+    }
     if (e == hipSuccess) e = hipEventRecord(l->ev[slot], l->stream);
     if (e != hipSuccess) {
       l->broken = true;
@@ -676,17 +707,28 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
         a2.rows = block_rows_for(l, K);
         a2.strips_x = fused_strips_x(a.nx, K);
         a2.strips_y = (a.ny + a2.rows - 1) / a2.rows;
+        a2.x_edge = a.x_edge;
+        a2.y_edge = a.y_edge;
+        a2.t_x_lo = a.t_x_lo;
+        a2.t_x_hi = a.t_x_hi;
+        a2.t_y_lo = a.t_y_lo;
+        a2.t_y_hi = a.t_y_hi;
+        a2.codes = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j) * q);
+        a2.ins = dev_ins + size_t(4) * j;
         e = hipSuccess;
-        // the multi-step kernels read kGhost ghost columns, which other
-        // producers do not write: refresh the frame once before the first
-        // multi-step launch that follows them
+        // the multi-step kernels read kGhost ghost columns of periodic x
+        // edges, which other producers do not write: refresh the frame once
+        // before the first multi-step launch that follows them
+        const bool px = a.x_edge == kPeriodic, py = a.y_edge == kPeriodic;
         if (!l->ghosts_full) {
-          e = fill_ghosts(l->ptr(l->c.e[l->cur]), a.plane, q, a.nx, a.ny, a.pitch, l->stream);
+          e = fill_ghosts(l->ptr(l->c.e[l->cur]), a.plane, q, a.nx, a.ny, a.pitch, px, py,
+                          l->stream);
           if (e == hipSuccess)
-            e = fill_ghosts(l->ptr(l->c.E[l->cur]), a.plane, 1, a.nx, a.ny, a.pitch, l->stream);
+            e = fill_ghosts(l->ptr(l->c.E[l->cur]), a.plane, 1, a.nx, a.ny, a.pitch, px, py,
+                            l->stream);
         }
         if (e == hipSuccess && l->per_cell && !l->wf_ghosts_full) {
-          e = fill_ghosts(l->ptr(l->c.Wf), a.plane, 1, a.nx, a.ny, a.pitch, l->stream);
+          e = fill_ghosts(l->ptr(l->c.Wf), a.plane, 1, a.nx, a.ny, a.pitch, px, py, l->stream);
           if (e == hipSuccess) l->wf_ghosts_full = true;
         }
         if (e == hipSuccess) e = launch_fused(a2, K, l->per_cell, l->stream);
@@ -854,6 +896,7 @@ wlbm_status wlbm_destroy(wlbm_lattice* l) {
   for (int k = 0; k < 2; ++k) {
     if (l->pinned[k]) (void)hipHostFree(l->pinned[k]);
     if (l->pinned_pulls[k]) (void)hipHostFree(l->pinned_pulls[k]);
+    if (l->pinned_ins[k]) (void)hipHostFree(l->pinned_ins[k]);
     if (l->ev[k]) (void)hipEventDestroy(l->ev[k]);
   }
   delete l;

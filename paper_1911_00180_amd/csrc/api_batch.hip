@@ -23,17 +23,37 @@ struct BatchGroup {
   size_t stage = 0;               // offset of its rows in a pinned staging buffer
 };
 
+// Lattices of one group with the same padded geometry (row pitch and plane
+// size) share the pull offsets of the multi-step kernel.
+struct BatchGeo {
+  int group = 0;
+  int pitch = 0;
+  long long plane = 0;
+  size_t pulls = 0;               // workspace offset of its ring of pull offsets
+  size_t stage = 0;               // offset of its rows in a pinned staging buffer (words)
+};
+
 struct wlbm_batch {
   std::vector<wlbm_lattice*> lats;
   std::vector<int> group;         // group of each lattice
   std::vector<BatchGroup> groups;
+  std::vector<int> geo;           // geometry of each lattice
+  std::vector<BatchGeo> geos;
+  std::vector<size_t> sels;       // per group: workspace offset of its selection-offset ring
+  std::vector<size_t> sels_stage; // per group: its rows in the pinned staging (words)
   int qmax = 0;
   hipStream_t stream = nullptr;
   char* ws = nullptr;
   size_t off_args = 0, off_first = 0, off_rc = 0, off_ri = 0;
+  // multi-step launches: argument table, prefix of block counts and, per
+  // lattice, its rings (selection offsets, pull offsets, codes, wall sums)
+  size_t off_fargs = 0, off_ffirst = 0, off_fsel = 0, off_fpull = 0, off_fcode = 0,
+         off_fins = 0, table_bytes = 0;
   int chunk = 0;
   uint8_t* pinned[2] = {nullptr, nullptr};     // staging of the schedule rows of every group
   float* pinned_ins[2] = {nullptr, nullptr};   // staging of the per-step wall sums
+  uint32_t* pinned_sels[2] = {nullptr, nullptr};    // staging of the selection offsets
+  uint32_t* pinned_pulls[2] = {nullptr, nullptr};   // staging of the pull offsets
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_pending[2] = {false, false};
   int64_t chunk_counter = 0;
@@ -53,8 +73,9 @@ struct wlbm_batch {
 namespace {
 
 struct BatchCarve {
-  size_t args, first, rc, ri, total;
-  std::vector<size_t> sched, ins;   // per group
+  size_t args, first, rc, ri, fargs, ffirst, fsel, fpull, fcode, fins, total;
+  std::vector<size_t> sched, ins, sels;   // per group
+  std::vector<size_t> pulls;              // per geometry
 };
 
 bool same_directions(const wlbm_lattice* a, const wlbm_lattice* b) {
@@ -76,7 +97,32 @@ void form_groups(wlbm_lattice* const* lats, int n, std::vector<int>& group,
   }
 }
 
-BatchCarve batch_carve(int n, const std::vector<wlbm_lattice*>& leads, int chunk) {
+// Geometry index of each lattice: lattices of one group with the same row
+// pitch and plane size (first-seen order).
+void form_geos(wlbm_lattice* const* lats, int n, const std::vector<int>& group,
+               std::vector<int>& geo, std::vector<BatchGeo>& geos) {
+  geo.assign(size_t(n), -1);
+  geos.clear();
+  for (int j = 0; j < n; ++j) {
+    for (size_t k = 0; k < geos.size() && geo[j] < 0; ++k)
+      if (geos[k].group == group[j] && geos[k].pitch == lats[j]->g.pitch &&
+          geos[k].plane == lats[j]->g.plane)
+        geo[j] = int(k);
+    if (geo[j] < 0) {
+      geo[j] = int(geos.size());
+      BatchGeo g;
+      g.group = group[j];
+      g.pitch = lats[j]->g.pitch;
+      g.plane = lats[j]->g.plane;
+      geos.push_back(g);
+    }
+  }
+}
+
+// The argument tables come first and in one block (one upload per call);
+// the rings follow.
+BatchCarve batch_carve(int n, const std::vector<wlbm_lattice*>& leads,
+                       const std::vector<BatchGeo>& geos, int chunk) {
   BatchCarve c{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -88,10 +134,19 @@ BatchCarve batch_carve(int n, const std::vector<wlbm_lattice*>& leads, int chunk
   c.first = take(size_t(n + 1) * sizeof(int));
   c.rc = take(size_t(n) * sizeof(void*));   // per lattice: its group's schedule ring
   c.ri = take(size_t(n) * sizeof(void*));   // and ring of inward-weight sums
+  c.fargs = take(size_t(2) * n * sizeof(FusedArgs));
+  c.ffirst = take(size_t(n + 1) * sizeof(int));
+  c.fsel = take(size_t(n) * sizeof(void*));
+  c.fpull = take(size_t(n) * sizeof(void*));
+  c.fcode = take(size_t(n) * sizeof(void*));
+  c.fins = take(size_t(n) * sizeof(void*));
   for (const wlbm_lattice* l : leads) {
     c.sched.push_back(take(size_t(2) * chunk * l->p.q));
     c.ins.push_back(take(size_t(2) * chunk * 4 * sizeof(float)));
+    c.sels.push_back(take(size_t(2) * chunk * l->p.q * sizeof(uint32_t)));
   }
+  for (const BatchGeo& g : geos)
+    c.pulls.push_back(take(size_t(2) * chunk * leads[size_t(g.group)]->p.q * sizeof(uint32_t)));
   c.total = off;
   return c;
 }
@@ -128,7 +183,10 @@ wlbm_status wlbm_batch_bytes(wlbm_lattice* const* lats, int32_t n, size_t* bytes
   std::vector<int> group;
   std::vector<wlbm_lattice*> leads;
   form_groups(lats, n, group, leads);
-  *bytes = batch_carve(n, leads, lats[0]->chunk).total;
+  std::vector<int> geo;
+  std::vector<BatchGeo> geos;
+  form_geos(lats, n, group, geo, geos);
+  *bytes = batch_carve(n, leads, geos, lats[0]->chunk).total;
   return WLBM_OK;
 }
 
@@ -141,7 +199,10 @@ wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, 
   std::vector<int> group;
   std::vector<wlbm_lattice*> leads;
   form_groups(lats, n, group, leads);
-  const BatchCarve bc = batch_carve(n, leads, lats[0]->chunk);
+  std::vector<int> geo;
+  std::vector<BatchGeo> geos;
+  form_geos(lats, n, group, geo, geos);
+  const BatchCarve bc = batch_carve(n, leads, geos, lats[0]->chunk);
   if (!d_ws) return fail(WLBM_EINVAL, "batch workspace is NULL");
   if (reinterpret_cast<uintptr_t>(d_ws) % kAlign)
     return fail(WLBM_EINVAL, "batch workspace must be 256-byte aligned");
@@ -158,8 +219,15 @@ wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, 
   b->off_first = bc.first;
   b->off_rc = bc.rc;
   b->off_ri = bc.ri;
+  b->off_fargs = bc.fargs;
+  b->off_ffirst = bc.ffirst;
+  b->off_fsel = bc.fsel;
+  b->off_fpull = bc.fpull;
+  b->off_fcode = bc.fcode;
+  b->off_fins = bc.fins;
+  b->table_bytes = bc.fins + size_t(n) * sizeof(void*);
   b->chunk = lats[0]->chunk;
-  size_t stage = 0;
+  size_t stage = 0, stage_sels = 0;
   for (size_t g = 0; g < leads.size(); ++g) {
     BatchGroup bg;
     bg.lead = leads[g];
@@ -168,7 +236,18 @@ wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, 
     bg.stage = stage;
     stage += size_t(b->chunk) * leads[g]->p.q;
     b->groups.push_back(bg);
+    b->sels.push_back(bc.sels[g]);
+    b->sels_stage.push_back(stage_sels);
+    stage_sels += size_t(b->chunk) * leads[g]->p.q;
     b->qmax = std::max(b->qmax, leads[g]->p.q);
+  }
+  b->geo = geo;
+  b->geos = geos;
+  size_t stage_pulls = 0;
+  for (size_t k = 0; k < geos.size(); ++k) {
+    b->geos[k].pulls = bc.pulls[k];
+    b->geos[k].stage = stage_pulls;
+    stage_pulls += size_t(b->chunk) * leads[size_t(geos[k].group)]->p.q;
   }
   const size_t ngroups = leads.size();
   hipError_t e = hipSuccess;
@@ -177,12 +256,17 @@ wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, 
     if (e == hipSuccess)
       e = hipHostMalloc(reinterpret_cast<void**>(&b->pinned_ins[k]),
                         ngroups * b->chunk * 4 * sizeof(float), hipHostMallocDefault);
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void**>(&b->pinned_sels[k]),
+                        stage_sels * sizeof(uint32_t), hipHostMallocDefault);
+    if (e == hipSuccess)
+      e = hipHostMalloc(reinterpret_cast<void**>(&b->pinned_pulls[k]),
+                        stage_pulls * sizeof(uint32_t), hipHostMallocDefault);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev[k], hipEventDisableTiming);
   }
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e == hipSuccess)
-    e = hipHostMalloc(reinterpret_cast<void**>(&b->table), bc.ri + size_t(n) * sizeof(void*),
-                      hipHostMallocDefault);
+    e = hipHostMalloc(reinterpret_cast<void**>(&b->table), b->table_bytes, hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->table_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     (void)wlbm_batch_destroy(b);
@@ -207,9 +291,22 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
   if (st) return st;
   if (nsteps == 0) return WLBM_OK;
   const int ngroups = int(b->groups.size());
-  // argument table: lattice j, buffer parity p (p = 1 after an odd number of
-  // steps of this call); wall temperatures and fields as they are now.  The
-  // pinned staging copy of the previous call must have been consumed.
+  // Several steps per launch when every lattice takes the multi-step kernels
+  // and all have one q (the kernel's shape): k_max steps per launch, the
+  // fewest any lattice allows; the steps left over at chunk ends and in the
+  // flux window run one per launch.
+  bool fuse = true;
+  int k_max = 4;
+  for (wlbm_lattice* l : b->lats) {
+    if (!lattice_fuses(l) || l->p.q != b->qmax)
+      fuse = false;
+    else
+      k_max = std::min(k_max, fused_k_max(l));
+  }
+  if (k_max < 2) fuse = false;
+  // argument tables: lattice j, buffer parity p (p = 1 after an odd number of
+  // launches of this call); wall temperatures and fields as they are now.
+  // The pinned staging copy of the previous call must have been consumed.
   if (b->table_pending) {
     hipError_t e = hipEventSynchronize(b->table_ev);
     if (e != hipSuccess) return fail(WLBM_EHIP, "hipEventSynchronize failed: %s",
@@ -220,12 +317,24 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
   int* first = reinterpret_cast<int*>(b->table + b->off_first);
   const void** ring_codes = reinterpret_cast<const void**>(b->table + b->off_rc);
   const void** ring_ins = reinterpret_cast<const void**>(b->table + b->off_ri);
+  FusedArgs* ftable = reinterpret_cast<FusedArgs*>(b->table + b->off_fargs);
+  int* ffirst = reinterpret_cast<int*>(b->table + b->off_ffirst);
+  const void** fsel = reinterpret_cast<const void**>(b->table + b->off_fsel);
+  const void** fpull = reinterpret_cast<const void**>(b->table + b->off_fpull);
+  const void** fcode = reinterpret_cast<const void**>(b->table + b->off_fcode);
+  const void** fins = reinterpret_cast<const void**>(b->table + b->off_fins);
   first[0] = 0;
+  ffirst[0] = 0;
   for (int j = 0; j < n; ++j) {
     wlbm_lattice* l = b->lats[j];
     const BatchGroup& bg = b->groups[size_t(b->group[j])];
     ring_codes[j] = b->ws + bg.sched;
     ring_ins[j] = b->ws + bg.ins;
+    fsel[j] = b->ws + b->sels[size_t(b->group[j])];
+    fpull[j] = b->ws + b->geos[size_t(b->geo[j])].pulls;
+    fcode[j] = b->ws + bg.sched;
+    fins[j] = b->ws + bg.ins;
+    const int rows = fuse ? block_rows_for(l, k_max) : 1;
     for (int par = 0; par < 2; ++par) {
       StepArgs& a = table[size_t(2) * j + par];
       const int in = l->cur ^ par;
@@ -255,13 +364,37 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
       a.y_edge = l->g.y_edge;
       a.tiles_x = tiles_x_for(l->g.nx);
       a.ntiles = a.tiles_x * tiles_y_for(l->g.ny, l->split);
+      FusedArgs& f = ftable[size_t(2) * j + par];
+      f = FusedArgs{};
+      f.e_in = a.e_in;
+      f.e_out = a.e_out;
+      f.E_in = a.E_in;
+      f.E_out = a.E_out;
+      f.Wf = a.Wf;
+      f.wtab = a.wtab;
+      f.W = a.W;
+      f.nx = a.nx;
+      f.ny = a.ny;
+      f.q = a.q;
+      f.pitch = a.pitch;
+      f.plane = a.plane;
+      f.rows = rows;
+      f.strips_x = fused_strips_x(a.nx, std::max(k_max, 2));
+      f.strips_y = (a.ny + rows - 1) / rows;
+      f.x_edge = a.x_edge;
+      f.y_edge = a.y_edge;
+      f.t_x_lo = a.t_x_lo;
+      f.t_x_hi = a.t_x_hi;
+      f.t_y_lo = a.t_y_lo;
+      f.t_y_hi = a.t_y_hi;
     }
     first[size_t(j) + 1] = first[size_t(j)] + table[size_t(2) * j].ntiles;
+    ffirst[size_t(j) + 1] =
+        ffirst[size_t(j)] + ftable[size_t(2) * j].strips_x * ftable[size_t(2) * j].strips_y;
   }
-  // the table, first[] and the ring pointers sit at the same offsets in the
-  // staging buffer and in the workspace, so one copy moves them all
-  HIP_TRY(hipMemcpyAsync(b->ws, b->table, b->off_ri + size_t(n) * sizeof(void*),
-                         hipMemcpyHostToDevice, b->stream));
+  // the tables sit at the same offsets in the staging buffer and in the
+  // workspace, so one copy moves them all
+  HIP_TRY(hipMemcpyAsync(b->ws, b->table, b->table_bytes, hipMemcpyHostToDevice, b->stream));
   HIP_TRY(hipEventRecord(b->table_ev, b->stream));
   b->table_pending = true;
   BatchStepArgs ba{};
@@ -272,6 +405,15 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
   ba.q = b->qmax;
   ba.ring_codes = reinterpret_cast<const uint32_t* const*>(b->ws + b->off_rc);
   ba.ring_ins = reinterpret_cast<const float* const*>(b->ws + b->off_ri);
+  FusedBatchArgs fb{};
+  fb.lats = reinterpret_cast<const FusedArgs*>(b->ws + b->off_fargs);
+  fb.first = reinterpret_cast<const int*>(b->ws + b->off_ffirst);
+  fb.sels = reinterpret_cast<const uint32_t* const*>(b->ws + b->off_fsel);
+  fb.pulls = reinterpret_cast<const uint32_t* const*>(b->ws + b->off_fpull);
+  fb.codes = reinterpret_cast<const uint8_t* const*>(b->ws + b->off_fcode);
+  fb.ins = reinterpret_cast<const float* const*>(b->ws + b->off_fins);
+  fb.n = n;
+  fb.nblocks = ffirst[size_t(n)];
   const bool grouped = ngroups > 1;
   // group 0's row and sums of step j in ring slot `slot`
   const BatchGroup& g0 = b->groups[0];
@@ -285,12 +427,43 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
   const int64_t flux_from = l0->flux_window > 0 ? nsteps - l0->flux_window : nsteps;
   bool has_sources = false;
   for (wlbm_lattice* l : b->lats) has_sources = has_sources || l->nsrc > 0;
+  // The multi-step kernels read the ghost frame of periodic edges, which
+  // other producers write only in part: refresh it before a multi-step
+  // launch that follows them (the current buffer of a lattice after `fl`
+  // launches of this call is cur ^ (fl & 1)).
+  std::vector<bool> frame_ok(static_cast<size_t>(n), false);
+  for (int j = 0; j < n; ++j) frame_ok[size_t(j)] = b->lats[j]->ghosts_full;
+  auto refresh = [&](int64_t fl) -> hipError_t {
+    for (int j = 0; j < n; ++j) {
+      wlbm_lattice* l = b->lats[j];
+      const bool px = l->g.x_edge == kPeriodic, py = l->g.y_edge == kPeriodic;
+      const int buf = l->cur ^ int(fl & 1);
+      hipError_t e = hipSuccess;
+      if (!frame_ok[size_t(j)]) {
+        e = fill_ghosts(l->ptr(l->c.e[buf]), l->g.plane, l->p.q, l->g.nx, l->g.ny, l->g.pitch,
+                        px, py, b->stream);
+        if (e == hipSuccess)
+          e = fill_ghosts(l->ptr(l->c.E[buf]), l->g.plane, 1, l->g.nx, l->g.ny, l->g.pitch, px,
+                          py, b->stream);
+        frame_ok[size_t(j)] = true;
+      }
+      if (e == hipSuccess && l->per_cell && !l->wf_ghosts_full) {
+        e = fill_ghosts(l->ptr(l->c.Wf), l->g.plane, 1, l->g.nx, l->g.ny, l->g.pitch, px, py,
+                        b->stream);
+        if (e == hipSuccess) l->wf_ghosts_full = true;
+      }
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
   // each group advances its own schedule state
   std::vector<TasState> tas;
   for (const BatchGroup& bg : b->groups) tas.push_back(bg.lead->tas);
-  std::vector<int8_t> dx(size_t(b->qmax)), dy(size_t(b->qmax));
-  std::vector<uint8_t> hop(size_t(b->qmax));
+  std::vector<int8_t> dx(size_t(b->chunk) * b->qmax), dy(size_t(b->chunk) * b->qmax);
+  std::vector<uint8_t> hop(size_t(b->chunk) * b->qmax);
   int64_t done = 0;
+  int64_t flips = 0;          // launches so far: the buffer parity
+  bool last_fused = false;
   while (done < nsteps) {
     const int cnt = int(std::min<int64_t>(b->chunk, nsteps - done));
     const int slot = int(b->chunk_counter & 1);
@@ -302,7 +475,8 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
     }
     // Build the schedule rows of this chunk (Sec. 2.3, Sec. 2.5) and the
     // per-step sums of inward weights used by diffuse walls, for each group,
-    // and upload them into the group's ring slot.
+    // with (for multi-step launches) the selection offsets of the group and
+    // the pull offsets of each geometry, and upload them into the rings.
     hipError_t e = hipSuccess;
     for (int g = 0; g < ngroups && e == hipSuccess; ++g) {
       const BatchGroup& bg = b->groups[size_t(g)];
@@ -311,18 +485,21 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
       uint8_t* rows = b->pinned[slot] + bg.stage;
       float* insums = b->pinned_ins[slot] + size_t(g) * b->chunk * 4;
       for (int j = 0; j < cnt; ++j) {
-        tas_advance(lead->dirs, tas[size_t(g)], dx.data(), dy.data(), hop.data());
+        int8_t* dxj = dx.data() + size_t(j) * q;
+        int8_t* dyj = dy.data() + size_t(j) * q;
+        uint8_t* hopj = hop.data() + size_t(j) * q;
+        tas_advance(lead->dirs, tas[size_t(g)], dxj, dyj, hopj);
         for (int m = 0; m < n; ++m)
           if (b->group[m] == g) b->lats[m]->book.note(tas[size_t(g)]);
         double lo_h = 0, lo_a = 0, hi_h = 0, hi_a = 0;
         for (int i = 0; i < q; ++i) {
-          rows[size_t(j) * q + i] = pack_code(dx[i], dy[i], hop[i]);
-          if (dy[i] == 1) {
+          rows[size_t(j) * q + i] = pack_code(dxj[i], dyj[i], hopj[i]);
+          if (dyj[i] == 1) {
             lo_a += lead->dirs.w[i];
-            if (hop[i]) lo_h += lead->dirs.w[i];
-          } else if (dy[i] == -1) {
+            if (hopj[i]) lo_h += lead->dirs.w[i];
+          } else if (dyj[i] == -1) {
             hi_a += lead->dirs.w[i];
-            if (hop[i]) hi_h += lead->dirs.w[i];
+            if (hopj[i]) hi_h += lead->dirs.w[i];
           }
         }
         insums[4 * j] = float(lo_h);
@@ -337,17 +514,42 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
       if (e == hipSuccess)
         e = hipMemcpyAsync(dev_ins, insums, size_t(cnt) * 4 * sizeof(float),
                            hipMemcpyHostToDevice, b->stream);
+      if (fuse && e == hipSuccess) {
+        uint32_t* sels = b->pinned_sels[slot] + b->sels_stage[size_t(g)];
+        for (size_t k = 0; k < size_t(cnt) * q; ++k) sels[k] = uint32_t(rows[k]) * kSelEntryBytes;
+        e = hipMemcpyAsync(reinterpret_cast<uint32_t*>(b->ws + b->sels[size_t(g)]) +
+                               size_t(slot) * b->chunk * q,
+                           sels, size_t(cnt) * q * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           b->stream);
+        for (size_t k = 0; k < b->geos.size() && e == hipSuccess; ++k) {
+          const BatchGeo& geo = b->geos[k];
+          if (geo.group != g) continue;
+          const uint32_t pitch4 = uint32_t(geo.pitch) * 4u, plane4 = uint32_t(geo.plane) * 4u;
+          uint32_t* pw = b->pinned_pulls[slot] + geo.stage;
+          for (int j = 0; j < cnt; ++j)
+            for (int i = 0; i < q; ++i) {
+              const size_t ji = size_t(j) * q + i;
+              const int hx = hop[ji] ? dx[ji] : 0, hy = hop[ji] ? dy[ji] : 0;
+              pw[ji] = uint32_t(1 - hy) * pitch4 + uint32_t(4 * (1 - hx)) +
+                       uint32_t(i % kMaxGroupPlanes) * plane4;
+            }
+          e = hipMemcpyAsync(reinterpret_cast<uint32_t*>(b->ws + geo.pulls) +
+                                 size_t(slot) * b->chunk * q,
+                             pw, size_t(cnt) * q * sizeof(uint32_t), hipMemcpyHostToDevice,
+                             b->stream);
+        }
+      }
     }
     if (e == hipSuccess) e = hipEventRecord(b->ev[slot], b->stream);
     if (e != hipSuccess) return fail(WLBM_EHIP, "schedule upload failed: %s", hipGetErrorString(e));
     b->ev_pending[slot] = true;
     ++b->chunk_counter;
-    // A whole chunk with no flux-window step and no sources, starting on an
-    // even step of this call, is one launch of the slot's captured graph:
-    // its kernels read the schedule rows and sums just uploaded, and the
-    // argument table of this call.
-    const bool graph = b->use_graphs && cnt == b->chunk && b->chunk % 2 == 0 &&
-                       done % 2 == 0 && done + cnt <= flux_from && !has_sources;
+    // A whole chunk of single steps with no flux-window step and no sources,
+    // starting on an even launch of this call, is one launch of the slot's
+    // captured graph: its kernels read the schedule rows and sums just
+    // uploaded, and the argument table of this call.
+    const bool graph = !fuse && b->use_graphs && cnt == b->chunk && b->chunk % 2 == 0 &&
+                       flips % 2 == 0 && done + cnt <= flux_from && !has_sources;
     if (graph) {
       const int64_t key = (int64_t(ba.nblocks) << 8) | (int64_t(l0->split) << 1) |
                           int64_t(l0->per_cell ? 1 : 0);
@@ -389,21 +591,39 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
         return fail(WLBM_EHIP, "batch graph launch failed: %s", hipGetErrorString(e));
       }
       done += cnt;
+      flips += cnt;
+      last_fused = false;
+      std::fill(frame_ok.begin(), frame_ok.end(), false);
       continue;
     }
     for (int j = 0; j < cnt; ++j) {
       const int64_t k = done + j;
       const bool flux = k >= flux_from;
+      if (fuse && j + k_max <= cnt && k + k_max <= flux_from) {
+        // steps k .. k + k_max - 1 in one launch
+        fb.row = slot * b->chunk + j;
+        fb.parity = int(flips & 1);
+        e = refresh(flips);
+        if (e == hipSuccess) e = launch_fused_batch(fb, b->qmax, k_max, l0->per_cell, b->stream);
+        if (e != hipSuccess) {
+          for (wlbm_lattice* l : b->lats) l->broken = true;
+          return fail(WLBM_EHIP, "batch multi-step launch failed: %s", hipGetErrorString(e));
+        }
+        ++flips;
+        last_fused = true;
+        j += k_max - 1;
+        continue;
+      }
       ba.row = slot * b->chunk + j;
       ba.codes = rows0(slot, j);
       ba.ins = ins0(slot, j);
-      ba.parity = int(k & 1);
+      ba.parity = int(flips & 1);
       ba.q_first = (flux && k == flux_from) ? 1 : 0;
       e = launch_step_batch(ba, l0->split, l0->per_cell, flux, grouped, b->stream);
       for (int jl = 0; jl < n && e == hipSuccess; ++jl) {
         wlbm_lattice* l = b->lats[jl];
         if (!l->nsrc) continue;
-        const int out = 1 - (l->cur ^ int(k & 1));
+        const int out = 1 - (l->cur ^ int(flips & 1));
         e = launch_apply_sources(l->g, l->ptr(l->c.e[out]), l->ptr(l->c.E[out]), l->src_cells,
                                  l->src_vals, l->nsrc, b->stream);
       }
@@ -411,15 +631,18 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
         for (wlbm_lattice* l : b->lats) l->broken = true;
         return fail(WLBM_EHIP, "batch step launch failed: %s", hipGetErrorString(e));
       }
+      ++flips;
+      last_fused = false;
+      std::fill(frame_ok.begin(), frame_ok.end(), false);
     }
     done += cnt;
   }
   for (int j = 0; j < n; ++j) {
     wlbm_lattice* l = b->lats[j];
     l->tas = tas[size_t(b->group[j])];
-    l->cur ^= int(nsteps & 1);
+    l->cur ^= int(flips & 1);
     l->flux_valid = l->flux_window > 0 && nsteps >= l->flux_window;
-    l->ghosts_full = false;
+    l->ghosts_full = last_fused;
   }
   return WLBM_OK;
 }
@@ -438,6 +661,8 @@ wlbm_status wlbm_batch_destroy(wlbm_batch* b) {
     if (b->gexec[k]) (void)hipGraphExecDestroy(b->gexec[k]);
     if (b->pinned[k]) (void)hipHostFree(b->pinned[k]);
     if (b->pinned_ins[k]) (void)hipHostFree(b->pinned_ins[k]);
+    if (b->pinned_sels[k]) (void)hipHostFree(b->pinned_sels[k]);
+    if (b->pinned_pulls[k]) (void)hipHostFree(b->pinned_pulls[k]);
     if (b->ev[k]) (void)hipEventDestroy(b->ev[k]);
   }
   if (b->cap) (void)hipStreamDestroy(b->cap);

@@ -36,8 +36,8 @@ inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 // Byte offsets of the lattice workspace regions.
 struct Carve {
-  size_t e[2], E[2], Wf, Wraw, qsx, qsy, partials, totals, flag, sched, pulls, wtab, sxtab, sytab,
-      mtab, total;
+  size_t e[2], E[2], Wf, Wraw, qsx, qsy, partials, totals, flag, sched, pulls, ins, wtab, sxtab,
+      sytab, mtab, total;
 };
 
 // Lattices that the multi-step kernels can advance.
@@ -82,6 +82,7 @@ struct wlbm_lattice {
   bool wf_ghosts_full = false;   // the same for the per-cell weight field
   uint8_t* pinned[2] = {nullptr, nullptr};
   uint32_t* pinned_pulls[2] = {nullptr, nullptr};   // staging of the pull offsets
+  float* pinned_ins[2] = {nullptr, nullptr};        // staging of the inward-weight sums
   hipEvent_t ev[2] = {nullptr, nullptr};
   bool ev_pending[2] = {false, false};
   int64_t chunk_counter = 0;
@@ -115,8 +116,13 @@ int auto_split(int q);
 // output into tape slot k.
 wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_bytes);
 // Whether run_steps may advance this lattice several steps per launch (with
-// no tape and no flux window).
+// no tape and no flux window), and at most how many.
 bool lattice_fuses(const wlbm_lattice* l);
+int fused_k_cap(const wlbm_lattice* l);
+// Steps per launch the lattice's multi-step launches take: step_fusion 2 .. 4,
+// or for 1 (automatic) four, two for lattices with walls and q above 64 or a
+// per-cell field (measured fastest), capped by fused_k_cap.
+int fused_k_max(const wlbm_lattice* l);
 // Output rows per block of the k-step kernel for the lattice's current
 // weight mode: the fixed or tuned height, else the launch model's pick.
 int block_rows_for(const wlbm_lattice* l, int k);

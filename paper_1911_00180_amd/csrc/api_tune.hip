@@ -36,7 +36,9 @@ int block_rows_for(const wlbm_lattice* l, int k) {
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       cus < 1)
     cus = 256;
-  const long long cap = (long long)std::max(1, fused_blocks_per_cu(l->p.q, k, l->per_cell)) * cus;
+  const bool walls = l->g.x_edge != kPeriodic || l->g.y_edge != kPeriodic;
+  const long long cap =
+      (long long)std::max(1, fused_blocks_per_cu(l->p.q, k, l->per_cell, walls)) * cus;
   const long long sx = fused_strips_x(l->g.nx, k);
   int best = cand[0];
   long long best_cost = -1;
@@ -172,6 +174,8 @@ wlbm_status wlbm_tune_block_rows(wlbm_lattice* l, void* d_state, size_t bytes, i
   if (!lattice_fuses(l))
     return fail(WLBM_EINVAL, "this lattice runs one step per launch (its edges, sources, q or "
                              "size rule out the multi-step kernels, or step_fusion is 0)");
+  if (k > fused_k_cap(l))
+    return fail(WLBM_EINVAL, "this lattice runs at most %d steps per launch", fused_k_cap(l));
   // a launch never crosses a schedule chunk: time whole launches of k steps
   const int per_call = std::max(1, std::min<int>(launches, l->chunk / k));
   const int64_t warm = 2, need = (warm + launches) * int64_t(k);

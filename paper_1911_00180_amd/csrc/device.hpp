@@ -111,12 +111,57 @@ struct FusedArgs {
   long long plane;
   int strips_x, strips_y;
   int rows;   // output rows per block: rows + 2 (k - 1) a multiple of 3
+  // Edges (x: periodic or blackbody; y: periodic, blackbody or fully
+  // diffuse) and blackbody temperatures.
+  int x_edge, y_edge;
+  float t_x_lo, t_x_hi, t_y_lo, t_y_hi;
+  // The schedule row of the launch's first step (step m of the launch at
+  // codes + m q / 4; wall rows decode it) and its four sums of inward weights
+  // of the diffuse walls (as StepArgs: lo hopping, lo all, hi hopping, hi all;
+  // step m at ins + 4 m), in device memory uploaded with the schedule.
+  const uint32_t* codes;
+  const float* ins;
 };
+// K = 2 .. 4 steps of n lattices with the same q and per-cell field use in
+// one launch.  lats holds each lattice's arguments for buffer parity 0 and 1
+// ([2n], on the device; the per-step fields are taken from the rings below);
+// first[j] is the first block of lattice j, first[n] = nblocks.  Lattice j's
+// per-step tables are rings of two schedule chunks: selection offsets
+// (sels[j]), pull offsets of its geometry (pulls[j]), schedule rows
+// (codes[j], q bytes a step) and inward-weight sums (ins[j], 4 a step); the
+// launch's first step is ring row `row`.
+struct FusedBatchArgs {
+  const FusedArgs* lats;
+  const int* first;
+  const uint32_t* const* sels;
+  const uint32_t* const* pulls;
+  const uint8_t* const* codes;
+  const float* const* ins;
+  int row;
+  int n, nblocks, parity;
+};
+hipError_t launch_fused_batch(const FusedBatchArgs& b, int q, int k, bool per_cell,
+                              hipStream_t s);
+hipError_t launch_fused_batch_walls2(const FusedBatchArgs& b, int q, bool per_cell,
+                                     hipStream_t s);
+hipError_t launch_fused_batch_walls3(const FusedBatchArgs& b, int q, bool per_cell,
+                                     hipStream_t s);
+hipError_t launch_fused_batch_walls4(const FusedBatchArgs& b, int q, bool per_cell,
+                                     hipStream_t s);
+
+// K = 2 .. 4 steps per launch; lattices with walls run the kernels of
+// fused_walls{2,3,4}.hip.
 hipError_t launch_fused(const FusedArgs& a, int k, bool per_cell, hipStream_t s);
-// Ghost frame (four ghost columns each side, ghost rows) of nplanes periodic
-// planes from the cells they wrap to.
+hipError_t launch_fused_walls2(const FusedArgs& a, bool per_cell, hipStream_t s);
+hipError_t launch_fused_walls3(const FusedArgs& a, bool per_cell, hipStream_t s);
+hipError_t launch_fused_walls4(const FusedArgs& a, bool per_cell, hipStream_t s);
+int fused_blocks_per_cu_walls2(int q, bool per_cell);
+int fused_blocks_per_cu_walls3(int q, bool per_cell);
+int fused_blocks_per_cu_walls4(int q, bool per_cell);
+// Ghost frame of nplanes planes from the cells they wrap to: the four ghost
+// columns each side if px (periodic x), the ghost rows if py.
 hipError_t fill_ghosts(float* base, long long plane, int nplanes, int nx, int ny, int pitch,
-                       hipStream_t s);
+                       bool px, bool py, hipStream_t s);
 int fused_strips_x(int nx, int k);
 // Candidate output rows per block for k steps per launch (at most max_cand,
 // written to cand); returns their number.
@@ -124,9 +169,9 @@ int fused_row_candidates(int ny, int k, int* cand, int max_cand);
 // Whether the multi-step kernels take this lattice: q a multiple of 8 up to
 // 64 or of 16 up to 128, nx >= 8, ny >= 2.
 bool fused_supported(int q, int nx, int ny);
-// Resident blocks per CU of the k-step kernel for q directions (occupancy
-// query of the runtime; 0 if it fails).
-int fused_blocks_per_cu(int q, int k, bool per_cell);
+// Resident blocks per CU of the k-step kernel for q directions and these
+// edges (occupancy query of the runtime; 0 if it fails).
+int fused_blocks_per_cu(int q, int k, bool per_cell, bool walls);
 
 // One time step of n lattices in one launch (same split, per-cell field use
 // and step; lattices with the same q, direction set and grid speeds share a

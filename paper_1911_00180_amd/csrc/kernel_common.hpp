@@ -126,6 +126,16 @@ __device__ __forceinline__ void decode(uint32_t code, int& dx, int& dy, bool& ho
   hop = (code >> 4) & 1u;
 }
 
+// The inflow of a diffuse-wall node is summed per batch of 8 directions; the
+// batch sums are grouped into kNodeParts consecutive ranges of
+// node_part_batches(q / 8) batches, each range added in order, and the range
+// sums added in order.  (The single-step kernel gives each range to its own
+// thread; the multi-step kernels add the same terms in the same order.)
+constexpr int kNodeParts = 3;
+__device__ __forceinline__ int node_part_batches(int nb) {
+  return (nb + kNodeParts - 1) / kNodeParts;
+}
+
 // One kernel block is four waves.  Its tile is 64 cells wide (one wave) and
 // 4 / NW rows tall; the Q directions of each cell are split over NW waves,
 // each taking Q / NW of them in batches of D.  Splitting keeps every wave

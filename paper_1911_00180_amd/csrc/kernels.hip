@@ -54,28 +54,43 @@ __device__ __forceinline__ bool node_fixed(const StepArgs& a, int wall, int& X, 
   return false;
 }
 
-// What directions i0 .. i1-1 stream into the node at (wrapped) column X on
-// this step, summed in direction order.
+// What batches b0 .. b1-1 of 8 directions stream into the node at (wrapped)
+// column X on this step: for every direction whose pending move leaves the
+// lattice through the node's wall, the packet that the pull form delivers to a
+// cell at the node's position (the DDED of the wall-row cell X - dx on a hop,
+// its EED on every step).  Each batch is summed in direction order and the
+// batch sums in batch order, so the multi-step kernels, which hold the
+// directions of a cell in other waves, can add the same terms in the same
+// order.
 template <bool WF>
-__device__ float node_inflow(const StepArgs& a, int wall, int X, int i0, int i1) {
+__device__ float node_inflow(const StepArgs& a, int wall, int X, int b0, int b1) {
   const int yrow = wall == 0 ? 0 : a.ny - 1;
   const int out_dy = wall == 0 ? -1 : 1;
-  float R = 0.f;
-  for (int i = i0; i < i1; ++i) {
-    const uint32_t code = (a.codes[i >> 2] >> (8 * (i & 3))) & 0xffu;
-    int dx, dy;
-    bool hop;
-    decode(code, dx, dy, hop);
-    if (dy != out_dy) continue;
-    // source cell of the packet; for a periodic x edge the ghost columns
-    // hold the wrapped values, for a blackbody edge X - dx stays inside
-    const long long o = cell(X - dx, yrow, a.pitch);
-    const float Ws = WF ? a.Wf[o] : a.W;
-    const float e = a.e_in[(long long)i * a.plane + o];
-    if (hop) R += fmaf(-Ws, e, e);
-    R = fmaf(Ws * a.wtab[i], a.E_in[o], R);
+  float S = 0.f;
+  for (int b = b0; b < b1; ++b) {
+    float R = 0.f;
+    for (int i = b * kMaxGroupPlanes; i < (b + 1) * kMaxGroupPlanes; ++i) {
+      const uint32_t code = (a.codes[i >> 2] >> (8 * (i & 3))) & 0xffu;
+      int dx, dy;
+      bool hop;
+      decode(code, dx, dy, hop);
+      if (dy != out_dy) continue;
+      // source cell of the packet; for a periodic x edge the ghost columns
+      // hold the wrapped values, for a blackbody edge X - dx stays inside
+      const long long o = cell(X - dx, yrow, a.pitch);
+      const float e = hop ? a.e_in[(long long)i * a.plane + o] : 0.f;
+      float out;
+      if constexpr (!WF) {
+        out = fmaf(a.W, fmaf(a.wtab[i], a.E_in[o], -e), e);
+      } else {
+        const float Ws = a.Wf[o];
+        out = e + fmaf(a.wtab[i], a.E_in[o] * Ws, -(Ws * e));
+      }
+      R += out;
+    }
+    S += R;
   }
-  return R;
+  return S;
 }
 
 // T_g and W_g T_g of the node at (wrapped) column X from its inflow R.
@@ -284,8 +299,6 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
   }
 }
 
-// Threads that share the inflow sum of one diffuse-wall node.
-constexpr int kNodeParts = 3;
 
 // LDS of one block of the step kernel.
 template <int NW, bool WF, bool FLUX>
@@ -352,11 +365,12 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
                      y0 + T::TY < a.ny;
   if (edge && !xwall && a.y_edge == kDiffuse) {
     // The inflow of each node of the tile's wall rows (and halo) is summed
-    // by kNodeParts threads over consecutive ranges of directions, then the
-    // parts are added in order.
+    // by kNodeParts threads over consecutive ranges of 8-direction batches,
+    // then the parts are added in order (node_inflow, node_part_batches).
     const bool lo = y0 == 0;
     const bool hi = a.ny - 1 < y0 + T::TY;
-    const int chunk = (a.q + kNodeParts - 1) / kNodeParts;
+    const int nb = a.q / kMaxGroupPlanes;
+    const int per = node_part_batches(nb);
     for (int k = threadIdx.x; k < 2 * T::LP * kNodeParts; k += kBlock) {
       const int node = k / kNodeParts, part = k - node * kNodeParts;
       const int wall = node / T::LP;
@@ -364,8 +378,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
       int X = x0 - 1 + (node - wall * T::LP);
       float tg, wtg;
       if (node_fixed<WF>(a, wall, X, tg, wtg)) continue;
-      const int i0 = part * chunk, i1 = min(a.q, i0 + chunk);
-      sh.sInflow[k] = node_inflow<WF>(a, wall, X, i0, i1);
+      const int b0 = min(nb, part * per), b1 = min(nb, b0 + per);
+      sh.sInflow[k] = node_inflow<WF>(a, wall, X, b0, b1);
     }
     __syncthreads();
     for (int k = threadIdx.x; k < 2 * T::LP; k += kBlock) {

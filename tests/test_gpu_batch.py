@@ -232,3 +232,43 @@ def test_batch_of_different_direction_sets_equals_one_by_one():
     batch.close()
     for lat in c:
         lat.close()
+
+
+@pytest.mark.parametrize("q,per_cell,fusion", [(128, False, 1), (64, True, 1), (32, False, 3),
+                                               (16, False, 4)])
+def test_batched_multi_step_launches_keep_the_bits_of_single_steps(q, per_cell, fusion):
+    """Films of several thicknesses (blackbody x, diffuse y) and a periodic and a
+    blackbody-y lattice in one batch: the batch advances several steps per launch
+    for all of them (each lattice's block height, one table of pull offsets per
+    geometry), and matches lattices stepped one step per launch bit for bit,
+    across schedule chunks, odd launch counts and a flux window."""
+    from paper_1911_00180_amd.lattice import Batch
+    cfgs = [dict(nx=150, ny=ny, mfp=mfp, x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0,
+                 t_x_hi=0.1) for ny, mfp in ((8, 2.0), (23, 9.0), (40, 30.0), (8, 5.0))]
+    cfgs += [dict(nx=97, ny=30, mfp=12.0),
+             dict(nx=64, ny=17, mfp=4.0, x_edge="periodic", y_edge="blackbody", t_y_lo=0.3)]
+    kw = dict(sched_chunk=24)
+    a = [_make(q, c, 40 + k, step_fusion=fusion, **kw) for k, c in enumerate(cfgs)]
+    b = [_make(q, c, 40 + k, step_fusion=0, **kw) for k, c in enumerate(cfgs)]
+    if per_cell:
+        for x, y, c in zip(a, b, cfgs):
+            f = torch.from_numpy(inputs.smooth_lognormal_field(c["nx"], c["ny"], 3, 4.0, 8.0,
+                                                               0.5, 2.0, 30.0)
+                                 .astype(np.float32))
+            x.set_mfp_field(f)
+            y.set_mfp_field(f)
+    for lat in a + b:
+        lat.set_flux_window(3)
+    batch = Batch(a)
+    for n in (50, 7, 24):
+        batch.step(n)
+        for lat in b:
+            lat.step(n)
+        for x, y in zip(a, b):
+            assert x.step_count == y.step_count
+            assert torch.equal(x.populations(), y.populations()), n
+            for u, v in zip(x.heat_flux(averaged=True), y.heat_flux(averaged=True)):
+                assert torch.equal(u, v)
+    batch.close()
+    for lat in a + b:
+        lat.close()

@@ -1,5 +1,6 @@
 """Several steps per launch (k_stepk, K = 2 .. 4) against one step per launch
-(k_step).
+(k_step), on periodic lattices and on lattices with blackbody x and y edges
+and adiabatic diffuse y walls.
 
 The multi-step kernels use the same arithmetic and the same summation order
 as the single-step kernel, so the populations must agree bit for bit,
@@ -212,5 +213,78 @@ def test_fused_random_shapes(seed):
         a.step(int(n))
         b.step(int(n))
         assert torch.equal(a.populations(), b.populations()), (nx, ny, q, kind, fusion, chunk, n)
+    a.close()
+    b.close()
+
+
+WALLED = {
+    "bbx": dict(x_edge="blackbody", y_edge="periodic", t_x_lo=1.0, t_x_hi=0.25),
+    "bby": dict(x_edge="periodic", y_edge="blackbody", t_y_lo=0.7, t_y_hi=0.1),
+    "bbxy": dict(x_edge="blackbody", y_edge="blackbody", t_x_lo=1.0, t_x_hi=0.0, t_y_lo=0.5,
+                 t_y_hi=0.2),
+    "dify": dict(x_edge="periodic", y_edge="diffuse"),
+    "bbx_dify": dict(x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0, t_x_hi=0.0),
+}
+
+
+@pytest.mark.parametrize("fusion", [2, 3, 4])
+@pytest.mark.parametrize("edges", sorted(WALLED))
+@pytest.mark.parametrize("nx,ny,q,mfp,per_cell", [
+    (150, 41, 64, 9.0, False), (97, 23, 32, 4.0, True), (9, 8, 8, 2.0, False),
+    (70, 130, 128, 6.0, True), (200, 3, 16, 1.5, False)])
+def test_walled_lattices_keep_the_bits_of_single_steps(fusion, edges, nx, ny, q, mfp, per_cell):
+    """Blackbody x / y edges and diffuse y walls (Sec. 2.6) inside the
+    multi-step kernel: every level overwrites blackbody cells, zeroes the rows
+    beyond a non-periodic y edge and re-emits the diffuse nodes' inflow, so
+    any number of steps per launch gives the bits of single steps."""
+    a, b = _pair(nx, ny, q, fusion=fusion, mfp=mfp, sched_chunk=17, **WALLED[edges])
+    assert a.block_rows(fusion) > 0 and b.block_rows(fusion) == 0
+    if per_cell:
+        f = torch.from_numpy(inputs.smooth_lognormal_field(nx, ny, 5, 4.0, 8.0, 0.5, 2.0,
+                                                           40.0).astype(np.float32))
+        a.set_mfp_field(f)
+        b.set_mfp_field(f)
+    e0 = torch.from_numpy(inputs.random_populations(9, q, ny, nx))
+    for lat in (a, b):
+        lat.set_populations(e0)
+    for n in (3, 4, 5, 1, 2, 40):
+        a.step(n)
+        b.step(n)
+        assert torch.equal(a.populations(), b.populations()), n
+        assert torch.equal(a.temperature(), b.temperature()), n
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_walled_random_shapes(seed):
+    """Seeded random walled lattices (edges, sizes, Q, direction set, per-cell
+    field, chunk and step counts, wall temperatures): multi-step launches keep
+    the bits of single steps."""
+    rng = np.random.default_rng(2000 + seed)
+    nx = int(rng.integers(8, 260))
+    ny = int(rng.integers(2, 80))
+    q = int(rng.choice([8, 16, 24, 32, 48, 64, 80, 96, 112, 128]))
+    kind = "ring" if rng.random() < 0.3 else "uniform"
+    edges = dict(WALLED[sorted(WALLED)[int(rng.integers(0, len(WALLED)))]])
+    for key in ("t_x_lo", "t_x_hi", "t_y_lo", "t_y_hi"):
+        if key in edges:
+            edges[key] = float(rng.uniform(0.0, 1.0))
+    fusion = int(rng.integers(1, 5))
+    chunk = int(rng.integers(16, 64))
+    a, b = _pair(nx, ny, q, fusion=fusion, mfp=float(rng.uniform(1.5, 50.0)), dirs=kind,
+                 sched_chunk=chunk, **edges)
+    if rng.random() < 0.4:
+        mfp = torch.from_numpy(inputs.smooth_lognormal_field(nx, ny, seed, 4.0, 8.0, 0.5, 2.0,
+                                                             40.0).astype(np.float32))
+        a.set_mfp_field(mfp)
+        b.set_mfp_field(mfp)
+    e0 = torch.from_numpy(inputs.random_populations(70 + seed, q, ny, nx))
+    for lat in (a, b):
+        lat.set_populations(e0)
+    for n in rng.integers(1, 40, 3):
+        a.step(int(n))
+        b.step(int(n))
+        assert torch.equal(a.populations(), b.populations()), (nx, ny, q, kind, edges, fusion, n)
     a.close()
     b.close()
