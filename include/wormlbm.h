@@ -104,10 +104,11 @@ typedef struct wlbm_params {
   int32_t step_fusion;       /* time steps per kernel launch where possible      */
                              /* (any edges but partly specular walls, no         */
                              /* sources, q a multiple of 8 up to 64 or of 16 up  */
-                             /* to 128, nx >= 8, ny >= 2, outside flux windows   */
-                             /* and tapes; periodic x with diffuse y: at most    */
-                             /* two): 1 = default (up to four), 2 .. 4 = at most */
-                             /* that many, 0 = one step per launch.  Results are */
+                             /* to 128, or 192 or 256, nx >= 8, ny >= 2, outside */
+                             /* flux windows and tapes; q above 128, and         */
+                             /* periodic x with diffuse y: at most two): 1 =     */
+                             /* automatic (up to four), 2 .. 4 = at most that    */
+                             /* many, 0 = one step per launch.  Results are      */
                              /* identical to single steps in every case.         */
   int32_t reserved[3];       /* must be zero                                     */
 } wlbm_params;

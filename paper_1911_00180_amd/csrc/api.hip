@@ -133,8 +133,10 @@ bool lattice_fuses(const wlbm_lattice* l) {
 }
 
 // Along a diffuse wall the dependence reaches two columns per step, which
-// the ghost frame of a periodic x edge covers for two steps per launch.
+// the ghost frame of a periodic x edge covers for two steps per launch; q
+// above 128 runs at most two steps per launch.
 int fused_k_cap(const wlbm_lattice* l) {
+  if (l->p.q > 128) return 2;   // 16 waves of 16 directions: registers for two levels
   return (l->g.x_edge == kPeriodic && l->g.y_edge == kDiffuse) ? 2 : 4;
 }
 

@@ -167,7 +167,8 @@ int fused_strips_x(int nx, int k);
 // written to cand); returns their number.
 int fused_row_candidates(int ny, int k, int* cand, int max_cand);
 // Whether the multi-step kernels take this lattice: q a multiple of 8 up to
-// 64 or of 16 up to 128, nx >= 8, ny >= 2.
+// 64 or of 16 up to 128, or q = 192 or 256 (two steps per launch), nx >= 8,
+// ny >= 2.
 bool fused_supported(int q, int nx, int ny);
 // Resident blocks per CU of the k-step kernel for q directions and these
 // edges (occupancy query of the runtime; 0 if it fails).

@@ -219,7 +219,9 @@ __device__ __forceinline__ void decode_at(const WLBM_CONST uint32_t* codes, int 
 // lane, eRow the wave's LDS copy of that row's E (per-cell mode: W E), Wrow
 // the row's W at its own lane (per-cell mode).  Each wave sums its batches of
 // the packets leaving through the wall into sR; after an LDS barrier every
-// wave adds all batches in k_step's grouping (node_part_batches).
+// wave adds all batches in k_step's grouping (node_part_batches).  sR is the
+// level's E batch-sum buffer of the other row parity, last read for the
+// previous row: a barrier first lets every wave finish those reads.
 template <int NW, int SH, bool WF>
 __device__ __forceinline__ void wall_nodes(const FusedArgs& a, const EdgeCtx& ec,
                                            const WLBM_CONST uint32_t* codes,
@@ -229,6 +231,7 @@ __device__ __forceinline__ void wall_nodes(const FusedArgs& a, const EdgeCtx& ec
   constexpr int NB = NW * SH / kMaxGroupPlanes;
   const WLBM_CONST float* wtab = scalar_ptr(a.wtab);
   const int out_dy = wall == 0 ? -1 : 1;
+  lds_barrier();
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     float R = 0.f;
@@ -378,8 +381,8 @@ __device__ __forceinline__ bool row_bb(const EdgeCtx& ec, const RowWalls& rw, ui
 // row r is summed.  Step-n slots: rows r-1, r, r+1 are S, S+1, S+2 (mod 3).
 template <int NW, int SH, int K, bool WF, int S, bool WALLS>
 __device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float* sP, float* eR,
-                                       float* sR, const EdgeCtx& ec, int t, int y0, int lane,
-                                       int part, uint32_t lcol) {
+                                       const EdgeCtx& ec, int t, int y0, int lane, int part,
+                                       uint32_t lcol) {
   constexpr int S1 = (S + 1) % 3, S2 = (S + 2) % 3;
   constexpr int NB = NW * SH / kMaxGroupPlanes;   // batches of 8 directions
   const RowCtx c = row_ctx(a);
@@ -424,7 +427,7 @@ __device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float
         }
       }
       wall_nodes<NW, SH, WF>(a, ec, codes, row_ptr(a.ins), rw.diffuse, src, eR + S1 * kERow,
-                             g.Wn[S1], sR, lane, part, tg, wtg);
+                             g.Wn[S1], sP + ((t + 1) & 1) * NB * 64, lane, part, tg, wtg);
     }
   }
 #pragma unroll
@@ -525,8 +528,8 @@ __device__ __forceinline__ void walls_up(const FusedArgs& a, const Ring<SH, K>& 
 // slot S of level L, and its E.
 template <int NW, int SH, int K, bool WF, int L, int S, bool WALLS>
 __device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, float* sP,
-                                          float* eR, float* sR, const EdgeCtx& ec, int t, int y0,
-                                          int lane, int part) {
+                                          float* eR, const EdgeCtx& ec, int t, int y0, int lane,
+                                          int part) {
   constexpr int S2 = (S + 2) % 3;
   constexpr int NB = NW * SH / kMaxGroupPlanes;
   const RowCtx c = row_ctx(a);
@@ -539,8 +542,9 @@ __device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, fl
   bool bb = false;
   const WLBM_CONST uint32_t* codes = nullptr;
   if constexpr (WALLS)
-    walls_up<NW, SH, K, WF, L, S>(a, g, eR, sR, ec, y0 - (K - 1) + t - (L - 1), lane, part, rw,
-                                  tg, wtg, bb, bbm, bbt, codes);
+    walls_up<NW, SH, K, WF, L, S>(a, g, eR, sP + (2 * (L - 1) + ((t + 1) & 1)) * NB * 64, ec,
+                                  y0 - (K - 1) + t - (L - 1), lane, part, rw, tg, wtg, bb, bbm,
+                                  bbt, codes);
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
@@ -579,8 +583,8 @@ __device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, fl
 // ghost copies of periodic edges.
 template <int NW, int SH, int K, bool WF, int S, bool WALLS>
 __device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, float* sP,
-                                          const float* eR, float* sR, const EdgeCtx& ec, int t,
-                                          int x0, int y0, int lane, int part, bool out_lane) {
+                                          const float* eR, const EdgeCtx& ec, int t, int x0,
+                                          int y0, int lane, int part, bool out_lane) {
   constexpr int NB = NW * SH / kMaxGroupPlanes;
   const RowCtx c = row_ctx(a);
   const WLBM_CONST uint32_t* sels = row_ptr(a.sels[K - 1]);
@@ -616,8 +620,8 @@ __device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, fl
   bool bb = false;
   const WLBM_CONST uint32_t* codes = nullptr;
   if constexpr (WALLS)
-    walls_up<NW, SH, K, WF, K, S>(a, g, eR, sR, ec, ro, lane, part, rw, tg, wtg, bb, bbm, bbt,
-                                  codes);
+    walls_up<NW, SH, K, WF, K, S>(a, g, eR, sP + (2 * (K - 1) + ((t + 1) & 1)) * NB * 64, ec, ro,
+                                  lane, part, rw, tg, wtg, bb, bbm, bbt, codes);
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
@@ -667,26 +671,25 @@ __device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, fl
 // the three rows it reads exist.
 template <int NW, int SH, int K, bool WF, int S, bool WALLS>
 __device__ __forceinline__ void iteration(const FusedArgs& a, Ring<SH, K>& g, float* sP,
-                                          float* eR, float* sR, const EdgeCtx& ec, int t, int x0,
-                                          int y0, int lane, int part, uint32_t lcol,
-                                          bool out_lane) {
-  level1<NW, SH, K, WF, S, WALLS>(a, g, sP, eR, sR, ec, t, y0, lane, part, lcol);
+                                          float* eR, const EdgeCtx& ec, int t, int x0, int y0,
+                                          int lane, int part, uint32_t lcol, bool out_lane) {
+  level1<NW, SH, K, WF, S, WALLS>(a, g, sP, eR, ec, t, y0, lane, part, lcol);
   if constexpr (K >= 3) {
     if (t < 2) return;
-    level_mid<NW, SH, K, WF, 2, S, WALLS>(a, g, sP, eR, sR, ec, t, y0, lane, part);
+    level_mid<NW, SH, K, WF, 2, S, WALLS>(a, g, sP, eR, ec, t, y0, lane, part);
   }
   if constexpr (K >= 4) {
     if (t < 4) return;
-    level_mid<NW, SH, K, WF, 3, S, WALLS>(a, g, sP, eR, sR, ec, t, y0, lane, part);
+    level_mid<NW, SH, K, WF, 3, S, WALLS>(a, g, sP, eR, ec, t, y0, lane, part);
   }
   if (t < 2 * (K - 1)) return;
-  level_out<NW, SH, K, WF, S, WALLS>(a, g, sP, eR, sR, ec, t, x0, y0, lane, part, out_lane);
+  level_out<NW, SH, K, WF, S, WALLS>(a, g, sP, eR, ec, t, x0, y0, lane, part, out_lane);
 }
 
 // One block's strip (x0, y0): the rows and lanes of the iteration loop.
 template <int NW, int SH, bool WF, int K, bool WALLS>
 __device__ __forceinline__ void run_block(const FusedArgs& a, float* sP, float (*sEr)[K * 3 * kERow],
-                                          float* sR, int x0, int y0) {
+                                          int x0, int y0) {
   const int lane = threadIdx.x & 63;
   const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   // this lane's column; lanes past the ghost frame read its last column
@@ -740,11 +743,10 @@ __device__ __forceinline__ void run_block(const FusedArgs& a, float* sP, float (
   // a.rows + 2 (K - 1) is a multiple of 3 (the loop is unrolled by three)
   const int T = a.rows + 2 * (K - 1);
   for (int t = 0; t < T; t += 3) {
-    iteration<NW, SH, K, WF, 0, WALLS>(a, g, sP, eR, sR, ec, t, x0, y0, lane, part, lcol,
+    iteration<NW, SH, K, WF, 0, WALLS>(a, g, sP, eR, ec, t, x0, y0, lane, part, lcol, out_lane);
+    iteration<NW, SH, K, WF, 1, WALLS>(a, g, sP, eR, ec, t + 1, x0, y0, lane, part, lcol,
                                        out_lane);
-    iteration<NW, SH, K, WF, 1, WALLS>(a, g, sP, eR, sR, ec, t + 1, x0, y0, lane, part, lcol,
-                                       out_lane);
-    iteration<NW, SH, K, WF, 2, WALLS>(a, g, sP, eR, sR, ec, t + 2, x0, y0, lane, part, lcol,
+    iteration<NW, SH, K, WF, 2, WALLS>(a, g, sP, eR, ec, t + 2, x0, y0, lane, part, lcol,
                                        out_lane);
   }
 }
@@ -756,8 +758,6 @@ __global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
   __shared__ float sP[2 * K * NB * 64];
   // each wave's own copy of the E rings: step n, then levels 1 .. K-1
   __shared__ float sEr[NW][K * 3 * kERow];
-  // batch sums of the inflow of diffuse-wall nodes (WALLS kernels)
-  __shared__ float sR[WALLS ? NB * 64 : 1];
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (b % a.strips_x) * kStrip<K>;
   const int y0 = (b / a.strips_x) * a.rows;
@@ -772,11 +772,11 @@ __global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
     const bool cols_free =
         a.x_edge == kPeriodic || (x0 - K >= 1 && x0 - K + 63 <= a.nx - 2);
     if (rows_free && cols_free) {
-      run_block<NW, SH, WF, K, false>(a, sP, sEr, sR, x0, y0);
+      run_block<NW, SH, WF, K, false>(a, sP, sEr, x0, y0);
       return;
     }
   }
-  run_block<NW, SH, WF, K, WALLS>(a, sP, sEr, sR, x0, y0);
+  run_block<NW, SH, WF, K, WALLS>(a, sP, sEr, x0, y0);
 }
 
 // A lattice's arguments from the batch's device table, field by field
@@ -824,7 +824,6 @@ __global__ __launch_bounds__(64 * NW) void k_stepk_batch(const FusedBatchArgs b)
   constexpr int NB = NW * SH / kMaxGroupPlanes;
   __shared__ float sP[2 * K * NB * 64];
   __shared__ float sEr[NW][K * 3 * kERow];
-  __shared__ float sR[NB * 64];
   const int gb = xcd_tile(blockIdx.x, gridDim.x);
   const WLBM_CONST int* first = scalar_ptr(b.first);
   int j = 0;
@@ -845,9 +844,9 @@ __global__ __launch_bounds__(64 * NW) void k_stepk_batch(const FusedBatchArgs b)
                          (y0 - (K - 1) >= 1 && y0 + a.rows - 1 + (K - 1) <= a.ny - 2);
   const bool cols_free = a.x_edge == kPeriodic || (x0 - K >= 1 && x0 - K + 63 <= a.nx - 2);
   if (rows_free && cols_free)
-    run_block<NW, SH, WF, K, false>(a, sP, sEr, sR, x0, y0);
+    run_block<NW, SH, WF, K, false>(a, sP, sEr, x0, y0);
   else
-    run_block<NW, SH, WF, K, true>(a, sP, sEr, sR, x0, y0);
+    run_block<NW, SH, WF, K, true>(a, sP, sEr, x0, y0);
 }
 
 template <int NW, int SH, int K>
@@ -880,8 +879,13 @@ hipError_t launch_fused_batch_qk(const FusedBatchArgs& b, int q, bool per_cell, 
     case 6: return launchk_batch<6, 16, K>(b, per_cell, s);
     case 7: return launchk_batch<7, 16, K>(b, per_cell, s);
     case 8: return launchk_batch<8, 16, K>(b, per_cell, s);
-    default: return hipErrorInvalidValue;
+    default: break;
   }
+  if constexpr (K == 2) {
+    if (q == 192) return launchk_batch<12, 16, K>(b, per_cell, s);
+    if (q == 256) return launchk_batch<16, 16, K>(b, per_cell, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <int NW, int SH, bool WALLS, int K>
@@ -905,7 +909,9 @@ int blocks_per_cu_tmpl(bool wf) {
   return e == hipSuccess ? n : 0;
 }
 
-// Dispatch on q: one wave per 8 directions up to q = 64, one per 16 up to 128.
+// Dispatch on q: one wave per 8 directions up to q = 64, one per 16 up to 128
+// and for q = 192 and 256 (two steps per launch: a block of 16 waves must keep
+// to 128 registers a lane so that four waves share each SIMD).
 template <bool WALLS, int K>
 hipError_t launch_fused_qk(const FusedArgs& a, bool per_cell, hipStream_t s) {
   if (a.q <= 64) {
@@ -926,8 +932,14 @@ hipError_t launch_fused_qk(const FusedArgs& a, bool per_cell, hipStream_t s) {
     case 6: return launchk<6, 16, WALLS, K>(a, per_cell, s);
     case 7: return launchk<7, 16, WALLS, K>(a, per_cell, s);
     case 8: return launchk<8, 16, WALLS, K>(a, per_cell, s);
-    default: return hipErrorInvalidValue;
+    default: break;
   }
+  // 192 and 256 directions: 12 or 16 waves of 16, two steps per launch
+  if constexpr (K == 2) {
+    if (a.q == 192) return launchk<12, 16, WALLS, K>(a, per_cell, s);
+    if (a.q == 256) return launchk<16, 16, WALLS, K>(a, per_cell, s);
+  }
+  return hipErrorInvalidValue;
 }
 
 template <bool WALLS, int K>
@@ -950,8 +962,13 @@ int blocks_per_cu_qk(int q, bool per_cell) {
     case 6: return blocks_per_cu_tmpl<6, 16, WALLS, K>(per_cell);
     case 7: return blocks_per_cu_tmpl<7, 16, WALLS, K>(per_cell);
     case 8: return blocks_per_cu_tmpl<8, 16, WALLS, K>(per_cell);
-    default: return 0;
+    default: break;
   }
+  if constexpr (K == 2) {
+    if (q == 192) return blocks_per_cu_tmpl<12, 16, WALLS, K>(per_cell);
+    if (q == 256) return blocks_per_cu_tmpl<16, 16, WALLS, K>(per_cell);
+  }
+  return 0;
 }
 
 }  // namespace

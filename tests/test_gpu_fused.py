@@ -36,7 +36,8 @@ def _pair(nx, ny, q, fusion=1, **kw):
 
 
 @pytest.mark.parametrize("fusion", [2, 3, 4])
-@pytest.mark.parametrize("nx,ny,q,mfp", [(150, 41, 64, 9.0), (97, 23, 32, 4.0), (9, 8, 8, 1e9)])
+@pytest.mark.parametrize("nx,ny,q,mfp", [(150, 41, 64, 9.0), (97, 23, 32, 4.0), (9, 8, 8, 1e9),
+                                         (100, 30, 256, 6.0)])
 def test_two_and_three_steps_per_launch(fusion, nx, ny, q, mfp):
     """At most two, three or four steps per launch against single steps, for
     counts that leave every remainder (and odd chunk ends)."""
@@ -231,7 +232,8 @@ WALLED = {
 @pytest.mark.parametrize("edges", sorted(WALLED))
 @pytest.mark.parametrize("nx,ny,q,mfp,per_cell", [
     (150, 41, 64, 9.0, False), (97, 23, 32, 4.0, True), (9, 8, 8, 2.0, False),
-    (70, 130, 128, 6.0, True), (200, 3, 16, 1.5, False)])
+    (70, 130, 128, 6.0, True), (200, 3, 16, 1.5, False), (90, 37, 256, 7.0, False),
+    (60, 20, 192, 3.0, True)])
 def test_walled_lattices_keep_the_bits_of_single_steps(fusion, edges, nx, ny, q, mfp, per_cell):
     """Blackbody x / y edges and diffuse y walls (Sec. 2.6) inside the
     multi-step kernel: every level overwrites blackbody cells, zeroes the rows
