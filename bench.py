@@ -73,11 +73,13 @@ def recorded_traffic(path=TRAFFIC_FILE, sources=STEP_SOURCES):
         return None
 
 
-def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1, block_rows=None):
+def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1, block_rows=None,
+            tune=True):
     """Time `steps` steps (after `warmup`) of the lattice; with several steps
-    per launch the block height is fixed beforehand (given, or timed by the
-    library's tuner on a saved state that is then restored), so that no
-    tuning happens inside the timed region."""
+    per launch the block height is fixed beforehand (given, timed by the
+    library's tuner on a saved state that is then restored, or - tune False -
+    the library's launch model), so that no tuning happens inside the timed
+    region."""
     import numpy as np
     import torch
 
@@ -91,7 +93,8 @@ def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1, 
     lat.set_temperature(torch.from_numpy(T0))
     for k, rows in (block_rows or {}).items():
         lat.set_block_rows(k, rows)
-    if fusion in (2, 3, 4) and lat.block_rows(fusion) > 0 and fusion not in (block_rows or {}):
+    if (tune and fusion in (2, 3, 4) and lat.block_rows(fusion) > 0
+            and fusion not in (block_rows or {})):
         lat.tune_block_rows(fusion)
     if fusion in (2, 3, 4) and lat.block_rows(fusion) <= 0:
         raise SystemExit(f"bench.py: no block height for {fusion} steps per launch")
@@ -109,7 +112,9 @@ def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1, 
     ms = ev0.elapsed_time(ev1)
     energy, _, _ = lat.totals()
     # block height the library chose for the multi-step kernel, if any
-    run_gpu.block_rows = lat.block_rows(fusion) if fusion in (2, 3, 4) else None
+    run_gpu.steps_per_launch = lat.steps_per_launch
+    run_gpu.block_rows = (lat.block_rows(run_gpu.steps_per_launch)
+                          if run_gpu.steps_per_launch > 1 else None)
     lat.close()
     del lat
     torch.cuda.empty_cache()
@@ -524,8 +529,12 @@ def main():
     if not args.no_large:
         nl, ql = 4096, 256
         edges = dict(x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0, t_x_hi=0.0)
-        msl, walll, _ = run_gpu(nl, nl, ql, 10.0 * nl, args.large_steps, 10, edges)
+        # the launch model's block height (timing candidate heights would copy
+        # the 17 GB state once per candidate)
+        msl, walll, _ = run_gpu(nl, nl, ql, 10.0 * nl, args.large_steps, 10, edges, fusion=1,
+                                tune=False)
         st = msl / args.large_steps
+        kl = run_gpu.steps_per_launch
         bl = bytes_per_update(ql) * nl * nl * ql
         out["large"] = {
             "workload": "4096x4096, Q=256, blackbody x walls (T=1/0), diffuse y walls, Kn=10 "
@@ -534,9 +543,13 @@ def main():
             "value": round(nl * nl * ql / (st * 1e-3) / 1e9, 3),
             "unit": "Gupdates/s",
             "ms_per_step": round(st, 4),
-            "steps_per_launch": 1,
+            "steps_per_launch": kl,
+            "block_rows": run_gpu.block_rows,
             "bytes_per_update": bytes_per_update(ql),
+            # per-update bytes x updates per launch / launch time, and the
+            # share of the peak one pass over the arrays per launch takes
             "roofline_frac": round(bl / (st * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "hbm_frac_one_pass": round(bl / kl / (st * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         }
     if args.large:
         # the 2048 x 2048, Q = 128 inverse problem, checkpoints sized to HBM

@@ -377,6 +377,15 @@ wlbm_status wlbm_set_dir_split(wlbm_lattice* lat, int32_t split);
 /* Current split, or -1 for NULL. */
 int32_t wlbm_get_dir_split(const wlbm_lattice* lat);
 
+/* Time steps that wlbm_step advances per kernel launch on this lattice as
+ * it stands (edges, q, per-cell field, sources, step_fusion): 1 for the
+ * single-step kernel, else 2 .. 4 (calls and schedule chunks that do not
+ * divide evenly, and flux-window steps, still run single steps).  The
+ * automatic choice (step_fusion = 1) is four, and two for lattices with
+ * walls and q above 64 or a per-cell field, and for q above 128 (measured
+ * fastest on MI355X).  -1 for NULL. */
+int32_t wlbm_get_steps_per_launch(const wlbm_lattice* lat);
+
 /* Output rows per block of the kernel that advances k = 2, 3 or 4 steps per
  * launch, for the lattice's current weight mode (uniform or per-cell field):
  * the height fixed by wlbm_set_block_rows or chosen by wlbm_tune_block_rows,

@@ -148,6 +148,11 @@ wlbm_status wlbm_autotune(wlbm_lattice* l, void* d_state, size_t bytes, int32_t 
 }
 
 
+int32_t wlbm_get_steps_per_launch(const wlbm_lattice* l) {
+  if (!l) return -1;
+  return lattice_fuses(l) ? fused_k_max(l) : 1;
+}
+
 int32_t wlbm_get_block_rows(const wlbm_lattice* l, int32_t k) {
   if (!l || k < 2 || k > 4) return -1;
   if (!lattice_fuses(l)) return 0;

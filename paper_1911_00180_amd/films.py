@@ -9,7 +9,8 @@ of the 2D gray model (unit heat capacity and group velocity).
 
 For the steady state the run starts from the linear profile between the walls
 (the steady state does not depend on T0) and averages the flux over whole
-1000-step intervals.
+10000-step intervals; a film is steady when its kappa changes by less than
+1e-6 between two consecutive intervals, twice in a row.
 
 The sweep: 24 films, Nx = 512, Q = 128 evenly spaced directions,
 Kn_j = 10^(-2 + 4j/23) per film thickness (MFP = Kn Ny cells), Ny_j drawn by
@@ -81,39 +82,50 @@ class FilmSweep:
         for lat in self.lattices:
             lat.step(n)
 
-    def kappa_ratios(self):
-        """kappa_eff / kappa of every film from the last flux window."""
+    def kappa_ratios(self, only=None):
+        """kappa_eff / kappa from the last flux window, of every film or of the
+        films with the indices `only` (the others get None)."""
         out = []
-        for (kn, ny, mfp), lat in zip(self.films, self.lattices):
+        for j, ((kn, ny, mfp), lat) in enumerate(zip(self.films, self.lattices)):
+            if only is not None and j not in only:
+                out.append(None)
+                continue
             qx, _ = lat.flux_mean(1, self.nx - 1, averaged=True)
             out.append(qx * (self.nx - 1) / (self.t_hot - self.t_cold) / (mfp / 2.0))
         return out
 
-    def run_to_steady(self, check_every: int = 1000, rtol: float = 1e-4, repeats: int = 3,
-                      max_steps: int = 400_000, log=None):
+    def run_to_steady(self, check_every: int = 10000, rtol: float = 1e-6, repeats: int = 2,
+                      max_steps: int = 1_000_000, log=None, only=None):
         """Step (batched) until, for every film, kappa averaged over whole
-        check intervals changes by less than rtol in `repeats` consecutive
-        checks; films that have converged leave the batch.  (The flux of a
-        single step carries the aperiodic TAS pattern: ten-step averages
-        scatter by ~1e-2, thousand-step averages by ~1e-5 - 1e-4.)  `log`, if
-        given, is called with a progress line after every check."""
+        check intervals changes by less than rtol (the sweep's criterion,
+        1e-6) in `repeats` consecutive checks; films that have converged leave
+        the batch.  (The flux of a single step carries the aperiodic TAS
+        pattern: ten-step averages scatter by ~1e-2 from window to window,
+        thousand-step averages by ~1e-5 - 1e-4, so the check interval is long.)
+        Returns (kappa ratios, steps run, last relative change, converged
+        flags) of the films run (`only`: their indices; default all).  `log`,
+        if given, is called with a progress line after every check."""
         for lat in self.lattices:
             lat.set_flux_window(check_every)
-        active = list(range(len(self.films)))
+        active = list(range(len(self.films))) if only is None else list(only)
+        run = list(active)
         last = [None] * len(self.films)
+        rel = [None] * len(self.films)
         calm = [0] * len(self.films)
         steps = [0] * len(self.films)
         done_k = [None] * len(self.films)
-        batch = self.batch
+        batch = self.batch if only is None else Batch([self.lattices[j] for j in active])
         total = 0
         while active and total < max_steps:
             batch.step(check_every)
             total += check_every
-            ks = self.kappa_ratios()
+            ks = self.kappa_ratios(only=active)
             still = []
             for j in active:
                 steps[j] = total
-                if last[j] is not None and abs(ks[j] - last[j]) <= rtol * abs(ks[j]):
+                if last[j] is not None:
+                    rel[j] = abs(ks[j] - last[j]) / abs(ks[j])
+                if rel[j] is not None and rel[j] <= rtol:
                     calm[j] += 1
                 else:
                     calm[j] = 0
@@ -133,7 +145,8 @@ class FilmSweep:
             batch.close()
         for j in active:
             done_k[j] = last[j]
-        return done_k, steps, not active
+        return ([done_k[j] for j in run], [steps[j] for j in run], [rel[j] for j in run],
+                [j not in active for j in run])
 
     def close(self) -> None:
         self.batch.close()
@@ -145,6 +158,13 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--steps", type=int, default=10000, help="fixed steps for the timing")
     ap.add_argument("--steady", action="store_true", help="also run every film to steady state")
+    ap.add_argument("--rtol", type=float, default=1e-6,
+                    help="steady when kappa changes by less than this between checks")
+    ap.add_argument("--check-every", type=int, default=10000,
+                    help="steps per check (the flux is averaged over each interval)")
+    ap.add_argument("--second-steps", type=int, default=2_000_000,
+                    help="steps of the second pass (ten times longer windows) for the films "
+                         "not steady after the first; 0: none")
     args = ap.parse_args()
     films = film_set()
     sweep = FilmSweep(films)
@@ -169,11 +189,24 @@ def main():
     sweep.close()
     if args.steady:
         steady = FilmSweep(films, start="linear")
-        k, steps, ok = steady.run_to_steady(
+        k, steps, rel, ok = steady.run_to_steady(
+            check_every=args.check_every, rtol=args.rtol,
             log=lambda m: print(m, file=sys.stderr, flush=True))
         res["kappa_ratio"] = k
         res["steady_steps"] = steps
-        res["all_converged"] = ok
+        res["last_relative_change"] = rel
+        res["converged"] = ok
+        res["criterion"] = {"rtol": args.rtol, "check_every": args.check_every, "repeats": 2}
+        # films whose flux still scatters by more than rtol between windows
+        # (the nearly ballistic ones) continue with ten times longer windows
+        rest = [j for j, c in enumerate(ok) if not c]
+        if rest and args.second_steps:
+            k2, s2, r2, ok2 = steady.run_to_steady(
+                check_every=10 * args.check_every, rtol=args.rtol, max_steps=args.second_steps,
+                only=rest, log=lambda m: print(m, file=sys.stderr, flush=True))
+            res["second_pass"] = {"films": rest, "check_every": 10 * args.check_every,
+                                  "kappa_ratio": k2, "extra_steps": s2,
+                                  "last_relative_change": r2, "converged": ok2}
         steady.close()
     print(json.dumps(res))
 

@@ -157,6 +157,12 @@ class Lattice:
     def dir_split(self) -> int:
         return W.wlbm_get_dir_split(self.handle)
 
+    @property
+    def steps_per_launch(self) -> int:
+        """Time steps a kernel launch advances on this lattice (1: single-step
+        kernel)."""
+        return W.wlbm_get_steps_per_launch(self.handle)
+
     def block_rows(self, k: int) -> int:
         """Output rows per block of the kernel for k = 2, 3 or 4 steps per
         launch (fixed, tuned or the launch model's pick; 0 if this lattice runs

@@ -46,7 +46,7 @@ EXPORTS = (
     "wlbm_read_flux_mean",
     "wlbm_set_sources", "wlbm_flux_distribution", "wlbm_set_speeds",
     "wlbm_accumulate_temperature", "wlbm_get_block_rows", "wlbm_set_block_rows",
-    "wlbm_tune_block_rows", "wlbm_read_totals_noalloc",
+    "wlbm_tune_block_rows", "wlbm_read_totals_noalloc", "wlbm_get_steps_per_launch",
 )
 
 
@@ -127,6 +127,7 @@ def lib() -> ctypes.CDLL:
         "wlbm_tune_block_rows": (c_int, [c_void_p, c_void_p, c_size_t, c_int32, c_int32,
                                          POINTER(c_int32)]),
         "wlbm_read_totals_noalloc": (c_int, [c_void_p, c_void_p]),
+        "wlbm_get_steps_per_launch": (c_int32, [c_void_p]),
         "wlbm_autotune": (c_int, [c_void_p, c_void_p, c_size_t, c_int32, POINTER(ctypes.c_float),
                                   POINTER(c_int32)]),
         "wlbm_batch_bytes": (c_int, [POINTER(c_void_p), c_int32, POINTER(c_size_t)]),
@@ -356,6 +357,10 @@ def wlbm_get_block_rows(h: int, k: int) -> int:
 
 def wlbm_set_block_rows(h: int, k: int, rows: int) -> None:
     _check(lib().wlbm_set_block_rows(c_void_p(h), k, rows))
+
+
+def wlbm_get_steps_per_launch(h: int) -> int:
+    return lib().wlbm_get_steps_per_launch(c_void_p(h))
 
 
 def wlbm_read_totals_noalloc(h: int, d_totals) -> None:
