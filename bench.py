@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, 8 TB/s
 CSRC = os.path.join(ROOT, "paper_1911_00180_amd", "csrc")
 STEP_SOURCES = ("kernels.hip", "kernel_common.hpp", "device.hpp")
-FUSED_SOURCES = ("fused.hip", "kernel_common.hpp", "device.hpp")
+FUSED_SOURCES = ("fused.hip", "fused_kernel.hpp", "kernel_common.hpp", "device.hpp")
 ADJOINT_SOURCES = ("adjoint.hip", "kernel_common.hpp", "device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_1024x1024_q64_traffic.md")
 FUSED_TRAFFIC_FILES = {k: os.path.join(ROOT, "profiles", f"k_stepk{k}_1024x1024_q64_traffic.md")
@@ -34,8 +34,8 @@ FUSED_TRAFFIC_FILES = {k: os.path.join(ROOT, "profiles", f"k_stepk{k}_1024x1024_
 ADJOINT_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_adjoint_1024x1024_q64.md")
 # the kernels that run the default workload (1024 x 1024 periodic, Q = 64),
 # by time steps per launch
-KERNELS = {1: "k_step<4, false, false>", 2: "k_stepk<8, 8, false, 2>",
-           3: "k_stepk<8, 8, false, 3>", 4: "k_stepk<8, 8, false, 4>"}
+KERNELS = {1: "k_step<4, false, false>", 2: "k_stepk<8, 8, false, 2, false>",
+           3: "k_stepk<8, 8, false, 3, false>", 4: "k_stepk<8, 8, false, 4, false>"}
 
 
 def bytes_per_update(q: int, per_cell_w: bool = False) -> float:
@@ -421,14 +421,25 @@ def main():
         sys.exit(1)
 
     if args.copy_probe_mib:
-        n = args.copy_probe_mib * (1 << 20) // 4
-        a = torch.ones(n, device="cuda:0")
+        # five launches of the read+write stream kernel (16-byte loads and
+        # stores, four per thread) over buffers of this size: the reference
+        # for scaling the FETCH_SIZE and WRITE_SIZE counters
+        import ctypes
+        nbytes = args.copy_probe_mib * (1 << 20)
+        probe = ctypes.CDLL(os.path.join(ROOT, "paper_1911_00180_amd", "libwlbm_probe.so"))
+        probe.wlbm_probe_copy.restype = ctypes.c_int
+        probe.wlbm_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                          ctypes.c_int, ctypes.c_int, ctypes.c_void_p]
+        a = torch.ones(nbytes // 4, device="cuda:0")
         b = torch.empty_like(a)
+        stream = torch.cuda.current_stream().cuda_stream
         for _ in range(5):
-            b.copy_(a)
+            if probe.wlbm_probe_copy(a.data_ptr(), b.data_ptr(), nbytes, 4, 0, stream):
+                sys.exit("bench.py: stream probe failed")
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": n * 4, "copy_probe_bytes_written": n * 4,
-                          "launches": 5}))
+        assert torch.equal(a[:1024], b[:1024])
+        print(json.dumps({"copy_probe_bytes_read": nbytes, "copy_probe_bytes_written": nbytes,
+                          "launches": 5, "kernel": "k_copy (libwlbm_probe.so)"}))
         return
 
     nx = ny = 1024

@@ -448,8 +448,12 @@ wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, 
  * step counts, buffers and flux windows are updated).  Wall temperatures and
  * fields are read from the lattices at each call; a member whose q,
  * direction set or grid speeds no longer match its group's is refused
- * (WLBM_EINVAL: create the batch again).  One kernel launch per step by
- * default; see wlbm_batch_set_graphs. */
+ * (WLBM_EINVAL: create the batch again).  When every member takes the
+ * multi-step kernels and all have one q, one launch advances all of them by
+ * the fewest steps per launch that any member allows
+ * (wlbm_get_steps_per_launch), each member with its own block height
+ * (wlbm_get_block_rows); otherwise one kernel launch per step (see
+ * wlbm_batch_set_graphs).  Results do not depend on either. */
 wlbm_status wlbm_batch_step(wlbm_batch* batch, int64_t nsteps);
 
 /* on = 1: each whole schedule chunk (sched_chunk steps, when that is even)

@@ -70,11 +70,11 @@ int fused_row_candidates(int ny, int k, int* cand, int max_cand) {
   return n;
 }
 
-// Waves per block: one per 8 directions up to q = 64, one per 16 up to 128
-// and for q = 192 and 256 (those at most two steps per launch).
+// Waves per block: one per 8 directions up to q = 128, one per 16 for q = 192
+// and 256 (those at most two steps per launch).
 bool fused_supported(int q, int nx, int ny) {
   return nx >= 2 * kGhost && ny >= 2 && q % kMaxGroupPlanes == 0 &&
-         (q <= 64 || (q <= 128 && q % 16 == 0) || q == 192 || q == 256);
+         (q <= 128 || q == 192 || q == 256);
 }
 
 int fused_blocks_per_cu(int q, int k, bool per_cell, bool walls) {

@@ -12,18 +12,22 @@
 // A block owns a strip of kStrip columns and a.rows rows of the output.  Its
 // NW waves cover the same 64 columns x0-K .. x0+63-K (x0-2K .. x0+63-2K with
 // walls, kLane0), one per lane, and take
-// SH directions each (8, or 16 above Q = 64).  Rows are pipelined: at
+// SH directions each (8, or 16; see launch_fused_qk).  Rows are pipelined: at
 // iteration t the waves compute level 1 (step n+1) of row r = y0-(K-1)+t from
 // the step-n populations in HBM, then level l of row r-(l-1) for l = 2 .. K
 // from level l-1, whose rows r-l .. r-l+2 are held in registers, a ring of
 // three rows per level; level K is the output.  The one-cell shifts in x of
 // the pulled populations are lane shifts of a whole wave (DPP wave_shr /
 // wave_shl), so level l is valid on lanes l .. 63-l; E, which every
-// direction reads at its own move, is read from the wave's own LDS copy of
-// the three E rows at a shifted address.  E of each row of each level is
-// summed over the waves in LDS in k_step's order (8-direction batch sums in
-// batch order), and every update uses k_step's arithmetic, so one launch
-// gives the same bits as K k_step launches.
+// direction reads at its own move, is read from the block's LDS ring of E
+// rows at a shifted address.  E of each row of each level is summed over the
+// waves in LDS in k_step's order (8-direction batch sums in batch order), and
+// every update uses k_step's arithmetic, so one launch gives the same bits as
+// K k_step launches.  Every wave adds the same batch sums in the same order
+// and writes the row it has summed into the ring: the waves write the same
+// bits to the same words, so a wave reads back what it has written itself
+// and the ring needs no barrier of its own (a slot is overwritten only after
+// the barrier that follows the last reads of its old row).
 //
 // Edges.  A periodic axis reads the ghost frame (kGhost columns, one row),
 // which must hold the wrapped values on entry (the caller refreshes it with
@@ -107,11 +111,11 @@ __device__ __forceinline__ float shift_by(float v, int dx) {
 // c = dx + 1 | (dy + 1) << 2 | hop << 4 with (hx, hy) the move on a hop and
 // (0, 0) on a pause: the lane masks of hy = -1, hy = 0, hx > 0 and hx < 0,
 // then, for each iteration slot S, the byte offset of E at (x - dx, rho - dy)
-// in a wave's LDS copy of an E ring, from the lane's own entry in slot 0
+// in the block's LDS ring of E rows, from the lane's own entry in slot 0
 // (rows rho - 1, rho, rho + 1 are in slots S, S + 2, S + 1 mod 3).
 enum SelWord : int { kHyLo, kHyMid, kHxPos, kHxNeg, kEOff0, kEOff1, kEOff2, kSelWords = 8 };
-// Row length (floats) of a wave's private LDS copy of one E row: 64 lanes
-// and one pad either side for the lane shifts.
+// Row length (floats) of one E row in LDS: 64 lanes and one pad either side
+// for the lane shifts.
 constexpr int kERow = 66;
 struct CodeSel {
   uint32_t m[32][kSelWords];
@@ -216,7 +220,7 @@ __device__ __forceinline__ void decode_at(const WLBM_CONST uint32_t* codes, int 
 // T_g and W_g T_g of the boundary nodes behind diffuse wall `wall` at each
 // lane's column for the step of level L (codes, ins), from row rho of the
 // previous level: src holds this wave's populations of that row at its own
-// lane, eRow the wave's LDS copy of that row's E (per-cell mode: W E), Wrow
+// lane, eRow that row's E in the LDS ring (per-cell mode: W E), Wrow
 // the row's W at its own lane (per-cell mode).  Each wave sums its batches of
 // the packets leaving through the wall into sR; after an LDS barrier every
 // wave adds all batches in k_step's grouping (node_part_batches).  sR is the
@@ -389,8 +393,8 @@ __device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float
   const WLBM_CONST uint32_t* sels = row_ptr(a.sels[0]);
   const int i_begin = part * SH;
   float* p1 = sP + (t & 1) * NB * 64;
-  // step-n E of row r + 1 (loaded during the previous iteration) into this
-  // wave's LDS copy; rows r - 1 and r are there already
+  // step-n E of row r + 1 (loaded during the previous iteration) into the
+  // LDS ring; rows r - 1 and r are there already
   eR[S2 * kERow + 1 + lane] = g.En[S2];
   __builtin_amdgcn_wave_barrier();
   const float* eLane0 = eR + 1 + lane;
@@ -477,7 +481,7 @@ __device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float
       if constexpr (WF) g.W[0][S] = 0.f;
     }
   }
-  // this wave's LDS copy of the row, read with lane shifts by the next level
+  // the row into the LDS ring, read with lane shifts by the next level
   eR[(3 + S) * kERow + 1 + lane] = g.E[0][S];
   __builtin_amdgcn_wave_barrier();
 }
@@ -688,7 +692,7 @@ __device__ __forceinline__ void iteration(const FusedArgs& a, Ring<SH, K>& g, fl
 
 // One block's strip (x0, y0): the rows and lanes of the iteration loop.
 template <int NW, int SH, bool WF, int K, bool WALLS>
-__device__ __forceinline__ void run_block(const FusedArgs& a, float* sP, float (*sEr)[K * 3 * kERow],
+__device__ __forceinline__ void run_block(const FusedArgs& a, float* sP, float* sEr,
                                           int x0, int y0) {
   const int lane = threadIdx.x & 63;
   const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -732,7 +736,7 @@ __device__ __forceinline__ void run_block(const FusedArgs& a, float* sP, float (
       g.En[k] = valid ? Ev : 0.f;
     }
   }
-  float* eR = sEr[part];
+  float* eR = sEr;
   // the pads either side of each row (read only by lanes whose results are
   // never used) hold zero
   if (lane < 3 * K) eR[lane * kERow] = eR[lane * kERow + kERow - 1] = 0.f;
@@ -756,8 +760,8 @@ __global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
   constexpr int NB = NW * SH / kMaxGroupPlanes;
   // E batch sums: [level 1 .. K][row parity][batch of 8 directions][lane]
   __shared__ float sP[2 * K * NB * 64];
-  // each wave's own copy of the E rings: step n, then levels 1 .. K-1
-  __shared__ float sEr[NW][K * 3 * kERow];
+  // the E rings of the block: step n, then levels 1 .. K-1
+  __shared__ float sEr[K * 3 * kERow];
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (b % a.strips_x) * kStrip<K>;
   const int y0 = (b / a.strips_x) * a.rows;
@@ -823,7 +827,7 @@ template <int NW, int SH, bool WF, int K>
 __global__ __launch_bounds__(64 * NW) void k_stepk_batch(const FusedBatchArgs b) {
   constexpr int NB = NW * SH / kMaxGroupPlanes;
   __shared__ float sP[2 * K * NB * 64];
-  __shared__ float sEr[NW][K * 3 * kERow];
+  __shared__ float sEr[K * 3 * kERow];
   const int gb = xcd_tile(blockIdx.x, gridDim.x);
   const WLBM_CONST int* first = scalar_ptr(b.first);
   int j = 0;
@@ -861,24 +865,40 @@ hipError_t launchk_batch(const FusedBatchArgs& b, bool wf, hipStream_t s) {
 
 template <int K>
 hipError_t launch_fused_batch_qk(const FusedBatchArgs& b, int q, bool per_cell, hipStream_t s) {
-  if (q <= 64) {
-    switch (q / 8) {
-      case 1: return launchk_batch<1, 8, K>(b, per_cell, s);
-      case 2: return launchk_batch<2, 8, K>(b, per_cell, s);
-      case 3: return launchk_batch<3, 8, K>(b, per_cell, s);
-      case 4: return launchk_batch<4, 8, K>(b, per_cell, s);
-      case 5: return launchk_batch<5, 8, K>(b, per_cell, s);
-      case 6: return launchk_batch<6, 8, K>(b, per_cell, s);
-      case 7: return launchk_batch<7, 8, K>(b, per_cell, s);
-      case 8: return launchk_batch<8, 8, K>(b, per_cell, s);
-      default: return hipErrorInvalidValue;
+  if constexpr (K == 2) {
+    switch (q) {
+      case 80: return launchk_batch<5, 16, K>(b, per_cell, s);
+      case 96: return launchk_batch<6, 16, K>(b, per_cell, s);
+      case 112: return launchk_batch<7, 16, K>(b, per_cell, s);
+      case 128: return launchk_batch<8, 16, K>(b, per_cell, s);
+      default: break;
     }
   }
-  switch (q / 16) {
-    case 5: return launchk_batch<5, 16, K>(b, per_cell, s);
-    case 6: return launchk_batch<6, 16, K>(b, per_cell, s);
-    case 7: return launchk_batch<7, 16, K>(b, per_cell, s);
-    case 8: return launchk_batch<8, 16, K>(b, per_cell, s);
+  switch (q) {
+    case 8: return launchk_batch<1, 8, K>(b, per_cell, s);
+    case 16: return launchk_batch<2, 8, K>(b, per_cell, s);
+    case 24: return launchk_batch<3, 8, K>(b, per_cell, s);
+    case 32: return launchk_batch<4, 8, K>(b, per_cell, s);
+    case 40: return launchk_batch<5, 8, K>(b, per_cell, s);
+    case 48: return launchk_batch<6, 8, K>(b, per_cell, s);
+    case 56: return launchk_batch<7, 8, K>(b, per_cell, s);
+    case 64: return launchk_batch<8, 8, K>(b, per_cell, s);
+    case 72: return launchk_batch<9, 8, K>(b, per_cell, s);
+    case 80: 
+      if constexpr (K != 2) return launchk_batch<10, 8, K>(b, per_cell, s);
+      break;
+    case 88: return launchk_batch<11, 8, K>(b, per_cell, s);
+    case 96: 
+      if constexpr (K != 2) return launchk_batch<12, 8, K>(b, per_cell, s);
+      break;
+    case 104: return launchk_batch<13, 8, K>(b, per_cell, s);
+    case 112: 
+      if constexpr (K != 2) return launchk_batch<14, 8, K>(b, per_cell, s);
+      break;
+    case 120: return launchk_batch<15, 8, K>(b, per_cell, s);
+    case 128: 
+      if constexpr (K != 2) return launchk_batch<16, 8, K>(b, per_cell, s);
+      break;
     default: break;
   }
   if constexpr (K == 2) {
@@ -909,32 +929,53 @@ int blocks_per_cu_tmpl(bool wf) {
   return e == hipSuccess ? n : 0;
 }
 
-// Dispatch on q: one wave per 8 directions up to q = 64, one per 16 up to 128
-// and for q = 192 and 256 (two steps per launch: a block of 16 waves must keep
-// to 128 registers a lane so that four waves share each SIMD).
+// Dispatch on q: one wave per 8 directions up to q = 128 (blocks of up to 16
+// waves), except at two steps per launch for q = 80, 96, 112 and 128, which
+// run half as many waves of 16 directions (each wave then adds its E batch
+// sums for twice the directions; three or four steps need the registers of
+// 8 directions a wave), and 12 or 16 waves of 16 directions for q = 192 and
+// 256 (two steps per launch: a block of 16 waves must keep to 128 registers
+// a lane so that four waves share each SIMD).  Measured on MI355X, 1024 x
+// 1024 periodic, q = 128: two steps 997 G updates/s with 16 directions a
+// wave, 963 with 8; four steps 1352 with 8 (1022 with 16).
 template <bool WALLS, int K>
 hipError_t launch_fused_qk(const FusedArgs& a, bool per_cell, hipStream_t s) {
-  if (a.q <= 64) {
-    switch (a.q / 8) {
-      case 1: return launchk<1, 8, WALLS, K>(a, per_cell, s);
-      case 2: return launchk<2, 8, WALLS, K>(a, per_cell, s);
-      case 3: return launchk<3, 8, WALLS, K>(a, per_cell, s);
-      case 4: return launchk<4, 8, WALLS, K>(a, per_cell, s);
-      case 5: return launchk<5, 8, WALLS, K>(a, per_cell, s);
-      case 6: return launchk<6, 8, WALLS, K>(a, per_cell, s);
-      case 7: return launchk<7, 8, WALLS, K>(a, per_cell, s);
-      case 8: return launchk<8, 8, WALLS, K>(a, per_cell, s);
-      default: return hipErrorInvalidValue;
+  if constexpr (K == 2) {
+    switch (a.q) {
+      case 80: return launchk<5, 16, WALLS, K>(a, per_cell, s);
+      case 96: return launchk<6, 16, WALLS, K>(a, per_cell, s);
+      case 112: return launchk<7, 16, WALLS, K>(a, per_cell, s);
+      case 128: return launchk<8, 16, WALLS, K>(a, per_cell, s);
+      default: break;
     }
   }
-  switch (a.q / 16) {
-    case 5: return launchk<5, 16, WALLS, K>(a, per_cell, s);
-    case 6: return launchk<6, 16, WALLS, K>(a, per_cell, s);
-    case 7: return launchk<7, 16, WALLS, K>(a, per_cell, s);
-    case 8: return launchk<8, 16, WALLS, K>(a, per_cell, s);
+  switch (a.q) {
+    case 8: return launchk<1, 8, WALLS, K>(a, per_cell, s);
+    case 16: return launchk<2, 8, WALLS, K>(a, per_cell, s);
+    case 24: return launchk<3, 8, WALLS, K>(a, per_cell, s);
+    case 32: return launchk<4, 8, WALLS, K>(a, per_cell, s);
+    case 40: return launchk<5, 8, WALLS, K>(a, per_cell, s);
+    case 48: return launchk<6, 8, WALLS, K>(a, per_cell, s);
+    case 56: return launchk<7, 8, WALLS, K>(a, per_cell, s);
+    case 64: return launchk<8, 8, WALLS, K>(a, per_cell, s);
+    case 72: return launchk<9, 8, WALLS, K>(a, per_cell, s);
+    case 80: 
+      if constexpr (K != 2) return launchk<10, 8, WALLS, K>(a, per_cell, s);
+      break;
+    case 88: return launchk<11, 8, WALLS, K>(a, per_cell, s);
+    case 96: 
+      if constexpr (K != 2) return launchk<12, 8, WALLS, K>(a, per_cell, s);
+      break;
+    case 104: return launchk<13, 8, WALLS, K>(a, per_cell, s);
+    case 112: 
+      if constexpr (K != 2) return launchk<14, 8, WALLS, K>(a, per_cell, s);
+      break;
+    case 120: return launchk<15, 8, WALLS, K>(a, per_cell, s);
+    case 128: 
+      if constexpr (K != 2) return launchk<16, 8, WALLS, K>(a, per_cell, s);
+      break;
     default: break;
   }
-  // 192 and 256 directions: 12 or 16 waves of 16, two steps per launch
   if constexpr (K == 2) {
     if (a.q == 192) return launchk<12, 16, WALLS, K>(a, per_cell, s);
     if (a.q == 256) return launchk<16, 16, WALLS, K>(a, per_cell, s);
@@ -944,24 +985,40 @@ hipError_t launch_fused_qk(const FusedArgs& a, bool per_cell, hipStream_t s) {
 
 template <bool WALLS, int K>
 int blocks_per_cu_qk(int q, bool per_cell) {
-  if (q <= 64) {
-    switch (q / 8) {
-      case 1: return blocks_per_cu_tmpl<1, 8, WALLS, K>(per_cell);
-      case 2: return blocks_per_cu_tmpl<2, 8, WALLS, K>(per_cell);
-      case 3: return blocks_per_cu_tmpl<3, 8, WALLS, K>(per_cell);
-      case 4: return blocks_per_cu_tmpl<4, 8, WALLS, K>(per_cell);
-      case 5: return blocks_per_cu_tmpl<5, 8, WALLS, K>(per_cell);
-      case 6: return blocks_per_cu_tmpl<6, 8, WALLS, K>(per_cell);
-      case 7: return blocks_per_cu_tmpl<7, 8, WALLS, K>(per_cell);
-      case 8: return blocks_per_cu_tmpl<8, 8, WALLS, K>(per_cell);
-      default: return 0;
+  if constexpr (K == 2) {
+    switch (q) {
+      case 80: return blocks_per_cu_tmpl<5, 16, WALLS, K>(per_cell);
+      case 96: return blocks_per_cu_tmpl<6, 16, WALLS, K>(per_cell);
+      case 112: return blocks_per_cu_tmpl<7, 16, WALLS, K>(per_cell);
+      case 128: return blocks_per_cu_tmpl<8, 16, WALLS, K>(per_cell);
+      default: break;
     }
   }
-  switch (q / 16) {
-    case 5: return blocks_per_cu_tmpl<5, 16, WALLS, K>(per_cell);
-    case 6: return blocks_per_cu_tmpl<6, 16, WALLS, K>(per_cell);
-    case 7: return blocks_per_cu_tmpl<7, 16, WALLS, K>(per_cell);
-    case 8: return blocks_per_cu_tmpl<8, 16, WALLS, K>(per_cell);
+  switch (q) {
+    case 8: return blocks_per_cu_tmpl<1, 8, WALLS, K>(per_cell);
+    case 16: return blocks_per_cu_tmpl<2, 8, WALLS, K>(per_cell);
+    case 24: return blocks_per_cu_tmpl<3, 8, WALLS, K>(per_cell);
+    case 32: return blocks_per_cu_tmpl<4, 8, WALLS, K>(per_cell);
+    case 40: return blocks_per_cu_tmpl<5, 8, WALLS, K>(per_cell);
+    case 48: return blocks_per_cu_tmpl<6, 8, WALLS, K>(per_cell);
+    case 56: return blocks_per_cu_tmpl<7, 8, WALLS, K>(per_cell);
+    case 64: return blocks_per_cu_tmpl<8, 8, WALLS, K>(per_cell);
+    case 72: return blocks_per_cu_tmpl<9, 8, WALLS, K>(per_cell);
+    case 80: 
+      if constexpr (K != 2) return blocks_per_cu_tmpl<10, 8, WALLS, K>(per_cell);
+      break;
+    case 88: return blocks_per_cu_tmpl<11, 8, WALLS, K>(per_cell);
+    case 96: 
+      if constexpr (K != 2) return blocks_per_cu_tmpl<12, 8, WALLS, K>(per_cell);
+      break;
+    case 104: return blocks_per_cu_tmpl<13, 8, WALLS, K>(per_cell);
+    case 112: 
+      if constexpr (K != 2) return blocks_per_cu_tmpl<14, 8, WALLS, K>(per_cell);
+      break;
+    case 120: return blocks_per_cu_tmpl<15, 8, WALLS, K>(per_cell);
+    case 128: 
+      if constexpr (K != 2) return blocks_per_cu_tmpl<16, 8, WALLS, K>(per_cell);
+      break;
     default: break;
   }
   if constexpr (K == 2) {
