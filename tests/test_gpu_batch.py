@@ -235,7 +235,8 @@ def test_batch_of_different_direction_sets_equals_one_by_one():
 
 
 @pytest.mark.parametrize("q,per_cell,fusion", [(128, False, 1), (64, True, 1), (32, False, 3),
-                                               (16, False, 4), (256, False, 1)])
+                                               (16, False, 4), (256, False, 1), (128, False, 3),
+                                               (120, True, 4), (88, False, 2)])
 def test_batched_multi_step_launches_keep_the_bits_of_single_steps(q, per_cell, fusion):
     """Films of several thicknesses (blackbody x, diffuse y) and a periodic and a
     blackbody-y lattice in one batch: the batch advances several steps per launch

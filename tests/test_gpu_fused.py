@@ -37,7 +37,8 @@ def _pair(nx, ny, q, fusion=1, **kw):
 
 @pytest.mark.parametrize("fusion", [2, 3, 4])
 @pytest.mark.parametrize("nx,ny,q,mfp", [(150, 41, 64, 9.0), (97, 23, 32, 4.0), (9, 8, 8, 1e9),
-                                         (100, 30, 256, 6.0)])
+                                         (100, 30, 256, 6.0), (61, 19, 120, 5.0),
+                                         (77, 26, 72, 3.0), (130, 50, 128, 8.0)])
 def test_two_and_three_steps_per_launch(fusion, nx, ny, q, mfp):
     """At most two, three or four steps per launch against single steps, for
     counts that leave every remainder (and odd chunk ends)."""
@@ -196,7 +197,7 @@ def test_fused_random_shapes(seed):
     rng = np.random.default_rng(1000 + seed)
     nx = int(rng.integers(8, 301))
     ny = int(rng.integers(2, 91))
-    q = int(rng.choice([8, 16, 24, 32, 48, 64, 80, 96, 112, 128]))
+    q = int(rng.choice([8, 16, 24, 32, 48, 64, 72, 80, 88, 96, 104, 112, 120, 128]))
     kind = "ring" if rng.random() < 0.3 else "uniform"
     fusion = int(rng.integers(1, 5))
     chunk = int(rng.integers(16, 64))
@@ -233,7 +234,7 @@ WALLED = {
 @pytest.mark.parametrize("nx,ny,q,mfp,per_cell", [
     (150, 41, 64, 9.0, False), (97, 23, 32, 4.0, True), (9, 8, 8, 2.0, False),
     (70, 130, 128, 6.0, True), (200, 3, 16, 1.5, False), (90, 37, 256, 7.0, False),
-    (60, 20, 192, 3.0, True)])
+    (60, 20, 192, 3.0, True), (45, 29, 88, 5.0, False), (103, 14, 104, 2.5, True)])
 def test_walled_lattices_keep_the_bits_of_single_steps(fusion, edges, nx, ny, q, mfp, per_cell):
     """Blackbody x / y edges and diffuse y walls (Sec. 2.6) inside the
     multi-step kernel: every level overwrites blackbody cells, zeroes the rows
@@ -266,7 +267,7 @@ def test_walled_random_shapes(seed):
     rng = np.random.default_rng(2000 + seed)
     nx = int(rng.integers(8, 260))
     ny = int(rng.integers(2, 80))
-    q = int(rng.choice([8, 16, 24, 32, 48, 64, 80, 96, 112, 128]))
+    q = int(rng.choice([8, 16, 24, 32, 48, 64, 72, 80, 88, 96, 104, 112, 120, 128]))
     kind = "ring" if rng.random() < 0.3 else "uniform"
     edges = dict(WALLED[sorted(WALLED)[int(rng.integers(0, len(WALLED)))]])
     for key in ("t_x_lo", "t_x_hi", "t_y_lo", "t_y_hi"):
