@@ -55,7 +55,7 @@ __device__ __forceinline__ void add_class(float (&h)[8], int c, float w, float v
 
 constexpr int kAdjRed = 10;  // values per cell reduced across waves
 
-template <int NW, bool WF, bool EDGE>
+template <int NW, bool WF, bool EDGE, bool GHOST = false>
 __device__ __forceinline__ void adj_sweep(const AdjArgs& a, float* sRed, int x0, int y0) {
   using T = TileShape<NW>;
   constexpr int D = T::D;
@@ -76,7 +76,7 @@ __device__ __forceinline__ void adj_sweep(const AdjArgs& a, float* sRed, int x0,
   const uint32_t boff = uint32_t(cell(ok ? x : 0, ok ? y : 0, pitch) * 4);
   const bool px = a.x_edge == kPeriodic;
   const bool py = a.y_edge == kPeriodic;
-  const bool ghost = EDGE && ok && has_ghost(x, y, a.nx, a.ny, px, py);
+  const bool ghost = (EDGE || GHOST) && ok && has_ghost(x, y, a.nx, a.ny, px, py);
   const bool wall = EDGE && ok && wall_cell(x, y, a.nx, a.ny, a.x_edge, a.y_edge);
 
   // G(z) from the eight move-class partial sums, in a fixed order
@@ -95,17 +95,22 @@ __device__ __forceinline__ void adj_sweep(const AdjArgs& a, float* sRed, int x0,
   float acc_neq = 0.f, acc_pause = 0.f, wsum = 0.f;
   float h[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
   const int share = a.q / NW;
-  for (int i0 = part * share; i0 < (part + 1) * share; i0 += D) {
-    uint32_t words[D / 4], nwords[D / 4];
+  // GHOST tiles (both edges periodic, no ragged lanes): byte offsets of this
+  // cell's ghost copies, stored only where the lane has them
+  const bool gxl = GHOST && (x == 0 || x == a.nx - 1);
+  const bool gyl = GHOST && (y == 0 || y == a.ny - 1);
+  const uint32_t gbx = boff + uint32_t((x == 0 ? a.nx : -a.nx) * 4);
+  const uint32_t gby = boff + uint32_t((y == 0 ? a.ny : -a.ny) * pitch * 4);
+  const uint32_t gbxy = gby + uint32_t((x == 0 ? a.nx : -a.nx) * 4);
+  // lam at z + h_j, the forward state and (paused directions) lam at z + s_j
+  // of the batch of directions i0 .. i0 + D - 1
+  auto load = [&](int i0, float (&lh)[D], float (&ep)[D], float (&ls)[D]) {
+    uint32_t words[D / 4];
 #pragma unroll
-    for (int k = 0; k < D / 4; ++k) {
-      words[k] = codes[(i0 >> 2) + k];
-      nwords[k] = codes_next[(i0 >> 2) + k];
-    }
+    for (int k = 0; k < D / 4; ++k) words[k] = codes[(i0 >> 2) + k];
     const rsrc_t rl =
         make_rsrc(a.lam_in + (long long)i0 * plane - halo, uint32_t((D * plane + 2 * halo) * 4));
     const rsrc_t re = make_rsrc(a.e_prev + (long long)i0 * plane, uint32_t(D * plane * 4));
-    float lh[D], ep[D], ls[D];
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       int dx, dy;
@@ -115,6 +120,14 @@ __device__ __forceinline__ void adj_sweep(const AdjArgs& a, float* sRed, int x0,
       lh[d] = buf_load(rl, boff, uint32_t((d * plane + halo + (hop ? sh : 0)) * 4));
       ep[d] = buf_load(re, boff, uint32_t(d * plane_bytes));
       ls[d] = hop ? 0.f : buf_load(rl, boff, uint32_t((d * plane + halo + sh) * 4));
+    }
+  };
+  auto process = [&](int i0, const float (&lh)[D], const float (&ep)[D], const float (&ls)[D]) {
+    uint32_t words[D / 4], nwords[D / 4];
+#pragma unroll
+    for (int k = 0; k < D / 4; ++k) {
+      words[k] = codes[(i0 >> 2) + k];
+      nwords[k] = codes_next[(i0 >> 2) + k];
     }
     const rsrc_t ro = make_rsrc(a.lam_out + (long long)i0 * plane, uint32_t(D * plane * 4));
 #pragma unroll
@@ -144,7 +157,17 @@ __device__ __forceinline__ void adj_sweep(const AdjArgs& a, float* sRed, int x0,
         }
       }
       buf_store_stream(mu, ro, boff, uint32_t(d * plane_bytes));
+      if constexpr (GHOST) {
+        if (gxl) buf_store_stream(mu, ro, gbx, uint32_t(d * plane_bytes));
+        if (gyl) buf_store_stream(mu, ro, gby, uint32_t(d * plane_bytes));
+        if (gxl && gyl) buf_store_stream(mu, ro, gbxy, uint32_t(d * plane_bytes));
+      }
     }
+  };
+  for (int i0 = part * share; i0 < (part + 1) * share; i0 += D) {
+    float lh[D], ep[D], ls[D];
+    load(i0, lh, ep, ls);
+    process(i0, lh, ep, ls);
   }
   float gw = fmaf(Ep, acc_pause, -acc_neq);
 
@@ -192,7 +215,13 @@ __global__ __launch_bounds__(kBlock) void k_adjoint(const AdjArgs a) {
   const int x0 = tx * T::TX;
   const int y0 = ty * T::TY;
   const bool edge = x0 == 0 || x0 + T::TX >= a.nx || y0 == 0 || y0 + T::TY >= a.ny;
-  if (edge)
+  // on a lattice with both edges periodic, an edge tile that holds no
+  // ragged lane only adds the ghost copies to the interior path
+  const bool pghost = edge && a.x_edge == kPeriodic && a.y_edge == kPeriodic &&
+                      x0 + T::TX <= a.nx && y0 + T::TY <= a.ny;
+  if (pghost)
+    adj_sweep<NW, WF, false, true>(a, sRed, x0, y0);
+  else if (edge)
     adj_sweep<NW, WF, true>(a, sRed, x0, y0);
   else
     adj_sweep<NW, WF, false>(a, sRed, x0, y0);
