@@ -71,7 +71,7 @@ Carve carve(const wlbm_params& p) {
   c.sched = take(size_t(2) * chunk_steps(p) * size_t(p.q));
   // per step, the multi-step kernels' pull offsets and selection-table
   // offsets of every direction (FusedArgs::pulls, FusedArgs::sels)
-  c.pulls = take(fusable(p) ? size_t(4) * chunk_steps(p) * size_t(p.q) * sizeof(uint32_t) : 0);
+  c.pulls = take(size_t(4) * chunk_steps(p) * size_t(p.q) * sizeof(uint32_t));
   // per step, the inward-weight sums of diffuse walls (FusedArgs::ins)
   c.ins = take(fusable(p) ? size_t(2) * chunk_steps(p) * 4 * sizeof(float) : 0);
   c.wtab = take(size_t(p.q) * sizeof(float));
@@ -379,7 +379,7 @@ wlbm_status wlbm_create(const wlbm_params* p, void* d_workspace, size_t ws_bytes
   const size_t stage = std::max<size_t>(size_t(l->chunk) * p->q, 4 * size_t(p->q) * sizeof(float));
   for (int k = 0; k < 2; ++k) {
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&l->pinned[k]), stage, hipHostMallocDefault);
-    if (e == hipSuccess && fusable(*p))
+    if (e == hipSuccess)
       e = hipHostMalloc(reinterpret_cast<void**>(&l->pinned_pulls[k]),
                         size_t(2) * l->chunk * p->q * sizeof(uint32_t), hipHostMallocDefault);
     if (e == hipSuccess && fusable(*p))
@@ -635,8 +635,9 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
     // Build the schedule rows of this chunk (Sec. 2.3, Sec. 2.5) and the
     // per-step sums of inward weights used by diffuse walls.
     uint8_t* rows = l->pinned[slot];
-    // with it, the multi-step kernels' first-step pull offsets (FusedArgs::pulls)
-    uint32_t* pw = fuse ? l->pinned_pulls[slot] : nullptr;
+    // with it, per step and direction, the pull offset and the selection-table
+    // offset (FusedArgs::pulls / sels, StepArgs::pulls / sels)
+    uint32_t* pw = l->pinned_pulls[slot];
     const uint32_t pitch4 = uint32_t(l->g.pitch) * 4u, plane4 = uint32_t(l->g.plane) * 4u;
     insums.assign(size_t(cnt) * 4, 0.f);
     for (int j = 0; j < cnt; ++j) {
@@ -672,7 +673,7 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
     if (e == hipSuccess && pw)
       e = hipMemcpyAsync(dev_pulls, pw, size_t(2 * cnt) * q * sizeof(uint32_t),
                          hipMemcpyHostToDevice, l->stream);
-    if (e == hipSuccess && pw) {
+    if (e == hipSuccess && fuse) {
       std::memcpy(l->pinned_ins[slot], insums.data(), size_t(cnt) * 4 * sizeof(float));
       e = hipMemcpyAsync(dev_ins, l->pinned_ins[slot], size_t(cnt) * 4 * sizeof(float),
                          hipMemcpyHostToDevice, l->stream);
@@ -744,6 +745,8 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
         continue;
       }
       a.codes = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j) * q);
+      a.pulls = dev_pulls + size_t(2 * j) * q;
+      a.sels = dev_pulls + size_t(2 * j + 1) * q;
       a.in_lo_hop = insums[4 * j];
       a.in_lo_all = insums[4 * j + 1];
       a.in_hi_hop = insums[4 * j + 2];

@@ -43,6 +43,11 @@ struct StepArgs {
   float* qsx;             // heat-flux window sums, [ny][nx] (flux mode)
   float* qsy;
   const uint32_t* codes;  // schedule row of this step
+  // k_step only: per direction, the byte offset of its pulled population and
+  // of its entry in the multi-step kernels' selection table (move code times
+  // kSelEntryBytes) for this step; k_step_batch decodes the codes instead
+  const uint32_t* pulls;
+  const uint32_t* sels;
   const float* wtab;      // [q] weights
   const float* sxtab;     // [q] unit vectors
   const float* sytab;

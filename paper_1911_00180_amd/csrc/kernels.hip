@@ -106,12 +106,38 @@ __device__ __forceinline__ void node_emit(const StepArgs& a, int wall, int X, fl
   wtg = Wg * tg;
 }
 
+// For each move code c = dx + 1 | (dy + 1) << 2 | hop << 4: the byte offset,
+// from a cell's own entry in the LDS tile of E (rows of TileShape::LP = 66
+// floats), of the entry at (x - dx, y - dy), and of W where the pulled
+// population was (the same on a hop, 0 on a pause).
+struct StepCodeTab {
+  int32_t eoff[32];
+  int32_t woff[32];
+};
+constexpr StepCodeTab make_step_code_tab() {
+  StepCodeTab t{};
+  for (int c = 0; c < 32; ++c) {
+    const int dx = (c & 3) - 1, dy = ((c >> 2) & 3) - 1;
+    const bool hop = (c >> 4) & 1;
+    t.eoff[c] = -4 * (dy * 66 + dx);
+    t.woff[c] = hop ? t.eoff[c] : 0;
+  }
+  return t;
+}
+__constant__ StepCodeTab kStepCode = make_step_code_tab();
+
 // Load the populations of directions i0 .. i0+D-1 that stream into the cell
 // at byte offset boff: the DDED of direction i comes from the cell one
 // pending worm move back on a hop and from the cell itself on a pause.  One
 // buffer descriptor covers the batch (direction d is d planes further on)
 // plus one row and column either side, so the shifted offset stays positive.
-template <int D>
+//
+// TAB: the host has uploaded, per step and direction, that load's byte offset
+// (pulls: (1 - hy) pitch 4 + 4 (1 - hx) + (i mod 8) plane 4, the offset below)
+// and the byte offset of the direction's entry in the selection table of the
+// multi-step kernels (sels: its move code times kSelEntryBytes), so the
+// kernel reads offsets instead of decoding codes in scalar code.
+template <int D, bool TAB>
 __device__ __forceinline__ void load_batch(const StepArgs& a, int i0, uint32_t boff,
                                            float (&v)[D]) {
   const WLBM_CONST uint32_t* codes = scalar_ptr(a.codes);
@@ -119,10 +145,16 @@ __device__ __forceinline__ void load_batch(const StepArgs& a, int i0, uint32_t b
   const long long plane = a.plane;
   const uint32_t win_bytes = uint32_t((D * plane + 2 * (pitch + 1)) * 4);
   const uint32_t plane_bytes = uint32_t(plane * 4);
+  const rsrc_t rs = make_rsrc(a.e_in + (long long)i0 * plane - (pitch + 1), win_bytes);
+  if constexpr (TAB) {
+    const WLBM_CONST uint32_t* pulls = scalar_ptr(a.pulls);
+#pragma unroll
+    for (int d = 0; d < D; ++d) v[d] = buf_load(rs, boff, pulls[i0 + d]);
+    return;
+  }
   uint32_t words[D / 4];
 #pragma unroll
   for (int k = 0; k < D / 4; ++k) words[k] = codes[(i0 >> 2) + k];
-  const rsrc_t rs = make_rsrc(a.e_in + (long long)i0 * plane - (pitch + 1), win_bytes);
 #pragma unroll
   for (int d = 0; d < D; ++d) {
     int dx, dy;
@@ -147,7 +179,7 @@ __device__ __forceinline__ void load_batch(const StepArgs& a, int i0, uint32_t b
 // direction split: each batch of D = 8 directions is summed in direction
 // order, then the batch sums are added in batch order (sBat holds them when
 // several waves share a cell).  The multi-step kernels add in the same order.
-template <int NW, bool WF, bool FLUX, bool EDGE, bool XWALL = false, bool GHOST = false>
+template <int NW, bool WF, bool FLUX, bool TAB, bool EDGE, bool XWALL = false, bool GHOST = false>
 __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const float* sW,
                                       const float* sTg, const float* sWTg, float* sRed,
                                       float* sBat, int x0, int y0, uint32_t boff,
@@ -188,22 +220,38 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
   float Eacc = 0.f, qx = 0.f, qy = 0.f;
   const int share = a.q / NW;
   constexpr int nrow = T::TY * 64;           // cells of the tile
+  // tiles other than EDGE tiles need no move components: with TAB they take
+  // the LDS offsets of E and W from the code table
+  constexpr bool kTab = TAB && !EDGE;
+  const WLBM_CONST uint32_t* sels = scalar_ptr(a.sels);
+  const char* sEc = reinterpret_cast<const char*>(sE + lc);
+  const char* sWc = reinterpret_cast<const char*>(sW + lc);
   auto relax_batch = [&](int i0, const float (&v)[D]) {
     float bsum = 0.f;
     uint32_t words[D / 4];
+    if constexpr (!kTab) {
 #pragma unroll
-    for (int k = 0; k < D / 4; ++k) words[k] = codes[(i0 >> 2) + k];
+      for (int k = 0; k < D / 4; ++k) words[k] = codes[(i0 >> 2) + k];
+    }
     const rsrc_t ro = make_rsrc(a.e_out + (long long)i0 * plane, batch_bytes);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
       const int i = i0 + d;
-      int dx, dy;
-      bool hop;
-      decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
+      int dx = 0, dy = 0;
+      bool hop = false;
+      int32_t eoff, woff;
+      if constexpr (kTab) {
+        const uint32_t c = sels[i] / kSelEntryBytes;
+        eoff = kStepCode.eoff[c];
+        woff = kStepCode.woff[c];
+      } else {
+        decode((words[d >> 2] >> (8 * (d & 3))) & 0xffu, dx, dy, hop);
+        eoff = -4 * (dy * T::LP + dx);
+        woff = hop ? eoff : 0;
+      }
       const float wi = wtab[i];
-      const int ls = lc - (dy * T::LP + dx);
       const float e = v[d];
-      const float Es = sE[ls];
+      const float Es = *reinterpret_cast<const float*>(sEc + eoff);
       float out;
       if constexpr (!WF) {
         // e + W (w_i E - e): the rounding error stays relative to the
@@ -211,7 +259,7 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
         out = fmaf(a.W, fmaf(wi, Es, -e), e);
       } else {
         // sE holds W E; sW holds W of each cell
-        const float Wh = sW[hop ? ls : lc];
+        const float Wh = *reinterpret_cast<const float*>(sWc + woff);
         out = e + fmaf(wi, Es, -(Wh * e));
       }
       if constexpr (XWALL) {
@@ -278,7 +326,7 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
   for (int i0 = part * share + D; i0 < i_end; i0 += D) {
     float vn[D];
     const bool more = i0 + D < i_end;
-    if (more) load_batch<D>(a, i0 + D, boff, vn);
+    if (more) load_batch<D, TAB>(a, i0 + D, boff, vn);
     relax_batch(i0, vc);
     if (more) {
 #pragma unroll
@@ -340,7 +388,7 @@ struct StepShared {
 };
 
 // One block's tile t of one time step of lattice a.
-template <int NW, bool WF, bool FLUX>
+template <int NW, bool WF, bool FLUX, bool TAB>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
                                           StepShared<NW, WF, FLUX>& sh) {
   using T = TileShape<NW>;
@@ -365,8 +413,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
   const uint32_t boff = uint32_t(cell(inside ? cx : 0, inside ? cy : 0, a.pitch) * 4);
   float v0[T::D], v1[T::D] = {};
   const int i_first = (wave % NW) * (a.q / NW);
-  load_batch<T::D>(a, i_first, boff, v0);
-  if (a.q / NW > T::D) load_batch<T::D>(a, i_first + T::D, boff, v1);
+  load_batch<T::D, TAB>(a, i_first, boff, v0);
+  if (a.q / NW > T::D) load_batch<T::D, TAB>(a, i_first + T::D, boff, v1);
 
   // Stage E (per-cell mode: W E) and W of the tile plus a one-cell halo.
   // Ghost rows/columns give the wrapped values of periodic edges and zero
@@ -432,21 +480,21 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
   const bool pghost = edge && a.x_edge == kPeriodic && a.y_edge == kPeriodic &&
                       x0 + T::TX <= a.nx && y0 + T::TY <= a.ny;
   if (xwall)
-    sweep<NW, WF, FLUX, false, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0, v1);
+    sweep<NW, WF, FLUX, TAB, false, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0, v1);
   else if (pghost)
-    sweep<NW, WF, FLUX, false, false, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0,
+    sweep<NW, WF, FLUX, TAB, false, false, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0,
                                             v1);
   else if (edge)
-    sweep<NW, WF, FLUX, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0, v1);
+    sweep<NW, WF, FLUX, TAB, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0, v1);
   else
-    sweep<NW, WF, FLUX, false>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0, v1);
+    sweep<NW, WF, FLUX, TAB, false>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0, v1);
 }
 
 template <int NW, bool WF, bool FLUX>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_step(
+__global__ __launch_bounds__(kBlock) void k_step(
     const StepArgs a) {
   __shared__ StepShared<NW, WF, FLUX> sh;
-  step_tile<NW, WF, FLUX>(a, xcd_tile(blockIdx.x, gridDim.x), sh);
+  step_tile<NW, WF, FLUX, true>(a, xcd_tile(blockIdx.x, gridDim.x), sh);
 }
 
 // One time step of several lattices in one launch.  The tiles of lattice j
@@ -456,7 +504,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
 // the lattices have several direction sets, each block takes the schedule
 // row of its lattice's ring.
 template <int NW, bool WF, bool FLUX, bool GROUPED>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_step_batch(
+__global__ __launch_bounds__(kBlock) void k_step_batch(
     const BatchStepArgs b) {
   __shared__ StepShared<NW, WF, FLUX> sh;
   const int g = xcd_tile(blockIdx.x, gridDim.x);
@@ -478,7 +526,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
   a.in_hi_hop = ins[2];
   a.in_hi_all = ins[3];
   a.q_first = b.q_first;
-  step_tile<NW, WF, FLUX>(a, g - first[j], sh);
+  step_tile<NW, WF, FLUX, false>(a, g - first[j], sh);
 }
 
 template <int NW, bool WF, bool FLUX>
