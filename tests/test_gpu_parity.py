@@ -291,8 +291,8 @@ def _window(s, half, n, walled):
 
 def test_full_size_4096_q256_walls_sampled_cells():
     """4096 x 4096, Q = 256, Kn = 10 (MFP 40960 cells), blackbody x walls at
-    T = 1 and 0, diffuse y walls, as the large benchmark runs it (single steps,
-    the library's default direction split), from a random initial field:
+    T = 1 and 0, diffuse y walls, as the large benchmark runs it (two steps
+    per launch, the library's default), from a random initial field:
     sampled cells after n steps, at the corners, along each wall and inside,
     equal the oracle run on the window that can influence them.  A window
     that reaches a wall ends at that wall; its far edge (a wall of the same
@@ -326,6 +326,32 @@ def test_full_size_4096_q256_walls_sampled_cells():
         cy = int(np.nonzero(ys == sy)[0][0])
         want = ora.temperature()[cy, cx]
         assert abs(T[sy, sx] - want) <= RTOL * 1.0, (sx, sy, T[sy, sx], want)
+
+
+def test_full_size_4096_q256_walls_2000_steps_keep_the_bits_of_single_steps():
+    """The same lattice for its full 2000 steps: two steps per launch (as
+    benchmarked) against one step per launch, bit for bit in every cell's
+    temperature and in the FP64 totals, after 500 and after 2000 steps (the
+    oracle windows of the test above cover 40 steps; over 2000 steps they
+    would span the lattice)."""
+    nx = ny = 4096
+    q, mfp = 256, 40960.0
+    walls = dict(x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0, t_x_hi=0.0)
+    T0 = torch.from_numpy(inputs.random_temperature(11, ny, nx))
+    a = _lattice(nx=nx, ny=ny, q=q, mfp=mfp, **walls)
+    b = _lattice(nx=nx, ny=ny, q=q, mfp=mfp, step_fusion=0, **walls)
+    assert a.steps_per_launch == 2 and b.steps_per_launch == 1
+    for lat in (a, b):
+        lat.set_temperature(T0)
+    for n in (500, 1500):
+        a.step(n)
+        b.step(n)
+        ta, tb = a.temperature(), b.temperature()
+        assert torch.isfinite(ta).all()
+        assert torch.equal(ta, tb), n
+        assert a.totals() == b.totals(), n
+    a.close()
+    b.close()
 
 
 @pytest.mark.parametrize("kn", [0.1, 10.0])
