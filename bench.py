@@ -270,7 +270,8 @@ def run_adjoint_kernel(nx=1024, ny=1024, q=64, steps=20):
 
 def run_films(steps=10000):
     """The 24-film sweep (Nx = 512, Q = 128, Ny 32..256, blackbody x, diffuse
-    y): fixed steps batched (one launch per step) against one-by-one."""
+    y): fixed steps batched (one launch for all films per two steps, block
+    height tuned for the batch) against one-by-one."""
     import torch
 
     from paper_1911_00180_amd.films import FilmSweep, film_set
@@ -283,6 +284,10 @@ def run_films(steps=10000):
         sw = FilmSweep(films)
         if mode == "batched_graphs":
             sw.batch.set_graphs(True)
+        if mode != "one_by_one" and sw.batch.steps_per_launch > 1:
+            # one block height for the whole batch, timed on a saved state
+            # before the timed steps (one by one, each film keeps its own)
+            out["batch_block_rows"] = sw.batch.tune_block_rows()
         go = sw.step_each if mode == "one_by_one" else sw.step_batched
         go(20)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -456,6 +456,26 @@ wlbm_status wlbm_batch_create(wlbm_lattice* const* lats, int32_t n, void* d_ws, 
  * wlbm_batch_set_graphs).  Results do not depend on either. */
 wlbm_status wlbm_batch_step(wlbm_batch* batch, int64_t nsteps);
 
+/* Time steps one launch of wlbm_batch_step advances every member (the fewest
+ * any member allows when all take the multi-step kernels with one q), or 1
+ * when the batch runs one step per launch; -1 for NULL. */
+int32_t wlbm_batch_get_steps_per_launch(const wlbm_batch* batch);
+
+/* Time every candidate block height of the batch's multi-step launches, one
+ * height for all members, on the members' current states: `launches`
+ * launches (1 .. 1000) after two warm-up launches, best of two passes; keep
+ * the fastest for every member (as wlbm_set_block_rows would) and return it
+ * in *rows (may be NULL).  The states and step counts are saved in d_states
+ * (256-byte aligned, at least the sum of the members' wlbm_state_bytes, each
+ * rounded up to 256 bytes; the members' slots in member order) and restored
+ * after every trial, so the members end where they started; flux-window sums
+ * are not touched.  Everything runs on the batch's stream, which the call
+ * waits for.  Without it each member keeps its own height, picked by the
+ * launch model as if it filled the GPU alone.  WLBM_EINVAL if the batch runs
+ * one step per launch. */
+wlbm_status wlbm_batch_tune_block_rows(wlbm_batch* batch, void* d_states, size_t bytes,
+                                       int32_t launches, int32_t* rows);
+
 /* on = 1: each whole schedule chunk (sched_chunk steps, when that is even)
  * with no flux-window step and no sources runs as one launch of a HIP graph
  * of its per-step launches, captured on first use for each of the two

@@ -172,6 +172,18 @@ wlbm_status check_members(wlbm_lattice* const* lats, int32_t n) {
   return WLBM_OK;
 }
 
+// Steps per launch of the batch's multi-step launches: the fewest any member
+// allows, when every member takes the multi-step kernels and all have one q
+// (the kernel's shape); 0 if the batch runs one step per launch.
+int batch_fused_k(const wlbm_batch* b) {
+  int k = 4;
+  for (const wlbm_lattice* l : b->lats) {
+    if (!lattice_fuses(l) || l->p.q != b->qmax) return 0;
+    k = std::min(k, fused_k_max(l));
+  }
+  return k >= 2 ? k : 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -295,15 +307,8 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
   // and all have one q (the kernel's shape): k_max steps per launch, the
   // fewest any lattice allows; the steps left over at chunk ends and in the
   // flux window run one per launch.
-  bool fuse = true;
-  int k_max = 4;
-  for (wlbm_lattice* l : b->lats) {
-    if (!lattice_fuses(l) || l->p.q != b->qmax)
-      fuse = false;
-    else
-      k_max = std::min(k_max, fused_k_max(l));
-  }
-  if (k_max < 2) fuse = false;
+  const int k_max = batch_fused_k(b);
+  const bool fuse = k_max >= 2;
   // argument tables: lattice j, buffer parity p (p = 1 after an odd number of
   // launches of this call); wall temperatures and fields as they are now.
   // The pinned staging copy of the previous call must have been consumed.
@@ -644,6 +649,118 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
     l->flux_valid = l->flux_window > 0 && nsteps >= l->flux_window;
     l->ghosts_full = last_fused;
   }
+  return WLBM_OK;
+}
+
+int32_t wlbm_batch_get_steps_per_launch(const wlbm_batch* b) {
+  if (!b) return -1;
+  const int k = batch_fused_k(b);
+  return k >= 2 ? k : 1;
+}
+
+wlbm_status wlbm_batch_tune_block_rows(wlbm_batch* b, void* d_states, size_t bytes,
+                                       int32_t launches, int32_t* rows_out) {
+  if (!b) return fail(WLBM_EINVAL, "batch is NULL");
+  wlbm_status st = check_members(b->lats.data(), int32_t(b->lats.size()));
+  if (st) return st;
+  if (launches < 1 || launches > 1000) return fail(WLBM_EINVAL, "launches must be in 1 .. 1000");
+  const int k = batch_fused_k(b);
+  if (k < 2)
+    return fail(WLBM_EINVAL, "this batch runs one step per launch (a member's edges, sources, q "
+                             "or size rule out the multi-step kernels, or the members' q differ)");
+  if (!d_states) return fail(WLBM_EINVAL, "state buffer is NULL");
+  // one slot per member, each 256-byte aligned
+  std::vector<size_t> off(b->lats.size()), len(b->lats.size());
+  size_t need = 0;
+  for (size_t j = 0; j < b->lats.size(); ++j) {
+    st = wlbm_state_bytes(b->lats[j], &len[j]);
+    if (st) return st;
+    off[j] = need;
+    need = align_up(need + len[j]);
+  }
+  if (bytes < need)
+    return fail(WLBM_EINVAL, "state buffer holds %zu bytes, the members' states need %zu", bytes,
+                need);
+  if (reinterpret_cast<uintptr_t>(d_states) % kAlign)
+    return fail(WLBM_EINVAL, "state buffer must be 256-byte aligned");
+  wlbm_lattice* l0 = b->lats[0];
+  const int pc = l0->per_cell ? 1 : 0;
+  const int64_t warm = 2, need_steps = (warm + launches) * int64_t(k);
+  if (l0->tas.n + need_steps > kMaxSteps) return fail(WLBM_EINVAL, "step count would overflow");
+  const int64_t step0 = l0->tas.n;
+  // whole launches of k steps: a launch never crosses a schedule chunk
+  const int per_call = std::max(1, std::min<int>(launches, b->chunk / k));
+  char* buf = static_cast<char*>(d_states);
+  // the members' state moves run on the batch's stream while tuning, and
+  // their flux-window sums are left alone
+  std::vector<hipStream_t> keep_stream(b->lats.size());
+  std::vector<int> keep_window(b->lats.size()), keep_rows(b->lats.size());
+  std::vector<uint8_t> keep_valid(b->lats.size());
+  for (size_t j = 0; j < b->lats.size(); ++j) {
+    wlbm_lattice* l = b->lats[j];
+    keep_stream[j] = l->stream;
+    keep_window[j] = l->flux_window;
+    keep_valid[j] = l->flux_valid ? 1 : 0;
+    keep_rows[j] = l->rows[pc][k];
+    l->stream = b->stream;
+    l->flux_window = 0;
+  }
+  auto restore_members = [&]() {
+    for (size_t j = 0; j < b->lats.size(); ++j) {
+      wlbm_lattice* l = b->lats[j];
+      l->stream = keep_stream[j];
+      l->flux_window = keep_window[j];
+      l->flux_valid = keep_valid[j] != 0;
+    }
+  };
+  for (size_t j = 0; j < b->lats.size() && !st; ++j)
+    st = wlbm_save_state(b->lats[j], buf + off[j], len[j]);
+  int ny_max = 1;
+  for (const wlbm_lattice* l : b->lats) ny_max = std::max(ny_max, l->g.ny);
+  int cand[32];
+  const int nc = fused_row_candidates(ny_max, k, cand, 32);
+  std::vector<float> best(size_t(nc), -1.f);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t he = hipSuccess;
+  if (!st && (he = hipEventCreate(&e0)) != hipSuccess)
+    st = fail(WLBM_EHIP, "hipEventCreate failed: %s", hipGetErrorString(he));
+  if (!st && (he = hipEventCreate(&e1)) != hipSuccess)
+    st = fail(WLBM_EHIP, "hipEventCreate failed: %s", hipGetErrorString(he));
+  // two passes over the candidates (one height for every member), each
+  // keeping its best time; the states are restored after every trial
+  for (int pass = 0; pass < 2 && !st; ++pass) {
+    for (int c = 0; c < nc && !st; ++c) {
+      for (wlbm_lattice* l : b->lats) l->rows[pc][k] = cand[c];
+      st = wlbm_batch_step(b, warm * k);
+      if (!st && (he = hipEventRecord(e0, b->stream)) != hipSuccess)
+        st = fail(WLBM_EHIP, "hipEventRecord failed: %s", hipGetErrorString(he));
+      for (int64_t left = launches; !st && left > 0; left -= per_call)
+        st = wlbm_batch_step(b, std::min<int64_t>(left, per_call) * k);
+      float ms = -1.f;
+      if (!st && (he = hipEventRecord(e1, b->stream)) != hipSuccess)
+        st = fail(WLBM_EHIP, "hipEventRecord failed: %s", hipGetErrorString(he));
+      if (!st && (he = hipEventSynchronize(e1)) != hipSuccess)
+        st = fail(WLBM_EHIP, "hipEventSynchronize failed: %s", hipGetErrorString(he));
+      if (!st && (he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess)
+        st = fail(WLBM_EHIP, "hipEventElapsedTime failed: %s", hipGetErrorString(he));
+      if (!st && (best[size_t(c)] < 0.f || ms < best[size_t(c)])) best[size_t(c)] = ms;
+      for (size_t j = 0; j < b->lats.size() && !st; ++j)
+        st = wlbm_load_state(b->lats[j], buf + off[j], len[j], step0);
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (st) {
+    for (size_t j = 0; j < b->lats.size(); ++j) b->lats[j]->rows[pc][k] = keep_rows[j];
+    restore_members();
+    return st;
+  }
+  int bi = 0;
+  for (int c = 1; c < nc; ++c)
+    if (best[size_t(c)] < best[size_t(bi)]) bi = c;
+  for (wlbm_lattice* l : b->lats) l->rows[pc][k] = cand[bi];
+  restore_members();
+  if (rows_out) *rows_out = cand[bi];
   return WLBM_OK;
 }
 

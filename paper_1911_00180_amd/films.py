@@ -16,8 +16,9 @@ The sweep: 24 films, Nx = 512, Q = 128 evenly spaced directions,
 Kn_j = 10^(-2 + 4j/23) per film thickness (MFP = Kn Ny cells), Ny_j drawn by
 default_rng(180) from the thicknesses in {32, 64, 128, 256} for which the
 MFP is at least one cell (W <= 1).  All films advance together through a
-Batch (one kernel launch per step for all 24); `step_each` advances them one
-after another for comparison.
+Batch (one kernel launch per two steps for all 24, with one block height for
+the batch timed by `tune`); `step_each` advances them one after another for
+comparison.
 
     python -m paper_1911_00180_amd.films [--steps N] [--steady]
 """
@@ -74,6 +75,14 @@ class FilmSweep:
     @property
     def updates_per_step(self) -> int:
         return sum(self.nx * ny * self.q for _, ny, _ in self.films)
+
+    def tune(self) -> int:
+        """Time the candidate block heights of the batch's multi-step
+        launches on the current states (restored) and keep the fastest for
+        every film; 0 if the batch runs one step per launch."""
+        if self.batch.steps_per_launch < 2:
+            return 0
+        return self.batch.tune_block_rows()
 
     def step_batched(self, n: int) -> None:
         self.batch.step(n)
@@ -168,6 +177,7 @@ def main():
     args = ap.parse_args()
     films = film_set()
     sweep = FilmSweep(films)
+    rows = sweep.tune()
     sweep.step_batched(10)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -182,13 +192,14 @@ def main():
     torch.cuda.synchronize()
     te = time.perf_counter() - t
     res = {"films": [{"kn": kn, "ny": ny, "mfp": mfp} for kn, ny, mfp in films],
-           "steps": args.steps, "batched_s": tb, "one_by_one_s": te,
+           "steps": args.steps, "batch_block_rows": rows, "batched_s": tb, "one_by_one_s": te,
            "batched_gups": sweep.updates_per_step * args.steps / tb / 1e9,
            "one_by_one_gups": sweep.updates_per_step * args.steps / te / 1e9}
     other.close()
     sweep.close()
     if args.steady:
         steady = FilmSweep(films, start="linear")
+        steady.tune()
         k, steps, rel, ok = steady.run_to_steady(
             check_every=args.check_every, rtol=args.rtol,
             log=lambda m: print(m, file=sys.stderr, flush=True))

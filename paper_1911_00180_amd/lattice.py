@@ -210,10 +210,12 @@ class Lattice:
 
 
 class Batch:
-    """Lattices advanced together, one kernel launch per step (same step
-    count, split, per-cell field use and flux window; q, direction sets and
-    grid speeds may differ); ``set_graphs(True)`` replays whole schedule
-    chunks as one HIP graph launch."""
+    """Lattices advanced together in one kernel launch (same step count,
+    split, per-cell field use and flux window; q, direction sets and grid
+    speeds may differ): several steps per launch when every lattice takes the
+    multi-step kernel with one q, else one step per launch, where
+    ``set_graphs(True)`` replays whole schedule chunks as one HIP graph
+    launch."""
 
     def __init__(self, lattices):
         self.lattices = list(lattices)
@@ -231,6 +233,23 @@ class Batch:
 
     def set_graphs(self, on: bool) -> None:
         W.wlbm_batch_set_graphs(self.handle, 1 if on else 0)
+
+    @property
+    def steps_per_launch(self) -> int:
+        """Time steps one launch advances every lattice (1: one per launch)."""
+        return W.wlbm_batch_get_steps_per_launch(self.handle)
+
+    def tune_block_rows(self, launches: int = 6) -> int:
+        """Time every candidate block height of the batch's multi-step
+        launches (one height for all lattices) on the current states
+        (restored afterwards) and keep the fastest for every lattice."""
+        for lat in self.lattices:
+            lat._sync_stream()
+        nbytes = sum((lat.state_bytes + 255) // 256 * 256 for lat in self.lattices)
+        buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        rows = W.wlbm_batch_tune_block_rows(self.handle, buf.data_ptr(), buf.numel(), launches)
+        del buf
+        return rows
 
     def close(self) -> None:
         if getattr(self, "handle", None):

@@ -47,6 +47,7 @@ EXPORTS = (
     "wlbm_set_sources", "wlbm_flux_distribution", "wlbm_set_speeds",
     "wlbm_accumulate_temperature", "wlbm_get_block_rows", "wlbm_set_block_rows",
     "wlbm_tune_block_rows", "wlbm_read_totals_noalloc", "wlbm_get_steps_per_launch",
+    "wlbm_batch_get_steps_per_launch", "wlbm_batch_tune_block_rows",
 )
 
 
@@ -135,6 +136,9 @@ def lib() -> ctypes.CDLL:
                                       POINTER(c_void_p)]),
         "wlbm_batch_step": (c_int, [c_void_p, c_int64]),
         "wlbm_batch_set_graphs": (c_int, [c_void_p, c_int32]),
+        "wlbm_batch_get_steps_per_launch": (c_int32, [c_void_p]),
+        "wlbm_batch_tune_block_rows": (c_int, [c_void_p, c_void_p, c_size_t, c_int32,
+                                               ctypes.POINTER(c_int32)]),
         "wlbm_batch_destroy": (c_int, [c_void_p]),
         "wlbm_read_flux_mean": (c_int, [c_void_p, c_int32, c_int32, c_int32, POINTER(c_double),
                                         POINTER(c_double)]),
@@ -402,6 +406,17 @@ def wlbm_batch_create(handles, d_ws, nbytes: int, stream) -> int:
 
 def wlbm_batch_step(b: int, nsteps: int) -> None:
     _check(lib().wlbm_batch_step(c_void_p(b), nsteps))
+
+
+def wlbm_batch_get_steps_per_launch(b: int) -> int:
+    return lib().wlbm_batch_get_steps_per_launch(c_void_p(b))
+
+
+def wlbm_batch_tune_block_rows(b: int, d_states, nbytes: int, launches: int) -> int:
+    rows = c_int32(0)
+    _check(lib().wlbm_batch_tune_block_rows(c_void_p(b), _ptr(d_states), nbytes, launches,
+                                            byref(rows)))
+    return rows.value
 
 
 def wlbm_batch_set_graphs(b: int, on: int) -> None:

@@ -273,3 +273,39 @@ def test_batched_multi_step_launches_keep_the_bits_of_single_steps(q, per_cell, 
     batch.close()
     for lat in a + b:
         lat.close()
+
+
+def test_batch_block_height_tuner_restores_states_and_keeps_the_bits():
+    """wlbm_batch_tune_block_rows: one height for every member, chosen among
+    the candidates; the members end at their states and step counts, and the
+    tuned batch keeps the bits of an untuned twin."""
+    from paper_1911_00180_amd.lattice import Batch
+    cfgs = [dict(nx=150, ny=ny, mfp=mfp, x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0,
+                 t_x_hi=0.1) for ny, mfp in ((8, 2.0), (23, 9.0), (40, 30.0))]
+    a = [_make(64, c, 60 + k) for k, c in enumerate(cfgs)]
+    b = [_make(64, c, 60 + k) for k, c in enumerate(cfgs)]
+    for x in a + b:
+        x.set_flux_window(5)
+    ba, bb = Batch(a), Batch(b)
+    k = ba.steps_per_launch
+    assert k >= 2
+    ba.step(24)
+    bb.step(24)
+    before = [x.populations().clone() for x in a]
+    rows = ba.tune_block_rows(launches=2)
+    assert rows >= 1 and (rows + 2 * (k - 1)) % 3 == 0
+    for x, p0 in zip(a, before):
+        assert x.step_count == 24
+        assert x.block_rows(k) == rows
+        assert torch.equal(x.populations(), p0)
+    for n in (40, 7):
+        ba.step(n)
+        bb.step(n)
+        for x, y in zip(a, b):
+            assert torch.equal(x.populations(), y.populations()), n
+            for u, v in zip(x.heat_flux(averaged=True), y.heat_flux(averaged=True)):
+                assert torch.equal(u, v)
+    ba.close()
+    bb.close()
+    for x in a + b:
+        x.close()
