@@ -391,7 +391,9 @@ int32_t wlbm_get_steps_per_launch(const wlbm_lattice* lat);
  * the height fixed by wlbm_set_block_rows or chosen by wlbm_tune_block_rows,
  * else the library's launch model's pick (the height whose blocks fill the
  * device in the fewest row iterations, from the kernel's occupancy and the
- * number of compute units).  wlbm_step never times anything itself.  0 if
+ * number of compute units; on a lattice with walls among blocks of at most
+ * 18 row iterations, R + 2 (k - 1) <= 18, which measured faster there).
+ * wlbm_step never times anything itself.  0 if
  * the lattice runs one step per launch (see step_fusion), -1 for NULL or k
  * outside 2 .. 4.  Results do not depend on the height. */
 int32_t wlbm_get_block_rows(const wlbm_lattice* lat, int32_t k);

@@ -18,13 +18,24 @@
 
 namespace wlbm {
 
+// Row iterations of a block (R + 2 (k - 1)) that the launch model allows on a
+// lattice with walls.
+constexpr int kMaxWalledIterations = 18;
+
 // Launch model of the k-step kernel: blocks run in rounds of (resident
 // blocks per CU) x (CUs); a block of R output rows iterates over R + 2 (k-1)
 // rows (the halo of the k levels).  The height with the fewest row
 // iterations over all rounds, (rounds) x (R + 2 (k - 1)), is picked; among
 // equals the taller (fewer blocks).  At 1024 x 1024, Q = 64, four steps per
 // launch this gives the 45-row blocks (22 x 23 = 506 blocks, one round of
-// 512) that timing also picks.
+// 512) that timing also picks.  On a lattice with walls the blocks that touch
+// one run the slower walled code, and short blocks measured faster: only
+// heights of at most 18 row iterations are considered there (four steps per
+// launch, 1024 x 1024 x 64 with blackbody x edges: 12 rows 0.060 ms per step
+// against 0.075 at the 45 rows the unrestricted model picks; 2048 x 2048 x
+// 128 with a per-cell field and blackbody x edges, two steps: 16 rows 0.571
+// against 0.618 at 61; 4096 x 4096 x 256, blackbody x and diffuse y: 16 rows
+// 4.26 against 4.29 at 58).
 int block_rows_for(const wlbm_lattice* l, int k) {
   const int pc = l->per_cell ? 1 : 0;
   if (l->rows[pc][k]) return l->rows[pc][k];
@@ -44,6 +55,7 @@ int block_rows_for(const wlbm_lattice* l, int k) {
   long long best_cost = -1;
   for (int c = 0; c < nc; ++c) {
     const int R = cand[c];
+    if (walls && c > 0 && R + 2 * (k - 1) > kMaxWalledIterations) break;
     const long long nb = sx * ((l->g.ny + R - 1) / R);
     const long long cost = ((nb + cap - 1) / cap) * (R + 2 * (k - 1));
     if (best_cost < 0 || cost <= best_cost) {
