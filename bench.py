@@ -93,11 +93,11 @@ def run_gpu(nx, ny, q, mfp, steps, warmup, edges, split=0, seed=1911, fusion=1, 
     lat.set_temperature(torch.from_numpy(T0))
     for k, rows in (block_rows or {}).items():
         lat.set_block_rows(k, rows)
-    if (tune and fusion in (2, 3, 4) and lat.block_rows(fusion) > 0
-            and fusion not in (block_rows or {})):
-        lat.tune_block_rows(fusion)
-    if fusion in (2, 3, 4) and lat.block_rows(fusion) <= 0:
-        raise SystemExit(f"bench.py: no block height for {fusion} steps per launch")
+    spl = lat.steps_per_launch
+    if tune and spl > 1 and lat.block_rows(spl) > 0 and spl not in (block_rows or {}):
+        lat.tune_block_rows(spl)
+    if spl > 1 and lat.block_rows(spl) <= 0:
+        raise SystemExit(f"bench.py: no block height for {spl} steps per launch")
     lat.step(warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
