@@ -185,7 +185,9 @@ wlbm_status wlbm_set_wall_temperatures(wlbm_lattice* lat, double t_x_lo, double 
 
 /* Number of trailing steps of each wlbm_step call over which the heat flux is
  * accumulated for wlbm_read_heat_flux(..., averaged = 1); 0 disables it
- * (default).  Sec. 3.4 averages the flux over ten steps. */
+ * (default).  Sec. 3.4 averages the flux over ten steps.  The per-cell sums
+ * are kept in float64 (a float32 sum over a million steps can be off by
+ * 1e-3 of its value); the steps of a window run one step per launch. */
 wlbm_status wlbm_set_flux_window(wlbm_lattice* lat, int32_t window);
 
 /* Advance nsteps >= 0 time steps of the worm-LBM: for every cell and

@@ -63,8 +63,9 @@ Carve carve(const wlbm_params& p) {
   c.E[1] = take(plane);
   c.Wf = take(plane);
   c.Wraw = take(cells);
-  c.qsx = take(cells);
-  c.qsy = take(cells);
+  // flux-window sums in float64: windows run to millions of steps
+  c.qsx = take(2 * cells);
+  c.qsy = take(2 * cells);
   c.partials = take(size_t(kReduceBlocks) * 3 * sizeof(double));
   c.totals = take(4 * sizeof(double));
   c.flag = take(sizeof(int));
@@ -594,8 +595,8 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
   std::vector<float> insums;
   StepArgs a{};
   a.Wf = l->ptr(l->c.Wf);
-  a.qsx = l->ptr(l->c.qsx);
-  a.qsy = l->ptr(l->c.qsy);
+  a.qsx = l->dptr(l->c.qsx);
+  a.qsy = l->dptr(l->c.qsy);
   a.wtab = l->ptr(l->c.wtab);
   a.sxtab = l->ptr(l->c.sxtab);
   a.sytab = l->ptr(l->c.sytab);
@@ -831,8 +832,8 @@ wlbm_status wlbm_read_heat_flux(wlbm_lattice* l, float* d_qx, float* d_qy, int32
   if (averaged) {
     if (!l->flux_valid)
       return fail(WLBM_ESTATE, "no complete flux window: set one and step at least that far");
-    HIP_TRY(launch_scale_pair(l->g.nx * l->g.ny, l->ptr(l->c.qsx), l->ptr(l->c.qsy),
-                              1.0f / float(l->flux_window), d_qx, d_qy, l->stream));
+    HIP_TRY(launch_scale_pair(l->g.nx * l->g.ny, l->dptr(l->c.qsx), l->dptr(l->c.qsy),
+                              1.0 / double(l->flux_window), d_qx, d_qy, l->stream));
   } else {
     HIP_TRY(launch_read_flux(l->g, l->ptr(l->c.e[l->cur]), l->ptr(l->c.sxtab),
                              l->ptr(l->c.sytab), d_qx, d_qy, l->stream));
@@ -877,7 +878,7 @@ wlbm_status wlbm_read_flux_mean(wlbm_lattice* l, int32_t x0, int32_t x1, int32_t
     return fail(WLBM_ESTATE, "no complete flux window: set one and step at least that far");
   double* dev = reinterpret_cast<double*>(l->ws + l->c.totals);
   HIP_TRY(launch_flux_sum(l->g, l->ptr(l->c.e[l->cur]), l->ptr(l->c.sxtab), l->ptr(l->c.sytab),
-                          l->ptr(l->c.qsx), l->ptr(l->c.qsy), averaged ? 1 : 0, x0, x1,
+                          l->dptr(l->c.qsx), l->dptr(l->c.qsy), averaged ? 1 : 0, x0, x1,
                           reinterpret_cast<double*>(l->ws + l->c.partials), kReduceBlocks, dev,
                           l->stream));
   double h[3];

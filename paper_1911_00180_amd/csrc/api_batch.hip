@@ -348,8 +348,8 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
       a.E_in = l->ptr(l->c.E[in]);
       a.E_out = l->ptr(l->c.E[1 - in]);
       a.Wf = l->ptr(l->c.Wf);
-      a.qsx = l->ptr(l->c.qsx);
-      a.qsy = l->ptr(l->c.qsy);
+      a.qsx = l->dptr(l->c.qsx);
+      a.qsy = l->dptr(l->c.qsy);
       a.wtab = l->ptr(l->c.wtab);
       a.sxtab = l->ptr(l->c.sxtab);
       a.sytab = l->ptr(l->c.sytab);

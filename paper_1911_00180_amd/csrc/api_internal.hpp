@@ -102,6 +102,7 @@ struct wlbm_lattice {
   int64_t am = -1;          // adjoint step index; -1 when no reverse pass is active
 
   float* ptr(size_t off) { return reinterpret_cast<float*>(ws + off); }
+  double* dptr(size_t off) { return reinterpret_cast<double*>(ws + off); }
   float* aptr(size_t off) { return reinterpret_cast<float*>(aws + off); }
 };
 

@@ -40,8 +40,8 @@ struct StepArgs {
   const float* E_in;
   float* E_out;
   const float* Wf;        // padded per-cell corrected weight (per-cell mode)
-  float* qsx;             // heat-flux window sums, [ny][nx] (flux mode)
-  float* qsy;
+  double* qsx;            // heat-flux window sums, [ny][nx] (flux mode), float64
+  double* qsy;
   const uint32_t* codes;  // schedule row of this step
   // k_step only: per direction, the byte offset of its pulled population and
   // of its entry in the multi-step kernels' selection table (move code times
@@ -222,7 +222,7 @@ hipError_t launch_axpy_field(const Geometry& g, float a, const float* f, float* 
                              hipStream_t s);
 hipError_t launch_read_flux(const Geometry& g, const float* e, const float* sxtab,
                             const float* sytab, float* qx, float* qy, hipStream_t s);
-hipError_t launch_scale_pair(int n, const float* ax, const float* ay, float scale, float* bx,
+hipError_t launch_scale_pair(int n, const double* ax, const double* ay, double scale, float* bx,
                              float* by, hipStream_t s);
 // Totals in float64: out[0] = sum E, out[1] = sum q_x, out[2] = sum q_y.
 hipError_t launch_totals(const Geometry& g, const float* e, const float* E, const float* sxtab,
@@ -231,7 +231,7 @@ hipError_t launch_totals(const Geometry& g, const float* e, const float* E, cons
 // Float64 sums of q_x, q_y over columns x0 <= x < x1, all rows: out[0], out[1]
 // (out[2] = 0).  window != 0: from the flux-window sums qsx/qsy; else from e.
 hipError_t launch_flux_sum(const Geometry& g, const float* e, const float* sxtab,
-                           const float* sytab, const float* qsx, const float* qsy, int window,
+                           const float* sytab, const double* qsx, const double* qsy, int window,
                            int x0, int x1, double* partials, int max_blocks, double* out,
                            hipStream_t s);
 // Per-cell corrected weight from an MFP field: check pass (sets *flag on a

@@ -365,11 +365,11 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
   if constexpr (FLUX) {
     const long long o = (long long)y * a.nx + x;
     if (a.q_first) {
-      a.qsx[o] = qx;
-      a.qsy[o] = qy;
+      a.qsx[o] = double(qx);
+      a.qsy[o] = double(qy);
     } else {
-      a.qsx[o] += qx;
-      a.qsy[o] += qy;
+      a.qsx[o] += double(qx);
+      a.qsy[o] += double(qy);
     }
   }
 }
@@ -645,12 +645,12 @@ __global__ __launch_bounds__(kBlock) void k_read_flux(const Geometry g, const fl
   qy[c] = ay;
 }
 
-__global__ __launch_bounds__(kBlock) void k_scale_pair(int n, const float* ax, const float* ay,
-                                                      float s, float* bx, float* by) {
+__global__ __launch_bounds__(kBlock) void k_scale_pair(int n, const double* ax, const double* ay,
+                                                      double s, float* bx, float* by) {
   const int c = blockIdx.x * kBlock + threadIdx.x;
   if (c >= n) return;
-  bx[c] = ax[c] * s;
-  by[c] = ay[c] * s;
+  bx[c] = float(ax[c] * s);
+  by[c] = float(ay[c] * s);
 }
 
 __device__ __forceinline__ double corrected(double mfp, double lam, double f, int corr) {
@@ -789,7 +789,7 @@ hipError_t launch_read_flux(const Geometry& g, const float* e, const float* sxta
   return hipGetLastError();
 }
 
-hipError_t launch_scale_pair(int n, const float* ax, const float* ay, float scale, float* bx,
+hipError_t launch_scale_pair(int n, const double* ax, const double* ay, double scale, float* bx,
                              float* by, hipStream_t s) {
   hipLaunchKernelGGL(k_scale_pair, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, n, ax, ay,
                      scale, bx, by);

@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kBlock) void k_totals_final(const double* partials,
 __global__ __launch_bounds__(kBlock) void k_flux_sum_partial(const Geometry g, const float* e,
                                                             const float* sxtab,
                                                             const float* sytab,
-                                                            const float* qsx, const float* qsy,
+                                                            const double* qsx, const double* qsy,
                                                             int window, int x0, int x1,
                                                             double* partials) {
   const int w = x1 - x0;
@@ -126,8 +126,8 @@ __global__ __launch_bounds__(kBlock) void k_flux_sum_partial(const Geometry g, c
     const int y = int(c / w);
     if (window) {
       const long long o = (long long)y * g.nx + x;
-      sx += double(qsx[o]);
-      sy += double(qsy[o]);
+      sx += qsx[o];
+      sy += qsy[o];
     } else {
       const long long o = cell(x, y, g.pitch);
       double ax = 0.0, ay = 0.0;
@@ -159,7 +159,7 @@ hipError_t launch_totals(const Geometry& g, const float* e, const float* E, cons
 }
 
 hipError_t launch_flux_sum(const Geometry& g, const float* e, const float* sxtab,
-                           const float* sytab, const float* qsx, const float* qsy, int window,
+                           const float* sytab, const double* qsx, const double* qsy, int window,
                            int x0, int x1, double* partials, int max_blocks, double* out,
                            hipStream_t s) {
   const long long need = ((long long)(x1 - x0) * g.ny + kBlock - 1) / kBlock;

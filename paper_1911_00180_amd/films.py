@@ -20,7 +20,7 @@ Batch (one kernel launch per two steps for all 24, with one block height for
 the batch timed by `tune`); `step_each` advances them one after another for
 comparison.
 
-    python -m paper_1911_00180_amd.films [--steps N] [--steady]
+    python -m paper_1911_00180_amd.films [--steps N] [--steady] [--only J,...]
 """
 from __future__ import annotations
 
@@ -171,11 +171,17 @@ def main():
                     help="steady when kappa changes by less than this between checks")
     ap.add_argument("--check-every", type=int, default=10000,
                     help="steps per check (the flux is averaged over each interval)")
+    ap.add_argument("--max-steps", type=int, default=1_000_000,
+                    help="steps of the first steady-state pass at most")
     ap.add_argument("--second-steps", type=int, default=2_000_000,
                     help="steps of the second pass (ten times longer windows) for the films "
                          "not steady after the first; 0: none")
+    ap.add_argument("--only", default="",
+                    help="comma-separated indices of the films to run (default: all 24)")
     args = ap.parse_args()
     films = film_set()
+    if args.only:
+        films = [films[int(j)] for j in args.only.split(",")]
     sweep = FilmSweep(films)
     rows = sweep.tune()
     sweep.step_batched(10)
@@ -201,13 +207,14 @@ def main():
         steady = FilmSweep(films, start="linear")
         steady.tune()
         k, steps, rel, ok = steady.run_to_steady(
-            check_every=args.check_every, rtol=args.rtol,
+            check_every=args.check_every, rtol=args.rtol, max_steps=args.max_steps,
             log=lambda m: print(m, file=sys.stderr, flush=True))
         res["kappa_ratio"] = k
         res["steady_steps"] = steps
         res["last_relative_change"] = rel
         res["converged"] = ok
-        res["criterion"] = {"rtol": args.rtol, "check_every": args.check_every, "repeats": 2}
+        res["criterion"] = {"rtol": args.rtol, "check_every": args.check_every, "repeats": 2,
+                            "max_steps": args.max_steps}
         # films whose flux still scatters by more than rtol between windows
         # (the nearly ballistic ones) continue with ten times longer windows
         rest = [j for j, c in enumerate(ok) if not c]
