@@ -149,7 +149,9 @@ class FilmSweep:
                 batch = Batch([self.lattices[j] for j in still])
             active = still
             if log is not None:
-                log(f"step {total}: {len(active)} films not yet steady")
+                changes = [rel[j] for j in active if rel[j] is not None]
+                worst = f", largest change {max(changes):.3g}" if changes else ""
+                log(f"step {total}: {len(active)} films not yet steady{worst}")
         if batch is not self.batch:
             batch.close()
         for j in active:
