@@ -178,10 +178,12 @@ __device__ __forceinline__ void load_batch(const StepArgs& a, int i0, uint32_t b
 // E' = sum_i out_i is added in a fixed order that does not depend on the
 // direction split: each batch of D = 8 directions is summed in direction
 // order, then the batch sums are added in batch order (sBat holds them when
-// several waves share a cell).  The multi-step kernels add in the same order.
+// several waves share a cell).  The heat flux of flux-window steps is summed
+// the same way (each batch's fma chain over its directions, then the batches
+// in order).  The multi-step kernels add in the same order.
 template <int NW, bool WF, bool FLUX, bool TAB, bool EDGE, bool XWALL = false, bool GHOST = false>
 __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const float* sW,
-                                      const float* sTg, const float* sWTg, float* sRed,
+                                      const float* sTg, const float* sWTg,
                                       float* sBat, int x0, int y0, uint32_t boff,
                                       const float (&v0)[TileShape<NW>::D],
                                       const float (&v1)[TileShape<NW>::D]) {
@@ -226,8 +228,9 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
   const WLBM_CONST uint32_t* sels = scalar_ptr(a.sels);
   const char* sEc = reinterpret_cast<const char*>(sE + lc);
   const char* sWc = reinterpret_cast<const char*>(sW + lc);
+  const int nbat = a.q / D;
   auto relax_batch = [&](int i0, const float (&v)[D]) {
-    float bsum = 0.f;
+    float bsum = 0.f, bqx = 0.f, bqy = 0.f;
     uint32_t words[D / 4];
     if constexpr (!kTab) {
 #pragma unroll
@@ -307,14 +310,23 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
       }
       bsum += out;
       if constexpr (FLUX) {
-        qx = fmaf(out, sxtab[i], qx);
-        qy = fmaf(out, sytab[i], qy);
+        bqx = fmaf(out, sxtab[i], bqx);
+        bqy = fmaf(out, sytab[i], bqy);
       }
     }
-    if constexpr (NW == 1)
+    if constexpr (NW == 1) {
       Eacc += bsum;
-    else
+      if constexpr (FLUX) {
+        qx += bqx;
+        qy += bqy;
+      }
+    } else {
       sBat[(i0 / D) * nrow + row * 64 + lane] = bsum;
+      if constexpr (FLUX) {
+        sBat[(nbat + i0 / D) * nrow + row * 64 + lane] = bqx;
+        sBat[(2 * nbat + i0 / D) * nrow + row * 64 + lane] = bqy;
+      }
+    }
   };
   // the first two batches were loaded before the E tile was staged; each
   // later batch is loaded while the one before it is relaxed
@@ -335,25 +347,16 @@ __device__ __forceinline__ void sweep(const StepArgs& a, const float* sE, const 
   }
 
   if constexpr (NW > 1) {
-    // batch sums of E' in batch order; flux partials of the NW waves in
-    // wave order
+    // batch sums of E' and of the flux in batch order
     constexpr int n = nrow;
-    const int slot = (part * T::TY + row) * 64 + lane;
-    if constexpr (FLUX) {
-      sRed[slot] = qx;
-      sRed[NW * n + slot] = qy;
-    }
     lds_barrier();
     if (part != 0) return;
     const int base = row * 64 + lane;
-    for (int k = 0; k < a.q / D; ++k) Eacc += sBat[k * n + base];
+    for (int k = 0; k < nbat; ++k) Eacc += sBat[k * n + base];
     if constexpr (FLUX) {
-      qx = sRed[base];
-      qy = sRed[NW * n + base];
-#pragma unroll
-      for (int k = 1; k < NW; ++k) {
-        qx += sRed[k * n + base];
-        qy += sRed[NW * n + k * n + base];
+      for (int k = 0; k < nbat; ++k) {
+        qx += sBat[(nbat + k) * n + base];
+        qy += sBat[(2 * nbat + k) * n + base];
       }
     }
   }
@@ -384,7 +387,6 @@ struct StepShared {
   float sTg[2 * T::LP];
   float sWTg[2 * T::LP];
   float sInflow[2 * T::LP * kNodeParts];   // partial inflows of diffuse-wall nodes
-  float sRed[NW > 1 && FLUX ? 2 * kBlock : 1];
 };
 
 // One block's tile t of one time step of lattice a.
@@ -396,8 +398,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
   float* sW = sh.sW;
   float* sTg = sh.sTg;
   float* sWTg = sh.sWTg;
-  float* sRed = sh.sRed;
-  extern __shared__ float sBat[];   // [q / 8][tile cells] when NW > 1
+  // when NW > 1: [q / 8][tile cells] batch sums of E', then (FLUX) of q_x, q_y
+  extern __shared__ float sBat[];
   const int tx = t % a.tiles_x;
   const int ty = t / a.tiles_x;
   const int x0 = tx * T::TX;
@@ -480,14 +482,14 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int t,
   const bool pghost = edge && a.x_edge == kPeriodic && a.y_edge == kPeriodic &&
                       x0 + T::TX <= a.nx && y0 + T::TY <= a.ny;
   if (xwall)
-    sweep<NW, WF, FLUX, TAB, false, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0, v1);
+    sweep<NW, WF, FLUX, TAB, false, true>(a, sE, sW, sTg, sWTg, sBat, x0, y0, boff, v0, v1);
   else if (pghost)
-    sweep<NW, WF, FLUX, TAB, false, false, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0,
+    sweep<NW, WF, FLUX, TAB, false, false, true>(a, sE, sW, sTg, sWTg, sBat, x0, y0, boff, v0,
                                             v1);
   else if (edge)
-    sweep<NW, WF, FLUX, TAB, true>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0, v1);
+    sweep<NW, WF, FLUX, TAB, true>(a, sE, sW, sTg, sWTg, sBat, x0, y0, boff, v0, v1);
   else
-    sweep<NW, WF, FLUX, TAB, false>(a, sE, sW, sTg, sWTg, sRed, sBat, x0, y0, boff, v0, v1);
+    sweep<NW, WF, FLUX, TAB, false>(a, sE, sW, sTg, sWTg, sBat, x0, y0, boff, v0, v1);
 }
 
 template <int NW, bool WF, bool FLUX>
@@ -532,7 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_step_batch(
 template <int NW, bool WF, bool FLUX>
 hipError_t launch_tmpl(const StepArgs& a, hipStream_t s) {
   hipLaunchKernelGGL((k_step<NW, WF, FLUX>), dim3(a.ntiles), dim3(kBlock),
-                     step_batch_lds_bytes(a.q, NW), s, a);
+                     step_batch_lds_bytes(a.q, NW) * (FLUX ? 3 : 1), s, a);
   return hipGetLastError();
 }
 
@@ -705,7 +707,7 @@ int tiles_y_for(int ny, int split) {
 template <int NW, bool WF, bool FLUX, bool GROUPED>
 hipError_t launch_batch_tmpl(const BatchStepArgs& b, hipStream_t s) {
   hipLaunchKernelGGL((k_step_batch<NW, WF, FLUX, GROUPED>), dim3(b.nblocks), dim3(kBlock),
-                     step_batch_lds_bytes(b.q, NW), s, b);
+                     step_batch_lds_bytes(b.q, NW) * (FLUX ? 3 : 1), s, b);
   return hipGetLastError();
 }
 
