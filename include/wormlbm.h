@@ -103,10 +103,10 @@ typedef struct wlbm_params {
                              /* diffusely (Eq. adiabatic-diffuse)                */
   int32_t step_fusion;       /* time steps per kernel launch where possible      */
                              /* (any edges but partly specular walls, no         */
-                             /* sources, q a multiple of 8 up to 64 or of 16 up  */
-                             /* to 128, or 192 or 256, nx >= 8, ny >= 2, outside */
-                             /* flux windows and tapes; q above 128, and         */
-                             /* periodic x with diffuse y: at most two): 1 =     */
+                             /* sources, q a multiple of 8 up to 128, or 192 or  */
+                             /* 256, nx >= 8, ny >= 2, outside tapes; q above    */
+                             /* 128, and periodic x with diffuse y: at most      */
+                             /* two): 1 =                                        */
                              /* automatic (up to four), 2 .. 4 = at most that    */
                              /* many, 0 = one step per launch.  Results are      */
                              /* identical to single steps in every case.         */
@@ -187,7 +187,9 @@ wlbm_status wlbm_set_wall_temperatures(wlbm_lattice* lat, double t_x_lo, double 
  * accumulated for wlbm_read_heat_flux(..., averaged = 1); 0 disables it
  * (default).  Sec. 3.4 averages the flux over ten steps.  The per-cell sums
  * are kept in float64 (a float32 sum over a million steps can be off by
- * 1e-3 of its value); the steps of a window run one step per launch. */
+ * 1e-3 of its value).  Steps of a window run several per launch as other
+ * steps do (the launch adds the flux of each of its window steps, with the
+ * bits of single steps). */
 wlbm_status wlbm_set_flux_window(wlbm_lattice* lat, int32_t window);
 
 /* Advance nsteps >= 0 time steps of the worm-LBM: for every cell and
@@ -381,8 +383,8 @@ int32_t wlbm_get_dir_split(const wlbm_lattice* lat);
 
 /* Time steps that wlbm_step advances per kernel launch on this lattice as
  * it stands (edges, q, per-cell field, sources, step_fusion): 1 for the
- * single-step kernel, else 2 .. 4 (calls and schedule chunks that do not
- * divide evenly, and flux-window steps, still run single steps).  The
+ * single-step kernel, else 2 .. 4 (steps left over where calls and schedule
+ * chunks do not divide evenly still run single steps).  The
  * automatic choice (step_fusion = 1) is four, and two for lattices with
  * walls and q above 64 or a per-cell field, and for q above 128 (measured
  * fastest on MI355X).  -1 for NULL. */

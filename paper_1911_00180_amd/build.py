@@ -17,10 +17,14 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libwormlbm.so")
-SOURCES = ["tables.cpp", "kernels.hip", "fused.hip", "fused_walls2.hip",
-           "fused_walls3.hip", "fused_walls4.hip", "fused_batch2.hip", "fused_batch3.hip",
-           "fused_batch4.hip", "adjoint.hip", "reduce.hip", "api.hip",
-           "api_states.hip", "api_batch.hip", "api_tune.hip", "api_noalloc.hip"]
+# Longest compiles first (the multi-step kernel instantiations), so that the
+# parallel build ends soonest.
+SOURCES = ["fused_batch_flux4.hip", "fused_batch_flux3.hip", "fused_batch_flux2.hip",
+           "fused_flux4.hip", "fused_flux3.hip", "fused_flux2.hip", "fused_batch4.hip",
+           "fused_batch3.hip", "fused_batch2.hip", "fused_walls4.hip", "fused_walls3.hip",
+           "fused_walls2.hip", "fused.hip", "kernels.hip", "adjoint.hip", "reduce.hip",
+           "api.hip", "api_states.hip", "api_batch.hip", "api_tune.hip", "api_noalloc.hip",
+           "tables.cpp"]
 # Stand-alone HBM stream kernel used by the benchmark to measure the
 # practical read+write ceiling of the device (not part of the library).
 PROBE_LIB = os.path.join(PKG, "libwlbm_probe.so")

@@ -689,9 +689,9 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
     for (int j = 0; j < cnt; ++j) {
       const int64_t k = done + j;
       const bool flux = k >= flux_from;
-      // steps k .. k+K-1 in one launch (all in this chunk, none in a flux
-      // window)
-      const int K = int(std::min<int64_t>({int64_t(k_max), int64_t(cnt - j), flux_from - k}));
+      // steps k .. k+K-1 in one launch (all in this chunk); those in the
+      // flux window add their heat flux to the window's sums in the launch
+      const int K = int(std::min<int64_t>(k_max, cnt - j));
       if (fuse && K >= 2) {
         FusedArgs a2{};
         a2.e_in = l->ptr(l->c.e[l->cur]);
@@ -719,6 +719,13 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
         a2.t_y_hi = a.t_y_hi;
         a2.codes = reinterpret_cast<const uint32_t*>(dev_rows + size_t(j) * q);
         a2.ins = dev_ins + size_t(4) * j;
+        for (int m = 0; m < K; ++m)
+          if (k + m >= flux_from) a2.flux_levels |= 1u << m;
+        a2.flux_first = (flux_from >= k && flux_from < k + K) ? int(flux_from - k) + 1 : 0;
+        a2.qsx = a.qsx;
+        a2.qsy = a.qsy;
+        a2.sxtab = a.sxtab;
+        a2.sytab = a.sytab;
         e = hipSuccess;
         // the multi-step kernels read kGhost ghost columns of periodic x
         // edges, which other producers do not write: refresh the frame once
@@ -735,7 +742,8 @@ wlbm_status run_steps(wlbm_lattice* l, int64_t nsteps, char* tape, size_t slot_b
           e = fill_ghosts(l->ptr(l->c.Wf), a.plane, 1, a.nx, a.ny, a.pitch, px, py, l->stream);
           if (e == hipSuccess) l->wf_ghosts_full = true;
         }
-        if (e == hipSuccess) e = launch_fused(a2, K, l->per_cell, l->stream);
+        if (e == hipSuccess)
+          e = launch_fused(a2, K, l->per_cell, a2.flux_levels != 0, l->stream);
         if (e != hipSuccess) {
           l->broken = true;
           return fail(WLBM_EHIP, "fused step kernel launch failed: %s", hipGetErrorString(e));

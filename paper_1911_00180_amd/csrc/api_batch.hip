@@ -305,8 +305,8 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
   const int ngroups = int(b->groups.size());
   // Several steps per launch when every lattice takes the multi-step kernels
   // and all have one q (the kernel's shape): k_max steps per launch, the
-  // fewest any lattice allows; the steps left over at chunk ends and in the
-  // flux window run one per launch.
+  // fewest any lattice allows; the steps left over at chunk ends run one per
+  // launch.
   const int k_max = batch_fused_k(b);
   const bool fuse = k_max >= 2;
   // argument tables: lattice j, buffer parity p (p = 1 after an odd number of
@@ -392,6 +392,10 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
       f.t_x_hi = a.t_x_hi;
       f.t_y_lo = a.t_y_lo;
       f.t_y_hi = a.t_y_hi;
+      f.qsx = a.qsx;
+      f.qsy = a.qsy;
+      f.sxtab = a.sxtab;
+      f.sytab = a.sytab;
     }
     first[size_t(j) + 1] = first[size_t(j)] + table[size_t(2) * j].ntiles;
     ffirst[size_t(j) + 1] =
@@ -604,12 +608,20 @@ wlbm_status wlbm_batch_step(wlbm_batch* b, int64_t nsteps) {
     for (int j = 0; j < cnt; ++j) {
       const int64_t k = done + j;
       const bool flux = k >= flux_from;
-      if (fuse && j + k_max <= cnt && k + k_max <= flux_from) {
-        // steps k .. k + k_max - 1 in one launch
+      if (fuse && j + k_max <= cnt) {
+        // steps k .. k + k_max - 1 in one launch; those in the flux window
+        // add their heat flux to the window's sums in the launch
         fb.row = slot * b->chunk + j;
         fb.parity = int(flips & 1);
+        fb.flux_levels = 0;
+        for (int m = 0; m < k_max; ++m)
+          if (k + m >= flux_from) fb.flux_levels |= 1u << m;
+        fb.flux_first =
+            (flux_from >= k && flux_from < k + k_max) ? int(flux_from - k) + 1 : 0;
         e = refresh(flips);
-        if (e == hipSuccess) e = launch_fused_batch(fb, b->qmax, k_max, l0->per_cell, b->stream);
+        if (e == hipSuccess)
+          e = launch_fused_batch(fb, b->qmax, k_max, l0->per_cell, fb.flux_levels != 0,
+                                 b->stream);
         if (e != hipSuccess) {
           for (wlbm_lattice* l : b->lats) l->broken = true;
           return fail(WLBM_EHIP, "batch multi-step launch failed: %s", hipGetErrorString(e));

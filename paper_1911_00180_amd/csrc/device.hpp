@@ -126,6 +126,17 @@ struct FusedArgs {
   // step m at ins + 4 m), in device memory uploaded with the schedule.
   const uint32_t* codes;
   const float* ins;
+  // Heat flux of flux-window steps (the flux kernels only): bit m - 1 of
+  // flux_levels set for step m of the launch (1 .. K) in the window; the
+  // window's float64 sums qsx, qsy ([ny][nx]) are set by step flux_first
+  // (0: by none of the launch's steps) and added to by the others; sxtab,
+  // sytab: s_x,i and s_y,i.
+  double* qsx;
+  double* qsy;
+  const float* sxtab;
+  const float* sytab;
+  uint32_t flux_levels;
+  int flux_first;
 };
 // K = 2 .. 4 steps of n lattices with the same q and per-cell field use in
 // one launch.  lats holds each lattice's arguments for buffer parity 0 and 1
@@ -144,8 +155,13 @@ struct FusedBatchArgs {
   const float* const* ins;
   int row;
   int n, nblocks, parity;
+  // flux-window steps of the launch, as FusedArgs (the same for every
+  // lattice; each lattice's sums and tables are in lats)
+  uint32_t flux_levels;
+  int flux_first;
 };
-hipError_t launch_fused_batch(const FusedBatchArgs& b, int q, int k, bool per_cell,
+// flux: the flux kernels (b.flux_levels != 0).
+hipError_t launch_fused_batch(const FusedBatchArgs& b, int q, int k, bool per_cell, bool flux,
                               hipStream_t s);
 hipError_t launch_fused_batch_walls2(const FusedBatchArgs& b, int q, bool per_cell,
                                      hipStream_t s);
@@ -153,13 +169,23 @@ hipError_t launch_fused_batch_walls3(const FusedBatchArgs& b, int q, bool per_ce
                                      hipStream_t s);
 hipError_t launch_fused_batch_walls4(const FusedBatchArgs& b, int q, bool per_cell,
                                      hipStream_t s);
+hipError_t launch_fused_batch_flux2(const FusedBatchArgs& b, int q, bool per_cell,
+                                    hipStream_t s);
+hipError_t launch_fused_batch_flux3(const FusedBatchArgs& b, int q, bool per_cell,
+                                    hipStream_t s);
+hipError_t launch_fused_batch_flux4(const FusedBatchArgs& b, int q, bool per_cell,
+                                    hipStream_t s);
 
 // K = 2 .. 4 steps per launch; lattices with walls run the kernels of
-// fused_walls{2,3,4}.hip.
-hipError_t launch_fused(const FusedArgs& a, int k, bool per_cell, hipStream_t s);
+// fused_walls{2,3,4}.hip, launches with flux-window steps (flux: a.flux_levels
+// != 0) those of fused_flux{2,3,4}.hip.
+hipError_t launch_fused(const FusedArgs& a, int k, bool per_cell, bool flux, hipStream_t s);
 hipError_t launch_fused_walls2(const FusedArgs& a, bool per_cell, hipStream_t s);
 hipError_t launch_fused_walls3(const FusedArgs& a, bool per_cell, hipStream_t s);
 hipError_t launch_fused_walls4(const FusedArgs& a, bool per_cell, hipStream_t s);
+hipError_t launch_fused_flux2(const FusedArgs& a, bool per_cell, hipStream_t s);
+hipError_t launch_fused_flux3(const FusedArgs& a, bool per_cell, hipStream_t s);
+hipError_t launch_fused_flux4(const FusedArgs& a, bool per_cell, hipStream_t s);
 int fused_blocks_per_cu_walls2(int q, bool per_cell);
 int fused_blocks_per_cu_walls3(int q, bool per_cell);
 int fused_blocks_per_cu_walls4(int q, bool per_cell);
@@ -172,8 +198,7 @@ int fused_strips_x(int nx, int k);
 // written to cand); returns their number.
 int fused_row_candidates(int ny, int k, int* cand, int max_cand);
 // Whether the multi-step kernels take this lattice: q a multiple of 8 up to
-// 64 or of 16 up to 128, or q = 192 or 256 (two steps per launch), nx >= 8,
-// ny >= 2.
+// 128, or q = 192 or 256 (two steps per launch), nx >= 8, ny >= 2.
 bool fused_supported(int q, int nx, int ny);
 // Resident blocks per CU of the k-step kernel for q directions and these
 // edges (occupancy query of the runtime; 0 if it fails).

@@ -94,12 +94,20 @@ int fused_blocks_per_cu(int q, int k, bool per_cell, bool walls) {
   }
 }
 
-hipError_t launch_fused(const FusedArgs& a, int k, bool per_cell, hipStream_t s) {
+hipError_t launch_fused(const FusedArgs& a, int k, bool per_cell, bool flux, hipStream_t s) {
+  if (flux) {
+    switch (k) {
+      case 2: return launch_fused_flux2(a, per_cell, s);
+      case 3: return launch_fused_flux3(a, per_cell, s);
+      case 4: return launch_fused_flux4(a, per_cell, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (a.x_edge == kPeriodic && a.y_edge == kPeriodic) {
     switch (k) {
-      case 2: return launch_fused_qk<false, 2>(a, per_cell, s);
-      case 3: return launch_fused_qk<false, 3>(a, per_cell, s);
-      case 4: return launch_fused_qk<false, 4>(a, per_cell, s);
+      case 2: return launch_fused_qk<false, 2, false>(a, per_cell, s);
+      case 3: return launch_fused_qk<false, 3, false>(a, per_cell, s);
+      case 4: return launch_fused_qk<false, 4, false>(a, per_cell, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -111,8 +119,16 @@ hipError_t launch_fused(const FusedArgs& a, int k, bool per_cell, hipStream_t s)
   }
 }
 
-hipError_t launch_fused_batch(const FusedBatchArgs& b, int q, int k, bool per_cell,
+hipError_t launch_fused_batch(const FusedBatchArgs& b, int q, int k, bool per_cell, bool flux,
                               hipStream_t s) {
+  if (flux) {
+    switch (k) {
+      case 2: return launch_fused_batch_flux2(b, q, per_cell, s);
+      case 3: return launch_fused_batch_flux3(b, q, per_cell, s);
+      case 4: return launch_fused_batch_flux4(b, q, per_cell, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (k) {
     case 2: return launch_fused_batch_walls2(b, q, per_cell, s);
     case 3: return launch_fused_batch_walls3(b, q, per_cell, s);

@@ -6,7 +6,7 @@ namespace wlbm {
 
 hipError_t launch_fused_batch_walls4(const FusedBatchArgs& b, int q, bool per_cell,
                                      hipStream_t s) {
-  return launch_fused_batch_qk<4>(b, q, per_cell, s);
+  return launch_fused_batch_qk<4, false>(b, q, per_cell, s);
 }
 
 }  // namespace wlbm

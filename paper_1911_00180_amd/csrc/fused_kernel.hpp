@@ -380,13 +380,96 @@ __device__ __forceinline__ bool row_bb(const EdgeCtx& ec, const RowWalls& rw, ui
   return ec.blk_xbb || rw.ybb;
 }
 
+// Heat flux of flux-window steps (FLUX kernels): each wave sums, per batch
+// of 8 directions, q = sum_i out_i s_i as an fma chain in direction order
+// into sQ (x then y, per level and row parity, as the E batch sums).  After
+// the level's barrier the first wave adds the x batches in batch order, as
+// k_step does, and the second wave the y batches (the first wave both if the
+// block has one), for the cells the block outputs (rows y0 .. y0 + rows - 1
+// of its strip), and keeps the step's sums in the block's ring sF until the
+// row's last level; there the wave adds the launch's window steps, in step
+// order, to the row's float64 window sums (fetched one output row ahead, so
+// that the wave does not wait for HBM) and stores them.  Same bits as
+// k_step's read-add-write per step.
+struct FluxCtx {
+  float* sQ;       // batch sums [level][row parity][x, y][batch][lane]
+  float* sF;       // step sums [row mod K][level][x, y][lane]
+  int x;           // this lane's column
+  bool out_lane;   // the lane outputs a column of the lattice
+  double p[2];     // window sums of the next output row: x, y (a wave that
+                   // has one component keeps it in p[0])
+};
+template <int NB>
+__device__ __forceinline__ float* flux_sums(const FluxCtx& fc, int L, int t) {
+  return fc.sQ + (2 * (L - 1) + (t & 1)) * 2 * NB * 64;
+}
+// One component's batch sums of a row in batch order (as the E sums).
+template <int NB>
+__device__ __forceinline__ float flux_batch_sum(const float* q, int lane) {
+  float v = 0.f;
+#pragma unroll
+  for (int k = 0; k < NB; ++k) v += q[k * 64 + lane];
+  return v;
+}
+// Level L < K of row rho, component c (0: x, 1: y): the step's sum into the
+// ring.
+template <int NB, int K>
+__device__ __forceinline__ void flux_level_c(const FusedArgs& a, const FluxCtx& fc, int L, int t,
+                                             int rho, int y0, int lane, int c) {
+  if (!((a.flux_levels >> (L - 1)) & 1u)) return;
+  if (!fc.out_lane || rho < y0 || rho >= y0 + a.rows || rho >= a.ny) return;
+  fc.sF[((rho % K) * K + (L - 1)) * 128 + c * 64 + lane] =
+      flux_batch_sum<NB>(flux_sums<NB>(fc, L, t) + c * NB * 64, lane);
+}
+// The output level K of row ro, component c: the launch's window steps added
+// to the row's sum in step order; then the next row's sum is fetched.
+template <int NW, int NB, int K>
+__device__ __forceinline__ void flux_out_c(const FusedArgs& a, FluxCtx& fc, int t, int ro, int y0,
+                                           int lane, int c) {
+  const uint32_t lv = a.flux_levels;
+  if (lv == 0) return;
+  double* sums = c == 0 ? a.qsx : a.qsy;
+  if (fc.out_lane && ro < a.ny) {
+    double acc = fc.p[NW == 1 ? c : 0];
+    const float* f = fc.sF + (ro % K) * K * 128 + c * 64 + lane;
+#pragma unroll
+    for (int m = 1; m < K; ++m) {
+      if ((lv >> (m - 1)) & 1u) {
+        const double v = double(f[(m - 1) * 128]);
+        acc = m == a.flux_first ? v : acc + v;
+      }
+    }
+    if ((lv >> (K - 1)) & 1u) {
+      const double v = double(flux_batch_sum<NB>(flux_sums<NB>(fc, K, t) + c * NB * 64, lane));
+      acc = K == a.flux_first ? v : acc + v;
+    }
+    sums[(long long)ro * a.nx + fc.x] = acc;
+  }
+  const int rn = ro + 1;
+  if (a.flux_first == 0 && fc.out_lane && rn < y0 + a.rows && rn < a.ny)
+    fc.p[NW == 1 ? c : 0] = sums[(long long)rn * a.nx + fc.x];
+}
+// The flux work of a level's first waves (after the level's barrier).
+template <int NW, int NB, int K>
+__device__ __forceinline__ void flux_level(const FusedArgs& a, const FluxCtx& fc, int L, int t,
+                                           int rho, int y0, int lane, int part) {
+  if (part == 0) flux_level_c<NB, K>(a, fc, L, t, rho, y0, lane, 0);
+  if (part == (NW == 1 ? 0 : 1)) flux_level_c<NB, K>(a, fc, L, t, rho, y0, lane, 1);
+}
+template <int NW, int NB, int K>
+__device__ __forceinline__ void flux_out(const FusedArgs& a, FluxCtx& fc, int t, int ro, int y0,
+                                         int lane, int part) {
+  if (part == 0) flux_out_c<NW, NB, K>(a, fc, t, ro, y0, lane, 0);
+  if (part == (NW == 1 ? 0 : 1)) flux_out_c<NW, NB, K>(a, fc, t, ro, y0, lane, 1);
+}
+
 // Level 1 at iteration t (row r = y0 - (K-1) + t, ring slot S = t mod 3)
 // from the step-n loads; then the loads of the next row are issued, and E of
 // row r is summed.  Step-n slots: rows r-1, r, r+1 are S, S+1, S+2 (mod 3).
-template <int NW, int SH, int K, bool WF, int S, bool WALLS>
+template <int NW, int SH, int K, bool WF, int S, bool WALLS, bool FLUX>
 __device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float* sP, float* eR,
                                        const EdgeCtx& ec, int t, int y0, int lane, int part,
-                                       uint32_t lcol) {
+                                       uint32_t lcol, const FluxCtx& fc) {
   constexpr int S1 = (S + 1) % 3, S2 = (S + 2) % 3;
   constexpr int NB = NW * SH / kMaxGroupPlanes;   // batches of 8 directions
   const RowCtx c = row_ctx(a);
@@ -434,10 +517,14 @@ __device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float
                              g.Wn[S1], sP + ((t + 1) & 1) * NB * 64, lane, part, tg, wtg);
     }
   }
+  float* q1 = FLUX ? flux_sums<NB>(fc, 1, t) : nullptr;
+  // s_x,i and s_y,i, re-read each row as the other per-direction tables
+  const WLBM_CONST float* sx = FLUX ? row_ptr(a.sxtab) : nullptr;
+  const WLBM_CONST float* sy = FLUX ? row_ptr(a.sytab) : nullptr;
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
-    float bsum = 0.f;
+    float bsum = 0.f, bqx = 0.f, bqy = 0.f;
 #pragma unroll
     for (int d = 0; d < kMaxGroupPlanes; ++d) {
       const int i = i0 + d;
@@ -459,8 +546,16 @@ __device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float
       if constexpr (WALLS) out = wall_update(out, wi, rw, codes, i, tg, wtg, bb, bbm, bbt);
       g.X[0][S][b0 + d] = out;
       bsum += out;
+      if constexpr (FLUX) {
+        bqx = fmaf(out, sx[i], bqx);
+        bqy = fmaf(out, sy[i], bqy);
+      }
     }
     p1[(i0 / kMaxGroupPlanes) * 64 + lane] = bsum;
+    if constexpr (FLUX) {
+      q1[(i0 / kMaxGroupPlanes) * 64 + lane] = bqx;
+      q1[(NB + i0 / kMaxGroupPlanes) * 64 + lane] = bqy;
+    }
   }
   // W of this row for the next level, before slot S is refilled
   if constexpr (WF) g.W[0][S] = g.Wn[S1];
@@ -473,6 +568,9 @@ __device__ __forceinline__ void level1(const FusedArgs& a, Ring<SH, K>& g, float
 #pragma unroll
   for (int k = 0; k < NB; ++k) E += p1[k * 64 + lane];
   g.E[0][S] = WF ? E * Wrow : E;
+  if constexpr (FLUX) {
+    flux_level<NW, NB, K>(a, fc, 1, t, y0 - (K - 1) + t, y0, lane, part);
+  }
   if constexpr (WALLS) {
     if (rw.outside) {
 #pragma unroll
@@ -530,10 +628,10 @@ __device__ __forceinline__ void walls_up(const FusedArgs& a, const Ring<SH, K>& 
 
 // An intermediate level L (2 .. K-1) at iteration t: row r - (L-1) into ring
 // slot S of level L, and its E.
-template <int NW, int SH, int K, bool WF, int L, int S, bool WALLS>
+template <int NW, int SH, int K, bool WF, int L, int S, bool WALLS, bool FLUX>
 __device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, float* sP,
                                           float* eR, const EdgeCtx& ec, int t, int y0, int lane,
-                                          int part) {
+                                          int part, const FluxCtx& fc) {
   constexpr int S2 = (S + 2) % 3;
   constexpr int NB = NW * SH / kMaxGroupPlanes;
   const RowCtx c = row_ctx(a);
@@ -549,10 +647,13 @@ __device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, fl
     walls_up<NW, SH, K, WF, L, S>(a, g, eR, sP + (2 * (L - 1) + ((t + 1) & 1)) * NB * 64, ec,
                                   y0 - (K - 1) + t - (L - 1), lane, part, rw, tg, wtg, bb, bbm,
                                   bbt, codes);
+  float* ql = FLUX ? flux_sums<NB>(fc, L, t) : nullptr;
+  const WLBM_CONST float* sx = FLUX ? row_ptr(a.sxtab) : nullptr;
+  const WLBM_CONST float* sy = FLUX ? row_ptr(a.sytab) : nullptr;
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
-    float bsum = 0.f;
+    float bsum = 0.f, bqx = 0.f, bqy = 0.f;
 #pragma unroll
     for (int d = 0; d < kMaxGroupPlanes; ++d) {
       float out = relax_up<SH, K, WF, L, S>(a, g, sel_at(c.tab, sels[i0 + d]), c.wtab[i0 + d],
@@ -561,8 +662,16 @@ __device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, fl
         out = wall_update(out, c.wtab[i0 + d], rw, codes, i0 + d, tg, wtg, bb, bbm, bbt);
       g.X[L - 1][S][b0 + d] = out;
       bsum += out;
+      if constexpr (FLUX) {
+        bqx = fmaf(out, sx[i0 + d], bqx);
+        bqy = fmaf(out, sy[i0 + d], bqy);
+      }
     }
     pl[(i0 / kMaxGroupPlanes) * 64 + lane] = bsum;
+    if constexpr (FLUX) {
+      ql[(i0 / kMaxGroupPlanes) * 64 + lane] = bqx;
+      ql[(NB + i0 / kMaxGroupPlanes) * 64 + lane] = bqy;
+    }
   }
   // W of this row (level L-1 holds it in slot S2)
   if constexpr (WF) g.W[L - 1][S] = g.W[L - 2][S2];
@@ -571,6 +680,9 @@ __device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, fl
 #pragma unroll
   for (int k = 0; k < NB; ++k) E += pl[k * 64 + lane];
   g.E[L - 1][S] = WF ? E * g.W[L - 1][S] : E;
+  if constexpr (FLUX) {
+    flux_level<NW, NB, K>(a, fc, L, t, y0 - (K - 1) + t - (L - 1), y0, lane, part);
+  }
   if constexpr (WALLS) {
     if (rw.outside) {
 #pragma unroll
@@ -585,10 +697,11 @@ __device__ __forceinline__ void level_mid(const FusedArgs& a, Ring<SH, K>& g, fl
 
 // The output level K at iteration t: row ro = r - (K-1), stored with the
 // ghost copies of periodic edges.
-template <int NW, int SH, int K, bool WF, int S, bool WALLS>
+template <int NW, int SH, int K, bool WF, int S, bool WALLS, bool FLUX>
 __device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, float* sP,
                                           const float* eR, const EdgeCtx& ec, int t, int x0,
-                                          int y0, int lane, int part, bool out_lane) {
+                                          int y0, int lane, int part, bool out_lane,
+                                          FluxCtx& fc) {
   constexpr int NB = NW * SH / kMaxGroupPlanes;
   const RowCtx c = row_ctx(a);
   const WLBM_CONST uint32_t* sels = row_ptr(a.sels[K - 1]);
@@ -626,10 +739,13 @@ __device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, fl
   if constexpr (WALLS)
     walls_up<NW, SH, K, WF, K, S>(a, g, eR, sP + (2 * (K - 1) + ((t + 1) & 1)) * NB * 64, ec, ro,
                                   lane, part, rw, tg, wtg, bb, bbm, bbt, codes);
+  float* qo = FLUX ? flux_sums<NB>(fc, K, t) : nullptr;
+  const WLBM_CONST float* sx = FLUX ? row_ptr(a.sxtab) : nullptr;
+  const WLBM_CONST float* sy = FLUX ? row_ptr(a.sytab) : nullptr;
 #pragma unroll
   for (int b0 = 0; b0 < SH; b0 += kMaxGroupPlanes) {
     const int i0 = i_begin + b0;
-    float bsum = 0.f;
+    float bsum = 0.f, bqx = 0.f, bqy = 0.f;
     const rsrc_t ro_rs = make_rsrc(a.e_out + (long long)i0 * plane,
                                    uint32_t(kMaxGroupPlanes * plane * 4));
     float o[kMaxGroupPlanes];
@@ -641,8 +757,16 @@ __device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, fl
         out = wall_update(out, c.wtab[i0 + d], rw, codes, i0 + d, tg, wtg, bb, bbm, bbt);
       bsum += out;
       o[d] = out;
+      if constexpr (FLUX) {
+        bqx = fmaf(out, sx[i0 + d], bqx);
+        bqy = fmaf(out, sy[i0 + d], bqy);
+      }
     }
     po[(i0 / kMaxGroupPlanes) * 64 + lane] = bsum;
+    if constexpr (FLUX) {
+      qo[(i0 / kMaxGroupPlanes) * 64 + lane] = bqx;
+      qo[(NB + i0 / kMaxGroupPlanes) * 64 + lane] = bqy;
+    }
     // the batch's stores, under one lane mask each
     auto put = [&](uint32_t off) {
 #pragma unroll
@@ -669,30 +793,35 @@ __device__ __forceinline__ void level_out(const FusedArgs& a, Ring<SH, K>& g, fl
       if (gx && gy) buf_store(E, Ers, obxy);
     }
   }
+  if constexpr (FLUX) {
+    flux_out<NW, NB, K>(a, fc, t, ro, y0, lane, part);
+  }
 }
 
 // Iteration t (ring slot S = t mod 3): level 1, then each higher level once
 // the three rows it reads exist.
-template <int NW, int SH, int K, bool WF, int S, bool WALLS>
+template <int NW, int SH, int K, bool WF, int S, bool WALLS, bool FLUX>
 __device__ __forceinline__ void iteration(const FusedArgs& a, Ring<SH, K>& g, float* sP,
                                           float* eR, const EdgeCtx& ec, int t, int x0, int y0,
-                                          int lane, int part, uint32_t lcol, bool out_lane) {
-  level1<NW, SH, K, WF, S, WALLS>(a, g, sP, eR, ec, t, y0, lane, part, lcol);
+                                          int lane, int part, uint32_t lcol, bool out_lane,
+                                          FluxCtx& fc) {
+  level1<NW, SH, K, WF, S, WALLS, FLUX>(a, g, sP, eR, ec, t, y0, lane, part, lcol, fc);
   if constexpr (K >= 3) {
     if (t < 2) return;
-    level_mid<NW, SH, K, WF, 2, S, WALLS>(a, g, sP, eR, ec, t, y0, lane, part);
+    level_mid<NW, SH, K, WF, 2, S, WALLS, FLUX>(a, g, sP, eR, ec, t, y0, lane, part, fc);
   }
   if constexpr (K >= 4) {
     if (t < 4) return;
-    level_mid<NW, SH, K, WF, 3, S, WALLS>(a, g, sP, eR, ec, t, y0, lane, part);
+    level_mid<NW, SH, K, WF, 3, S, WALLS, FLUX>(a, g, sP, eR, ec, t, y0, lane, part, fc);
   }
   if (t < 2 * (K - 1)) return;
-  level_out<NW, SH, K, WF, S, WALLS>(a, g, sP, eR, ec, t, x0, y0, lane, part, out_lane);
+  level_out<NW, SH, K, WF, S, WALLS, FLUX>(a, g, sP, eR, ec, t, x0, y0, lane, part, out_lane,
+                                           fc);
 }
 
 // One block's strip (x0, y0): the rows and lanes of the iteration loop.
-template <int NW, int SH, bool WF, int K, bool WALLS>
-__device__ __forceinline__ void run_block(const FusedArgs& a, float* sP, float* sEr,
+template <int NW, int SH, bool WF, int K, bool WALLS, bool FLUX>
+__device__ __forceinline__ void run_block(const FusedArgs& a, float* sP, float* sEr, float* sQ,
                                           int x0, int y0) {
   const int lane = threadIdx.x & 63;
   const int part = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -704,6 +833,21 @@ __device__ __forceinline__ void run_block(const FusedArgs& a, float* sP, float* 
   const int xl = x < a.nx + kGhost - 1 ? x : a.nx + kGhost - 1;
   const uint32_t lcol = uint32_t((kXOff + xl) * 4);
   const bool out_lane = lane >= L0 && lane < L0 + kStrip<K> && x < a.nx;
+  FluxCtx fc{};
+  if constexpr (FLUX) {
+    constexpr int NB = NW * SH / kMaxGroupPlanes;
+    fc.sQ = sQ;
+    fc.sF = sQ + 2 * K * 2 * NB * 64;
+    fc.x = x;
+    fc.out_lane = out_lane;
+    // the window sums of the first output row, unless a step of this launch
+    // starts the window
+    if (a.flux_levels != 0 && a.flux_first == 0 && out_lane && y0 < a.ny) {
+      const long long o = (long long)y0 * a.nx + x;
+      if (part == 0) fc.p[0] = a.qsx[o];
+      if (part == (NW == 1 ? 0 : 1)) fc.p[NW == 1 ? 1 : 0] = a.qsy[o];
+    }
+  }
   EdgeCtx ec{};
   if constexpr (WALLS) {
     ec.x = x;
@@ -747,21 +891,17 @@ __device__ __forceinline__ void run_block(const FusedArgs& a, float* sP, float* 
   // a.rows + 2 (K - 1) is a multiple of 3 (the loop is unrolled by three)
   const int T = a.rows + 2 * (K - 1);
   for (int t = 0; t < T; t += 3) {
-    iteration<NW, SH, K, WF, 0, WALLS>(a, g, sP, eR, ec, t, x0, y0, lane, part, lcol, out_lane);
-    iteration<NW, SH, K, WF, 1, WALLS>(a, g, sP, eR, ec, t + 1, x0, y0, lane, part, lcol,
-                                       out_lane);
-    iteration<NW, SH, K, WF, 2, WALLS>(a, g, sP, eR, ec, t + 2, x0, y0, lane, part, lcol,
-                                       out_lane);
+    iteration<NW, SH, K, WF, 0, WALLS, FLUX>(a, g, sP, eR, ec, t, x0, y0, lane, part, lcol,
+                                             out_lane, fc);
+    iteration<NW, SH, K, WF, 1, WALLS, FLUX>(a, g, sP, eR, ec, t + 1, x0, y0, lane, part, lcol,
+                                             out_lane, fc);
+    iteration<NW, SH, K, WF, 2, WALLS, FLUX>(a, g, sP, eR, ec, t + 2, x0, y0, lane, part, lcol,
+                                             out_lane, fc);
   }
 }
 
-template <int NW, int SH, bool WF, int K, bool WALLS>
-__global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
-  constexpr int NB = NW * SH / kMaxGroupPlanes;
-  // E batch sums: [level 1 .. K][row parity][batch of 8 directions][lane]
-  __shared__ float sP[2 * K * NB * 64];
-  // the E rings of the block: step n, then levels 1 .. K-1
-  __shared__ float sEr[K * 3 * kERow];
+template <int NW, int SH, bool WF, int K, bool WALLS, bool FLUX>
+__device__ __forceinline__ void stepk_block(const FusedArgs& a, float* sP, float* sEr, float* sQ) {
   const int b = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (b % a.strips_x) * kStrip<K>;
   const int y0 = (b / a.strips_x) * a.rows;
@@ -776,11 +916,38 @@ __global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
     const bool cols_free =
         a.x_edge == kPeriodic || (x0 - K >= 1 && x0 - K + 63 <= a.nx - 2);
     if (rows_free && cols_free) {
-      run_block<NW, SH, WF, K, false>(a, sP, sEr, x0, y0);
+      run_block<NW, SH, WF, K, false, FLUX>(a, sP, sEr, sQ, x0, y0);
       return;
     }
   }
-  run_block<NW, SH, WF, K, WALLS>(a, sP, sEr, x0, y0);
+  run_block<NW, SH, WF, K, WALLS, FLUX>(a, sP, sEr, sQ, x0, y0);
+}
+
+// E batch sums: [level 1 .. K][row parity][batch of 8 directions][lane]
+template <int NW, int SH, int K>
+constexpr int kSumFloats = 2 * K * (NW * SH / kMaxGroupPlanes) * 64;
+// heat-flux batch sums: as the E sums, x and y; then the ring of step sums
+template <int NW, int SH, int K>
+constexpr int kFluxFloats = 2 * kSumFloats<NW, SH, K> + K * K * 2 * 64;
+
+template <int NW, int SH, bool WF, int K, bool WALLS>
+__global__ __launch_bounds__(64 * NW) void k_stepk(const FusedArgs a) {
+  __shared__ float sP[kSumFloats<NW, SH, K>];
+  // the E rings of the block: step n, then levels 1 .. K-1
+  __shared__ float sEr[K * 3 * kERow];
+  stepk_block<NW, SH, WF, K, WALLS, false>(a, sP, sEr, nullptr);
+}
+
+// With the heat flux of flux-window steps: held to 128 registers a lane
+// (four waves a SIMD; the flux sums would otherwise take the count past it
+// and halve the resident blocks).
+template <int NW, int SH, bool WF, int K, bool WALLS>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void k_stepk_flux(
+    const FusedArgs a) {
+  __shared__ float sP[kSumFloats<NW, SH, K>];
+  __shared__ float sEr[K * 3 * kERow];
+  __shared__ float sQ[kFluxFloats<NW, SH, K>];
+  stepk_block<NW, SH, WF, K, WALLS, true>(a, sP, sEr, sQ);
 }
 
 // A lattice's arguments from the batch's device table, field by field
@@ -816,6 +983,12 @@ __device__ __forceinline__ FusedArgs load_args(const WLBM_CONST FusedArgs* p) {
   a.ins = p->ins;
   return a;
 }
+__device__ __forceinline__ void load_flux_args(FusedArgs& a, const WLBM_CONST FusedArgs* p) {
+  a.qsx = p->qsx;
+  a.qsy = p->qsy;
+  a.sxtab = p->sxtab;
+  a.sytab = p->sytab;
+}
 
 // K steps of n lattices in one launch (the in-plane film sweeps of Sec. 3.5
 // run many lattices of different thickness and Knudsen number): each block
@@ -823,17 +996,20 @@ __device__ __forceinline__ FusedArgs load_args(const WLBM_CONST FusedArgs* p) {
 // lattice's arguments for the current buffer parity from the device table
 // and its per-step tables from its rings (scalar loads), and runs the block
 // as k_stepk does.
-template <int NW, int SH, bool WF, int K>
-__global__ __launch_bounds__(64 * NW) void k_stepk_batch(const FusedBatchArgs b) {
-  constexpr int NB = NW * SH / kMaxGroupPlanes;
-  __shared__ float sP[2 * K * NB * 64];
-  __shared__ float sEr[K * 3 * kERow];
+template <int NW, int SH, bool WF, int K, bool FLUX>
+__device__ __forceinline__ void stepk_batch_block(const FusedBatchArgs& b, float* sP, float* sEr,
+                                                  float* sQ) {
   const int gb = xcd_tile(blockIdx.x, gridDim.x);
   const WLBM_CONST int* first = scalar_ptr(b.first);
   int j = 0;
   while (j + 1 < b.n && gb >= first[j + 1]) ++j;
   j = __builtin_amdgcn_readfirstlane(j);
   FusedArgs a = load_args(scalar_ptr(b.lats) + 2 * j + b.parity);
+  if constexpr (FLUX) {
+    load_flux_args(a, scalar_ptr(b.lats) + 2 * j + b.parity);
+    a.flux_levels = b.flux_levels;
+    a.flux_first = b.flux_first;
+  }
   const size_t q = size_t(a.q);
   const uint32_t* sel0 = scalar_ptr(b.sels)[j] + size_t(b.row) * q;
 #pragma unroll
@@ -848,73 +1024,103 @@ __global__ __launch_bounds__(64 * NW) void k_stepk_batch(const FusedBatchArgs b)
                          (y0 - (K - 1) >= 1 && y0 + a.rows - 1 + (K - 1) <= a.ny - 2);
   const bool cols_free = a.x_edge == kPeriodic || (x0 - K >= 1 && x0 - K + 63 <= a.nx - 2);
   if (rows_free && cols_free)
-    run_block<NW, SH, WF, K, false>(a, sP, sEr, x0, y0);
+    run_block<NW, SH, WF, K, false, FLUX>(a, sP, sEr, sQ, x0, y0);
   else
-    run_block<NW, SH, WF, K, true>(a, sP, sEr, x0, y0);
+    run_block<NW, SH, WF, K, true, FLUX>(a, sP, sEr, sQ, x0, y0);
 }
 
-template <int NW, int SH, int K>
+template <int NW, int SH, bool WF, int K>
+__global__ __launch_bounds__(64 * NW) void k_stepk_batch(const FusedBatchArgs b) {
+  __shared__ float sP[kSumFloats<NW, SH, K>];
+  __shared__ float sEr[K * 3 * kERow];
+  stepk_batch_block<NW, SH, WF, K, false>(b, sP, sEr, nullptr);
+}
+
+template <int NW, int SH, bool WF, int K>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(4))) void
+k_stepk_batch_flux(const FusedBatchArgs b) {
+  __shared__ float sP[kSumFloats<NW, SH, K>];
+  __shared__ float sEr[K * 3 * kERow];
+  __shared__ float sQ[kFluxFloats<NW, SH, K>];
+  stepk_batch_block<NW, SH, WF, K, true>(b, sP, sEr, sQ);
+}
+
+template <int NW, int SH, int K, bool FLUX>
 hipError_t launchk_batch(const FusedBatchArgs& b, bool wf, hipStream_t s) {
   const dim3 grid(b.nblocks), block(64 * NW);
-  if (wf)
-    hipLaunchKernelGGL((k_stepk_batch<NW, SH, true, K>), grid, block, 0, s, b);
-  else
-    hipLaunchKernelGGL((k_stepk_batch<NW, SH, false, K>), grid, block, 0, s, b);
+  if constexpr (FLUX) {
+    if (wf)
+      hipLaunchKernelGGL((k_stepk_batch_flux<NW, SH, true, K>), grid, block, 0, s, b);
+    else
+      hipLaunchKernelGGL((k_stepk_batch_flux<NW, SH, false, K>), grid, block, 0, s, b);
+  } else {
+    if (wf)
+      hipLaunchKernelGGL((k_stepk_batch<NW, SH, true, K>), grid, block, 0, s, b);
+    else
+      hipLaunchKernelGGL((k_stepk_batch<NW, SH, false, K>), grid, block, 0, s, b);
+  }
   return hipGetLastError();
 }
 
-template <int K>
+template <int K, bool FLUX>
 hipError_t launch_fused_batch_qk(const FusedBatchArgs& b, int q, bool per_cell, hipStream_t s) {
   if constexpr (K == 2) {
     switch (q) {
-      case 80: return launchk_batch<5, 16, K>(b, per_cell, s);
-      case 96: return launchk_batch<6, 16, K>(b, per_cell, s);
-      case 112: return launchk_batch<7, 16, K>(b, per_cell, s);
-      case 128: return launchk_batch<8, 16, K>(b, per_cell, s);
+      case 80: return launchk_batch<5, 16, K, FLUX>(b, per_cell, s);
+      case 96: return launchk_batch<6, 16, K, FLUX>(b, per_cell, s);
+      case 112: return launchk_batch<7, 16, K, FLUX>(b, per_cell, s);
+      case 128: return launchk_batch<8, 16, K, FLUX>(b, per_cell, s);
       default: break;
     }
   }
   switch (q) {
-    case 8: return launchk_batch<1, 8, K>(b, per_cell, s);
-    case 16: return launchk_batch<2, 8, K>(b, per_cell, s);
-    case 24: return launchk_batch<3, 8, K>(b, per_cell, s);
-    case 32: return launchk_batch<4, 8, K>(b, per_cell, s);
-    case 40: return launchk_batch<5, 8, K>(b, per_cell, s);
-    case 48: return launchk_batch<6, 8, K>(b, per_cell, s);
-    case 56: return launchk_batch<7, 8, K>(b, per_cell, s);
-    case 64: return launchk_batch<8, 8, K>(b, per_cell, s);
-    case 72: return launchk_batch<9, 8, K>(b, per_cell, s);
+    case 8: return launchk_batch<1, 8, K, FLUX>(b, per_cell, s);
+    case 16: return launchk_batch<2, 8, K, FLUX>(b, per_cell, s);
+    case 24: return launchk_batch<3, 8, K, FLUX>(b, per_cell, s);
+    case 32: return launchk_batch<4, 8, K, FLUX>(b, per_cell, s);
+    case 40: return launchk_batch<5, 8, K, FLUX>(b, per_cell, s);
+    case 48: return launchk_batch<6, 8, K, FLUX>(b, per_cell, s);
+    case 56: return launchk_batch<7, 8, K, FLUX>(b, per_cell, s);
+    case 64: return launchk_batch<8, 8, K, FLUX>(b, per_cell, s);
+    case 72: return launchk_batch<9, 8, K, FLUX>(b, per_cell, s);
     case 80: 
-      if constexpr (K != 2) return launchk_batch<10, 8, K>(b, per_cell, s);
+      if constexpr (K != 2) return launchk_batch<10, 8, K, FLUX>(b, per_cell, s);
       break;
-    case 88: return launchk_batch<11, 8, K>(b, per_cell, s);
+    case 88: return launchk_batch<11, 8, K, FLUX>(b, per_cell, s);
     case 96: 
-      if constexpr (K != 2) return launchk_batch<12, 8, K>(b, per_cell, s);
+      if constexpr (K != 2) return launchk_batch<12, 8, K, FLUX>(b, per_cell, s);
       break;
-    case 104: return launchk_batch<13, 8, K>(b, per_cell, s);
+    case 104: return launchk_batch<13, 8, K, FLUX>(b, per_cell, s);
     case 112: 
-      if constexpr (K != 2) return launchk_batch<14, 8, K>(b, per_cell, s);
+      if constexpr (K != 2) return launchk_batch<14, 8, K, FLUX>(b, per_cell, s);
       break;
-    case 120: return launchk_batch<15, 8, K>(b, per_cell, s);
+    case 120: return launchk_batch<15, 8, K, FLUX>(b, per_cell, s);
     case 128: 
-      if constexpr (K != 2) return launchk_batch<16, 8, K>(b, per_cell, s);
+      if constexpr (K != 2) return launchk_batch<16, 8, K, FLUX>(b, per_cell, s);
       break;
     default: break;
   }
   if constexpr (K == 2) {
-    if (q == 192) return launchk_batch<12, 16, K>(b, per_cell, s);
-    if (q == 256) return launchk_batch<16, 16, K>(b, per_cell, s);
+    if (q == 192) return launchk_batch<12, 16, K, FLUX>(b, per_cell, s);
+    if (q == 256) return launchk_batch<16, 16, K, FLUX>(b, per_cell, s);
   }
   return hipErrorInvalidValue;
 }
 
-template <int NW, int SH, bool WALLS, int K>
+template <int NW, int SH, bool WALLS, int K, bool FLUX>
 hipError_t launchk(const FusedArgs& a, bool wf, hipStream_t s) {
   const dim3 grid(a.strips_x * a.strips_y), block(64 * NW);
-  if (wf)
-    hipLaunchKernelGGL((k_stepk<NW, SH, true, K, WALLS>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((k_stepk<NW, SH, false, K, WALLS>), grid, block, 0, s, a);
+  if constexpr (FLUX) {
+    if (wf)
+      hipLaunchKernelGGL((k_stepk_flux<NW, SH, true, K, WALLS>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_stepk_flux<NW, SH, false, K, WALLS>), grid, block, 0, s, a);
+  } else {
+    if (wf)
+      hipLaunchKernelGGL((k_stepk<NW, SH, true, K, WALLS>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_stepk<NW, SH, false, K, WALLS>), grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 
@@ -938,47 +1144,47 @@ int blocks_per_cu_tmpl(bool wf) {
 // a lane so that four waves share each SIMD).  Measured on MI355X, 1024 x
 // 1024 periodic, q = 128: two steps 997 G updates/s with 16 directions a
 // wave, 963 with 8; four steps 1352 with 8 (1022 with 16).
-template <bool WALLS, int K>
+template <bool WALLS, int K, bool FLUX>
 hipError_t launch_fused_qk(const FusedArgs& a, bool per_cell, hipStream_t s) {
   if constexpr (K == 2) {
     switch (a.q) {
-      case 80: return launchk<5, 16, WALLS, K>(a, per_cell, s);
-      case 96: return launchk<6, 16, WALLS, K>(a, per_cell, s);
-      case 112: return launchk<7, 16, WALLS, K>(a, per_cell, s);
-      case 128: return launchk<8, 16, WALLS, K>(a, per_cell, s);
+      case 80: return launchk<5, 16, WALLS, K, FLUX>(a, per_cell, s);
+      case 96: return launchk<6, 16, WALLS, K, FLUX>(a, per_cell, s);
+      case 112: return launchk<7, 16, WALLS, K, FLUX>(a, per_cell, s);
+      case 128: return launchk<8, 16, WALLS, K, FLUX>(a, per_cell, s);
       default: break;
     }
   }
   switch (a.q) {
-    case 8: return launchk<1, 8, WALLS, K>(a, per_cell, s);
-    case 16: return launchk<2, 8, WALLS, K>(a, per_cell, s);
-    case 24: return launchk<3, 8, WALLS, K>(a, per_cell, s);
-    case 32: return launchk<4, 8, WALLS, K>(a, per_cell, s);
-    case 40: return launchk<5, 8, WALLS, K>(a, per_cell, s);
-    case 48: return launchk<6, 8, WALLS, K>(a, per_cell, s);
-    case 56: return launchk<7, 8, WALLS, K>(a, per_cell, s);
-    case 64: return launchk<8, 8, WALLS, K>(a, per_cell, s);
-    case 72: return launchk<9, 8, WALLS, K>(a, per_cell, s);
+    case 8: return launchk<1, 8, WALLS, K, FLUX>(a, per_cell, s);
+    case 16: return launchk<2, 8, WALLS, K, FLUX>(a, per_cell, s);
+    case 24: return launchk<3, 8, WALLS, K, FLUX>(a, per_cell, s);
+    case 32: return launchk<4, 8, WALLS, K, FLUX>(a, per_cell, s);
+    case 40: return launchk<5, 8, WALLS, K, FLUX>(a, per_cell, s);
+    case 48: return launchk<6, 8, WALLS, K, FLUX>(a, per_cell, s);
+    case 56: return launchk<7, 8, WALLS, K, FLUX>(a, per_cell, s);
+    case 64: return launchk<8, 8, WALLS, K, FLUX>(a, per_cell, s);
+    case 72: return launchk<9, 8, WALLS, K, FLUX>(a, per_cell, s);
     case 80: 
-      if constexpr (K != 2) return launchk<10, 8, WALLS, K>(a, per_cell, s);
+      if constexpr (K != 2) return launchk<10, 8, WALLS, K, FLUX>(a, per_cell, s);
       break;
-    case 88: return launchk<11, 8, WALLS, K>(a, per_cell, s);
+    case 88: return launchk<11, 8, WALLS, K, FLUX>(a, per_cell, s);
     case 96: 
-      if constexpr (K != 2) return launchk<12, 8, WALLS, K>(a, per_cell, s);
+      if constexpr (K != 2) return launchk<12, 8, WALLS, K, FLUX>(a, per_cell, s);
       break;
-    case 104: return launchk<13, 8, WALLS, K>(a, per_cell, s);
+    case 104: return launchk<13, 8, WALLS, K, FLUX>(a, per_cell, s);
     case 112: 
-      if constexpr (K != 2) return launchk<14, 8, WALLS, K>(a, per_cell, s);
+      if constexpr (K != 2) return launchk<14, 8, WALLS, K, FLUX>(a, per_cell, s);
       break;
-    case 120: return launchk<15, 8, WALLS, K>(a, per_cell, s);
+    case 120: return launchk<15, 8, WALLS, K, FLUX>(a, per_cell, s);
     case 128: 
-      if constexpr (K != 2) return launchk<16, 8, WALLS, K>(a, per_cell, s);
+      if constexpr (K != 2) return launchk<16, 8, WALLS, K, FLUX>(a, per_cell, s);
       break;
     default: break;
   }
   if constexpr (K == 2) {
-    if (a.q == 192) return launchk<12, 16, WALLS, K>(a, per_cell, s);
-    if (a.q == 256) return launchk<16, 16, WALLS, K>(a, per_cell, s);
+    if (a.q == 192) return launchk<12, 16, WALLS, K, FLUX>(a, per_cell, s);
+    if (a.q == 256) return launchk<16, 16, WALLS, K, FLUX>(a, per_cell, s);
   }
   return hipErrorInvalidValue;
 }

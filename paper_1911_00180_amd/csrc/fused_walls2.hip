@@ -6,7 +6,7 @@
 namespace wlbm {
 
 hipError_t launch_fused_walls2(const FusedArgs& a, bool per_cell, hipStream_t s) {
-  return launch_fused_qk<true, 2>(a, per_cell, s);
+  return launch_fused_qk<true, 2, false>(a, per_cell, s);
 }
 
 int fused_blocks_per_cu_walls2(int q, bool per_cell) {

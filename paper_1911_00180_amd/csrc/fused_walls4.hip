@@ -6,7 +6,7 @@
 namespace wlbm {
 
 hipError_t launch_fused_walls4(const FusedArgs& a, bool per_cell, hipStream_t s) {
-  return launch_fused_qk<true, 4>(a, per_cell, s);
+  return launch_fused_qk<true, 4, false>(a, per_cell, s);
 }
 
 int fused_blocks_per_cu_walls4(int q, bool per_cell) {

@@ -270,6 +270,7 @@ def test_batched_multi_step_launches_keep_the_bits_of_single_steps(q, per_cell, 
             assert torch.equal(x.populations(), y.populations()), n
             for u, v in zip(x.heat_flux(averaged=True), y.heat_flux(averaged=True)):
                 assert torch.equal(u, v)
+            assert x.flux_mean(averaged=True) == y.flux_mean(averaged=True), n
     batch.close()
     for lat in a + b:
         lat.close()

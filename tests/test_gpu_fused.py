@@ -6,9 +6,10 @@ The multi-step kernels use the same arithmetic and the same summation order
 as the single-step kernel, so the populations must agree bit for bit,
 whatever direction split the single steps use and whatever block height the
 library picks, on ragged and tiny lattices, for step counts that leave single
-steps at the end, across schedule chunks and around flux windows (whose
-steps run alone).  Oracle parity of the multi-step path is covered by every
-periodic parity test, which runs it by default.
+steps at the end, across schedule chunks and inside flux windows (whose
+float64 heat-flux sums the multi-step launches accumulate step by step).
+Oracle parity of the multi-step path is covered by every periodic parity
+test, which runs it by default.
 """
 import numpy as np
 import pytest
@@ -97,6 +98,39 @@ def test_fused_with_mfp_field_and_flux_window():
         assert torch.equal(a.populations(), b.populations()), n
         for u, v in zip(a.heat_flux(averaged=True), b.heat_flux(averaged=True)):
             assert torch.equal(u, v)
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("fusion", [2, 3, 4])
+@pytest.mark.parametrize("nx,ny,q,kw", [
+    (150, 41, 64, dict(mfp=9.0)),
+    (70, 45, 32, dict(mfp=6.0, x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0)),
+    (61, 19, 128, dict(mfp=5.0, x_edge="blackbody", y_edge="diffuse", t_x_lo=1.0, t_x_hi=0.2)),
+    (64, 17, 8, dict(mfp=4.0, x_edge="periodic", y_edge="blackbody", t_y_lo=0.3)),
+    (100, 30, 256, dict(mfp=6.0)),
+])
+def test_flux_windows_inside_multi_step_launches(fusion, nx, ny, q, kw):
+    """Flux-window steps run several per launch: windows that start at each
+    step of a launch, or before the call, and span launches and schedule
+    chunks keep the float64 window sums of single steps bit for bit (the
+    per-cell averages and the fixed-order float64 means)."""
+    a, b = _pair(nx, ny, q, fusion=fusion, sched_chunk=16, **kw)
+    assert a.steps_per_launch >= 2
+    e0 = torch.from_numpy(inputs.random_populations(21, q, ny, nx))
+    for lat in (a, b):
+        lat.set_populations(e0)
+    for window, n in ((1, 9), (2, 9), (3, 10), (4, 12), (5, 11), (7, 7), (13, 50), (40, 45)):
+        for lat in (a, b):
+            lat.set_flux_window(window)
+        a.step(n)
+        b.step(n)
+        assert torch.equal(a.populations(), b.populations()), (window, n)
+        for u, v in zip(a.heat_flux(averaged=True), b.heat_flux(averaged=True)):
+            assert torch.equal(u, v), (window, n)
+        assert a.flux_mean(averaged=True) == b.flux_mean(averaged=True), (window, n)
+        assert (a.flux_mean(1, nx - 1, averaged=True) ==
+                b.flux_mean(1, nx - 1, averaged=True)), (window, n)
     a.close()
     b.close()
 
