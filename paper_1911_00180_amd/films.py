@@ -168,6 +168,9 @@ class FilmSweep:
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--steps", type=int, default=10000, help="fixed steps for the timing")
+    ap.add_argument("--window", type=int, default=10,
+                    help="flux window of the timed steps (the last this many steps of each "
+                         "call accumulate the heat flux; 0: none)")
     ap.add_argument("--steady", action="store_true", help="also run every film to steady state")
     ap.add_argument("--rtol", type=float, default=1e-6,
                     help="steady when kappa changes by less than this between checks")
@@ -184,7 +187,7 @@ def main():
     films = film_set()
     if args.only:
         films = [films[int(j)] for j in args.only.split(",")]
-    sweep = FilmSweep(films)
+    sweep = FilmSweep(films, window=args.window)
     rows = sweep.tune()
     sweep.step_batched(10)
     torch.cuda.synchronize()
@@ -192,7 +195,7 @@ def main():
     sweep.step_batched(args.steps)
     torch.cuda.synchronize()
     tb = time.perf_counter() - t
-    other = FilmSweep(films)
+    other = FilmSweep(films, window=args.window)
     other.step_each(10)
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -200,7 +203,7 @@ def main():
     torch.cuda.synchronize()
     te = time.perf_counter() - t
     res = {"films": [{"kn": kn, "ny": ny, "mfp": mfp} for kn, ny, mfp in films],
-           "steps": args.steps, "batch_block_rows": rows, "batched_s": tb, "one_by_one_s": te,
+           "steps": args.steps, "window": args.window, "batch_block_rows": rows, "batched_s": tb, "one_by_one_s": te,
            "batched_gups": sweep.updates_per_step * args.steps / tb / 1e9,
            "one_by_one_gups": sweep.updates_per_step * args.steps / te / 1e9}
     other.close()
