@@ -49,6 +49,12 @@
 //   grouped as k_step groups them); the node re-emits it as w_i T_g into the
 //   inward directions of the wall row.
 //
+// Flux windows.  k_stepk_flux and k_stepk_batch_flux (the same code with
+// FLUX set) also add the heat flux q = sum_i e_i s_i (Sec. 2.2 Eq. q_corr)
+// of the launch's flux-window steps to the window's float64 per-cell sums,
+// in k_step's order, so a window gives the same sums with any number of
+// steps per launch.
+//
 // Scalar work per direction is kept to loads: the host writes, per step and
 // direction, the byte offset of the direction's entry in the selection table
 // and, for the first step, the offset of its pulled population, so the kernel
